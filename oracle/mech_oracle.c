@@ -1,0 +1,337 @@
+/*
+ * mech_oracle.c -- plain FP64 CPU oracle (TEST INFRASTRUCTURE ONLY).
+ *
+ * Straight scalar loops in the order of the timestep described in
+ * mech_oracle.h.  Built with -O2 -fno-fast-math -ffp-contract=off against the
+ * host libm, single threaded, so the summation order of rhs/d is the instance
+ * order and every rounding is an IEEE double rounding.
+ *
+ * Paper references:
+ *   section 3 (NMODL DSL): SUFFIX density mechanisms vs POINT_PROCESS
+ *     synapses, RANGE / PARAMETER / ASSIGNED / STATE variables, BREAKPOINT
+ *     (current and conductance each step), DERIVATIVE + SOLVE (state update);
+ *   section 5.2 (SymPy): linear independent ODEs are advanced by their analytic
+ *     solution with the coefficients held constant over the step (cnexp);
+ *   section 5.2, last paragraph: by default the conductance di/dv is
+ *     approximated numerically at run time;
+ *   section 8, Table 3: a timestep is State Update + Current Update + Other.
+ *
+ * Mechanism equations (the paper gives none; readings listed in the design doc):
+ *   hh    Hodgkin & Huxley (1952) kinetics, modern sign convention, rest -65 mV
+ *   pas   i = g (v - e)
+ *   ih    one gate, alpha = 0.005 exp(-(v+90)/20), beta = 0.005 exp((v+90)/20)
+ *   cahva m^2 h, Nernst eca, shell calcium with relaxation to cai0
+ *   syn   double-exponential AMPA + NMDA conductance with Mg block
+ */
+#include "mech_oracle.h"
+
+#include <math.h>
+#include <stddef.h>
+
+#define ORC_PI 3.14159265358979323846
+#define ORC_R 8.314462618   /* J/(mol K) */
+#define ORC_F 96485.33212   /* C/mol     */
+
+/* ------------------------------------------------------------------ hh -- */
+/* Hodgkin-Huxley rate functions, 1/ms at q10 = 1.  alpha_m and alpha_n have a
+ * removable singularity (0/0) at v = -40 and v = -55; the value there is the
+ * limit, and expm1 keeps the denominator accurate next to it.               */
+static double hh_am(double v) {
+    double x = v + 40.0;
+    if (x == 0.0) return 1.0;
+    return 0.1 * x / (-expm1(-x / 10.0));
+}
+static double hh_bm(double v) { return 4.0 * exp(-(v + 65.0) / 18.0); }
+static double hh_ah(double v) { return 0.07 * exp(-(v + 65.0) / 20.0); }
+static double hh_bh(double v) { return 1.0 / (1.0 + exp(-(v + 35.0) / 10.0)); }
+static double hh_an(double v) {
+    double x = v + 55.0;
+    if (x == 0.0) return 0.1;
+    return 0.01 * x / (-expm1(-x / 10.0));
+}
+static double hh_bn(double v) { return 0.125 * exp(-(v + 65.0) / 80.0); }
+
+static double hh_q10(double celsius) { return pow(3.0, (celsius - 6.3) / 10.0); }
+
+void orc_hh_rates(double v, double *o) {
+    o[0] = hh_am(v); o[1] = hh_bm(v);
+    o[2] = hh_ah(v); o[3] = hh_bh(v);
+    o[4] = hh_an(v); o[5] = hh_bn(v);
+}
+
+void orc_hh_inf_tau(double v, double celsius, double *o) {
+    double r[6], q = hh_q10(celsius);
+    orc_hh_rates(v, r);
+    for (int j = 0; j < 3; ++j) {
+        double a = r[2 * j], b = r[2 * j + 1];
+        o[j] = a / (a + b);
+        o[3 + j] = 1.0 / (q * (a + b));
+    }
+}
+
+/* ------------------------------------------------------------------ ih -- */
+static double ih_a(double v) { return 0.005 * exp(-(v + 90.0) / 20.0); }
+static double ih_b(double v) { return 0.005 * exp((v + 90.0) / 20.0); }
+
+void orc_ih_inf_tau(double v, double *o) {
+    double a = ih_a(v), b = ih_b(v);
+    o[0] = a / (a + b);
+    o[1] = 1.0 / (a + b);
+}
+
+/* --------------------------------------------------------------- cahva -- */
+static double ca_am(double v) {
+    double x = v + 20.0;
+    if (x == 0.0) return 0.5;
+    return 0.1 * x / (-expm1(-x / 5.0));
+}
+static double ca_bm(double v) { return 0.8 * exp(-(v + 45.0) / 15.0); }
+static double ca_ah(double v) { return 0.0005 * exp(-(v + 60.0) / 25.0); }
+static double ca_bh(double v) { return 0.006 / (1.0 + exp(-(v + 20.0) / 10.0)); }
+
+void orc_cahva_inf_tau(double v, double *o) {
+    double am = ca_am(v), bm = ca_bm(v), ah = ca_ah(v), bh = ca_bh(v);
+    o[0] = am / (am + bm);
+    o[1] = ah / (ah + bh);
+    o[2] = 1.0 / (am + bm);
+    o[3] = 1.0 / (ah + bh);
+}
+
+double orc_nernst_ca(double cai, double cao, double celsius) {
+    double T = celsius + 273.15;
+    return 1e3 * ORC_R * T / (2.0 * ORC_F) * log(cao / cai);
+}
+
+/* d cai/dt = -kappa*ica - (cai - cai0)/tau_ca.  A current density ica
+ * (mA/cm2) carries ica*1e-3/(2F) mol/(s cm2) into a shell of depth `depth` um
+ * (depth*1e-7 L per cm2), of which the fraction gamma stays free:
+ * kappa = 1e4*gamma/(2*F*depth) in mM/ms per mA/cm2.                        */
+double orc_ca_kappa(double gamma, double depth) {
+    return 1e4 * gamma / (2.0 * ORC_F * depth);
+}
+
+/* ----------------------------------------------------------------- syn -- */
+double orc_mg_block(double v, double mg) {
+    return 1.0 / (1.0 + exp(-0.062 * v) * mg / 3.57);
+}
+
+/* g(t) = exp(-t/tau_d) - exp(-t/tau_r) peaks at
+ * t_p = tau_r tau_d/(tau_d - tau_r) ln(tau_d/tau_r); f = 1/g(t_p), so that one
+ * event of weight w gives a conductance whose peak is exactly w.           */
+double orc_syn_peak_factor(double tau_r, double tau_d, double *t_peak) {
+    double tp = tau_r * tau_d / (tau_d - tau_r) * log(tau_d / tau_r);
+    if (t_peak) *t_peak = tp;
+    return 1.0 / (exp(-tp / tau_d) - exp(-tp / tau_r));
+}
+
+/* -------------------------------------------------------------- events -- */
+/* SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): the n-th output (n >= 1) of
+ * the generator started at `seed` is mix(seed + n*gamma).  The event draw of
+ * synapse gid at step k is output number n = gid*2^32 + k + 1.              */
+uint64_t orc_event_hash(uint64_t seed, int64_t gid, int64_t k) {
+    uint64_t n = ((uint64_t)gid << 32) + (uint64_t)k + 1u;
+    uint64_t z = seed + n * UINT64_C(0x9E3779B97F4A7C15);
+    z = (z ^ (z >> 30)) * UINT64_C(0xBF58476D1CE4E5B9);
+    z = (z ^ (z >> 27)) * UINT64_C(0x94D049BB133111EB);
+    return z ^ (z >> 31);
+}
+
+/* A synapse fires at a step with probability p = rate*dt (dt in ms): the
+ * draw is compared with T = floor(p * 2^64).                                */
+uint64_t orc_event_threshold(double rate_hz, double dt) {
+    double p = rate_hz * dt * 1e-3;
+    if (!(p > 0.0)) return 0;
+    if (p >= 1.0) return UINT64_MAX;
+    return (uint64_t)floor(p * 18446744073709551616.0);
+}
+
+/* ------------------------------------------------------------- current -- */
+/* Current of one instance at potential v with every STATE frozen:
+ * density mechanisms in mA/cm2, the synapse in nA.                         */
+static double instance_i(const orc_globals *gl, const orc_slot *s, int64_t i, double v) {
+    switch (s->kind) {
+    case ORC_PAS:
+        return s->par[0][i] * (v - s->par[1][i]);
+    case ORC_HH: {
+        double m = s->st[0][i], h = s->st[1][i], n = s->st[2][i];
+        double gna = s->par[0][i] * m * m * m * h;
+        double gk = s->par[1][i] * n * n * n * n;
+        return gna * (v - gl->ena) + gk * (v - gl->ek) + s->par[2][i] * (v - s->par[3][i]);
+    }
+    case ORC_IH:
+        return s->par[0][i] * s->st[0][i] * (v - gl->eh);
+    case ORC_CAHVA: {
+        double m = s->st[0][i], h = s->st[1][i];
+        double eca = orc_nernst_ca(s->st[2][i], gl->cao, gl->celsius);
+        return s->par[0][i] * m * m * h * (v - eca);
+    }
+    case ORC_SYN: {
+        double ga = s->st[1][i] - s->st[0][i];
+        double gn = s->st[3][i] - s->st[2][i];
+        /* nS * mV = pA; 1e-3 converts to nA */
+        return 1e-3 * (ga + gn * orc_mg_block(v, gl->mg)) * (v - gl->e_syn);
+    }
+    }
+    return 0.0;
+}
+
+void orc_instance_current(const orc_globals *gl, const orc_slot *s, int64_t i,
+                          double v, double *cur, double *cond) {
+    double i0 = instance_i(gl, s, i, v);
+    double i1 = instance_i(gl, s, i, v + gl->fd_dv);
+    *cur = i0;
+    *cond = (i1 - i0) / gl->fd_dv;
+}
+
+/* --------------------------------------------------------------- phases -- */
+void orc_init(const orc_globals *gl, orc_nodes *nd, orc_slot *slots, int nslots) {
+    for (int s = 0; s < nslots; ++s) {
+        orc_slot *sl = &slots[s];
+        for (int64_t i = 0; i < sl->n; ++i) {
+            double v = nd->v[sl->node[i]];
+            double o[6];
+            switch (sl->kind) {
+            case ORC_HH:
+                orc_hh_inf_tau(v, gl->celsius, o);
+                sl->st[0][i] = o[0]; sl->st[1][i] = o[1]; sl->st[2][i] = o[2];
+                break;
+            case ORC_IH:
+                orc_ih_inf_tau(v, o);
+                sl->st[0][i] = o[0];
+                break;
+            case ORC_CAHVA:
+                orc_cahva_inf_tau(v, o);
+                sl->st[0][i] = o[0]; sl->st[1][i] = o[1]; sl->st[2][i] = gl->cai0;
+                if (sl->ica) sl->ica[i] = 0.0;
+                break;
+            case ORC_SYN:
+                for (int j = 0; j < 4; ++j) sl->st[j][i] = 0.0;
+                break;
+            default:
+                break;
+            }
+        }
+    }
+    if (nd->spikes)
+        for (int64_t n = 0; n < nd->n_nodes; ++n) nd->spikes[n] = 0;
+}
+
+void orc_events(const orc_globals *gl, orc_slot *slots, int nslots, int64_t k, double dt) {
+    uint64_t T = orc_event_threshold(gl->event_rate_hz, dt);
+    double fa = orc_syn_peak_factor(gl->tau_r_ampa, gl->tau_d_ampa, NULL);
+    double fn = orc_syn_peak_factor(gl->tau_r_nmda, gl->tau_d_nmda, NULL);
+    for (int s = 0; s < nslots; ++s) {
+        orc_slot *sl = &slots[s];
+        if (sl->kind != ORC_SYN) continue;
+        for (int64_t i = 0; i < sl->n; ++i) {
+            int64_t gid = sl->gid ? sl->gid[i] : i;
+            if (orc_event_hash(gl->event_seed, gid, k) < T) {
+                double w = sl->par[0][i];
+                sl->st[0][i] += w * fa;
+                sl->st[1][i] += w * fa;
+                sl->st[2][i] += w * fn;
+                sl->st[3][i] += w * fn;
+            }
+        }
+    }
+}
+
+void orc_cur(const orc_globals *gl, orc_nodes *nd, orc_slot *slots, int nslots) {
+    for (int64_t n = 0; n < nd->n_nodes; ++n) { nd->rhs[n] = 0.0; nd->d[n] = 0.0; }
+    for (int s = 0; s < nslots; ++s) {
+        orc_slot *sl = &slots[s];
+        for (int64_t i = 0; i < sl->n; ++i) {
+            int32_t ni = sl->node[i];
+            double I0, g;
+            orc_instance_current(gl, sl, i, nd->v[ni], &I0, &g);
+            if (sl->kind == ORC_CAHVA && sl->ica) sl->ica[i] = I0;
+            if (sl->kind == ORC_SYN) {
+                /* nA/um2 -> mA/cm2 and uS/um2 -> S/cm2: both a factor 100 */
+                double sc = 1e2 / nd->area[ni];
+                nd->rhs[ni] -= sc * I0;
+                nd->d[ni] += sc * g;
+            } else {
+                nd->rhs[ni] -= I0;
+                nd->d[ni] += g;
+            }
+        }
+    }
+}
+
+void orc_vclamp(orc_nodes *nd, double t) {
+    for (int64_t n = 0; n < nd->n_nodes; ++n)
+        nd->v[n] = nd->clamp_off[n] +
+                   nd->clamp_amp[n] * sin(2.0 * ORC_PI * nd->clamp_freq[n] * t * 1e-3 + nd->clamp_phase[n]);
+}
+
+/* Backward Euler for an isolated compartment, linearised in v:
+ * 1e-3*cm*(v_new - v)/dt = rhs - d*(v_new - v).                              */
+void orc_visolated(const orc_globals *gl, orc_nodes *nd, double dt) {
+    for (int64_t n = 0; n < nd->n_nodes; ++n) {
+        double v0 = nd->v[n];
+        double v1 = v0 + nd->rhs[n] / (1e-3 * nd->cm[n] / dt + nd->d[n]);
+        if (nd->spikes && v0 < gl->vthresh && v1 >= gl->vthresh) nd->spikes[n] += 1;
+        nd->v[n] = v1;
+    }
+}
+
+/* cnexp: x' = (x_inf - x)/tau with x_inf and tau frozen over the step has the
+ * exact solution x(t+dt) = x_inf + (x - x_inf) exp(-dt/tau).                */
+static double cnexp(double x, double xinf, double tau, double dt) {
+    return xinf + (x - xinf) * exp(-dt / tau);
+}
+
+void orc_state(const orc_globals *gl, orc_nodes *nd, orc_slot *slots, int nslots, double dt) {
+    double kappa = orc_ca_kappa(gl->ca_gamma, gl->ca_depth);
+    for (int s = 0; s < nslots; ++s) {
+        orc_slot *sl = &slots[s];
+        for (int64_t i = 0; i < sl->n; ++i) {
+            double v = nd->v[sl->node[i]];
+            double o[6];
+            switch (sl->kind) {
+            case ORC_HH:
+                orc_hh_inf_tau(v, gl->celsius, o);
+                sl->st[0][i] = cnexp(sl->st[0][i], o[0], o[3], dt);
+                sl->st[1][i] = cnexp(sl->st[1][i], o[1], o[4], dt);
+                sl->st[2][i] = cnexp(sl->st[2][i], o[2], o[5], dt);
+                break;
+            case ORC_IH:
+                orc_ih_inf_tau(v, o);
+                sl->st[0][i] = cnexp(sl->st[0][i], o[0], o[1], dt);
+                break;
+            case ORC_CAHVA: {
+                orc_cahva_inf_tau(v, o);
+                sl->st[0][i] = cnexp(sl->st[0][i], o[0], o[2], dt);
+                sl->st[1][i] = cnexp(sl->st[1][i], o[1], o[3], dt);
+                /* linear in cai with ica held at its stored value:
+                 * cai_inf = cai0 - kappa*tau_ca*ica, time constant tau_ca   */
+                double cinf = gl->cai0 - kappa * gl->tau_ca * sl->ica[i];
+                sl->st[2][i] = cnexp(sl->st[2][i], cinf, gl->tau_ca, dt);
+                break;
+            }
+            case ORC_SYN:
+                sl->st[0][i] *= exp(-dt / gl->tau_r_ampa);
+                sl->st[1][i] *= exp(-dt / gl->tau_d_ampa);
+                sl->st[2][i] *= exp(-dt / gl->tau_r_nmda);
+                sl->st[3][i] *= exp(-dt / gl->tau_d_nmda);
+                break;
+            default:
+                break;
+            }
+        }
+    }
+}
+
+int orc_run(const orc_globals *gl, orc_nodes *nd, orc_slot *slots, int nslots,
+            int64_t k0, int64_t nsteps, double dt, int vmode) {
+    if (!gl || !nd || (nslots > 0 && !slots) || nsteps < 0 || !(dt > 0.0)) return -1;
+    if (vmode == ORC_V_CLAMP) orc_vclamp(nd, (double)k0 * dt);
+    for (int64_t k = k0; k < k0 + nsteps; ++k) {
+        orc_events(gl, slots, nslots, k, dt);
+        orc_cur(gl, nd, slots, nslots);
+        if (vmode == ORC_V_CLAMP) orc_vclamp(nd, (double)(k + 1) * dt);
+        else if (vmode == ORC_V_ISOLATED) orc_visolated(gl, nd, dt);
+        orc_state(gl, nd, slots, nslots, dt);
+    }
+    return 0;
+}

@@ -1,0 +1,119 @@
+/*
+ * mech_oracle.h -- plain FP64 CPU oracle for the per-timestep mechanism kernels.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This code is the slow, obviously-correct reference
+ * that the GPU library is checked against.  Only the tests, the smoke check and
+ * the CPU-baseline leg of the benchmark may load it; the product path never
+ * does.  It shares no code, header, table or constant with the GPU library.
+ *
+ * What it computes (paper: section 3, NMODL blocks; section 5.2, cnexp; section
+ * 5.2 last paragraph, numerically approximated conductance; section 8 and
+ * Table 3, the State Update / Current Update / Other split of a timestep):
+ *
+ *   one timestep k (t_k = k*dt, never a running sum):
+ *     1. events   : every synapse whose counter-based draw H(seed,gid,k) lies
+ *                   below T = floor(rate*dt*1e-3 * 2^64) receives w*f on both
+ *                   rise and decay states of both receptors;
+ *     2. cur      : rhs = d = 0, then for every slot in order and every instance
+ *                   in index order: I0 = i(v), I1 = i(v+dv), g = (I1-I0)/dv,
+ *                   rhs[node] -= s*I0, d[node] += s*g  (s = 1 for density
+ *                   mechanisms, s = 100/area for point processes);
+ *     3. voltage  : CLAMP    v = off + amp*sin(2*pi*freq*t_{k+1}*1e-3 + phase)
+ *                   ISOLATED v += rhs/(1e-3*cm/dt + d), count upward crossings
+ *                   of vthresh
+ *                   EXTERNAL v unchanged;
+ *     4. state    : cnexp update of every STATE at the new v.
+ *
+ * Units: mV, ms, mA/cm2 and S/cm2 (density), nA and uS (point process),
+ * um2, uF/cm2, mM, degC; synaptic weights and states in nS.
+ *
+ * Parity pins: every function here is pinned in tests/ against closed forms,
+ * invariants, published values or brute force.  The Ih and Ca-HVA rate
+ * constants are this project's own synthetic definitions; beyond the closed
+ * forms and invariants they are pinned to nothing external ("parity unpinned"
+ * for their constants, see the test module docstrings).
+ */
+#ifndef MECH_ORACLE_H
+#define MECH_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_PAS = 0, ORC_HH = 1, ORC_IH = 2, ORC_CAHVA = 3, ORC_SYN = 4 };
+enum { ORC_V_EXTERNAL = 0, ORC_V_CLAMP = 1, ORC_V_ISOLATED = 2 };
+
+/* One mechanism type ("slot") and its instances, in the caller's order.
+ *   st : STATE arrays     hh: m,h,n   ih: m   cahva: m,h,cai   syn: Aa,Ba,An,Bn
+ *   par: RANGE parameters hh: gnabar,gkbar,gl,el   pas: g,e   ih: gbar
+ *                         cahva: gbar   syn: weight (nS)
+ *   ica: Ca-HVA calcium current written by cur and read by state (mA/cm2)
+ *   gid: synapse event-stream id (NULL: the instance index is used)        */
+typedef struct {
+    int32_t kind;
+    int64_t n;
+    const int32_t *node;
+    const int64_t *gid;
+    double *st[4];
+    const double *par[4];
+    double *ica;
+} orc_slot;
+
+typedef struct {
+    double celsius;                 /* degC                                  */
+    double ena, ek, eh;             /* mV                                    */
+    double cao, cai0, tau_ca;       /* mM, mM, ms                            */
+    double ca_gamma, ca_depth;      /* free fraction, shell depth (um)       */
+    double e_syn, mg;               /* mV, mM                                */
+    double tau_r_ampa, tau_d_ampa;  /* ms                                    */
+    double tau_r_nmda, tau_d_nmda;  /* ms                                    */
+    double event_rate_hz;           /* Hz                                    */
+    double vthresh;                 /* mV                                    */
+    double fd_dv;                   /* mV                                    */
+    uint64_t event_seed;
+} orc_globals;
+
+typedef struct {
+    int64_t n_nodes;
+    double *v, *rhs, *d;
+    const double *area;             /* um2, NULL if no point process        */
+    const double *cm;               /* uF/cm2, ISOLATED mode only            */
+    const double *clamp_off, *clamp_amp, *clamp_freq, *clamp_phase;
+    int32_t *spikes;                /* ISOLATED mode only                    */
+} orc_nodes;
+
+/* ---- single-point functions (used by the pins) ----------------------- */
+/* out = {m_inf, h_inf, n_inf, tau_m, tau_h, tau_n}                         */
+void orc_hh_inf_tau(double v, double celsius, double *out6);
+/* out = {alpha_m, beta_m, alpha_h, beta_h, alpha_n, beta_n} (1/ms, q10 = 1) */
+void orc_hh_rates(double v, double *out6);
+void orc_ih_inf_tau(double v, double *out2);                 /* m_inf, tau_m */
+void orc_cahva_inf_tau(double v, double *out4);   /* m_inf, h_inf, tau_m, tau_h */
+double orc_mg_block(double v, double mg);
+double orc_syn_peak_factor(double tau_r, double tau_d, double *t_peak);
+double orc_nernst_ca(double cai, double cao, double celsius);     /* mV      */
+double orc_ca_kappa(double gamma, double depth);   /* mM/ms per mA/cm2      */
+uint64_t orc_event_hash(uint64_t seed, int64_t gid, int64_t k);
+uint64_t orc_event_threshold(double rate_hz, double dt);
+/* current of one instance at v with frozen states: *i = I(v), *g = FD di/dv */
+void orc_instance_current(const orc_globals *gl, const orc_slot *s, int64_t i,
+                          double v, double *cur, double *cond);
+
+/* ---- phases and the full step loop ------------------------------------ */
+void orc_init(const orc_globals *gl, orc_nodes *nd, orc_slot *slots, int nslots);
+void orc_events(const orc_globals *gl, orc_slot *slots, int nslots, int64_t k, double dt);
+void orc_cur(const orc_globals *gl, orc_nodes *nd, orc_slot *slots, int nslots);
+void orc_vclamp(orc_nodes *nd, double t);
+void orc_visolated(const orc_globals *gl, orc_nodes *nd, double dt);
+void orc_state(const orc_globals *gl, orc_nodes *nd, orc_slot *slots, int nslots, double dt);
+/* runs steps k0 .. k0+nsteps-1; in CLAMP mode v is first set to the clamp
+ * value at t_{k0}.  Returns 0, or -1 on a bad argument.                   */
+int orc_run(const orc_globals *gl, orc_nodes *nd, orc_slot *slots, int nslots,
+            int64_t k0, int64_t nsteps, double dt, int vmode);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

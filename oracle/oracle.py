@@ -1,0 +1,256 @@
+"""ctypes binding of the FP64 CPU oracle (TEST INFRASTRUCTURE ONLY).
+
+Only tests, the smoke check and the benchmark's CPU-baseline leg import this
+module.  It loads ``liboracle.so`` built from ``mech_oracle.c`` by plain gcc
+with -O2 -fno-fast-math -ffp-contract=off (``build()``), and it imports
+nothing from the GPU package: a workload is read through its attributes
+(``n_nodes``, ``slots[i].kind/.node/.params/.gid``, ``area``, ``cm``,
+``clamp_*``, ``globals``, ``vmode``, ``dt``, ``v_init``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Dict, List
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "mech_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+KIND = {"pas": 0, "hh": 1, "ih": 2, "cahva": 3, "syn": 4}
+VMODE = {"external": 0, "clamp": 1, "isolated": 2}
+PARAMS = {"pas": ("g", "e"), "hh": ("gnabar", "gkbar", "gl", "el"), "ih": ("gbar",),
+          "cahva": ("gbar",), "syn": ("weight",)}
+STATES = {"pas": (), "hh": ("m", "h", "n"), "ih": ("m",), "cahva": ("m", "h", "cai"),
+          "syn": ("A_ampa", "B_ampa", "A_nmda", "B_nmda")}
+GLOBAL_FIELDS = ("celsius", "ena", "ek", "eh", "cao", "cai0", "tau_ca", "ca_gamma", "ca_depth",
+                 "e_syn", "mg", "tau_r_ampa", "tau_d_ampa", "tau_r_nmda", "tau_d_nmda",
+                 "event_rate_hz", "vthresh", "fd_dv")
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+_lp = C.POINTER(C.c_int64)
+
+
+class _Slot(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n", C.c_int64), ("node", _ip), ("gid", _lp),
+                ("st", _dp * 4), ("par", _dp * 4), ("ica", _dp)]
+
+
+class _Globals(C.Structure):
+    _fields_ = [(f, C.c_double) for f in GLOBAL_FIELDS] + [("event_seed", C.c_uint64)]
+
+
+class _Nodes(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("v", _dp), ("rhs", _dp), ("d", _dp), ("area", _dp), ("cm", _dp),
+                ("clamp_off", _dp), ("clamp_amp", _dp), ("clamp_freq", _dp), ("clamp_phase", _dp),
+                ("spikes", _ip)]
+
+
+def build(force: bool = False) -> str:
+    """Compile liboracle.so with gcc (plain C99, strict IEEE, no contraction)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < max(
+            os.path.getmtime(SRC), os.path.getmtime(os.path.join(HERE, "mech_oracle.h"))):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-std=c99", "-O2", "-fno-fast-math", "-ffp-contract=off",
+                               "-Wall", "-Wextra", "-fPIC", "-shared", SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        L.orc_hh_inf_tau.argtypes = [C.c_double, C.c_double, _dp]
+        L.orc_hh_rates.argtypes = [C.c_double, _dp]
+        L.orc_ih_inf_tau.argtypes = [C.c_double, _dp]
+        L.orc_cahva_inf_tau.argtypes = [C.c_double, _dp]
+        L.orc_mg_block.argtypes = [C.c_double, C.c_double]
+        L.orc_mg_block.restype = C.c_double
+        L.orc_syn_peak_factor.argtypes = [C.c_double, C.c_double, _dp]
+        L.orc_syn_peak_factor.restype = C.c_double
+        L.orc_nernst_ca.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.orc_nernst_ca.restype = C.c_double
+        L.orc_ca_kappa.argtypes = [C.c_double, C.c_double]
+        L.orc_ca_kappa.restype = C.c_double
+        L.orc_event_hash.argtypes = [C.c_uint64, C.c_int64, C.c_int64]
+        L.orc_event_hash.restype = C.c_uint64
+        L.orc_event_threshold.argtypes = [C.c_double, C.c_double]
+        L.orc_event_threshold.restype = C.c_uint64
+        L.orc_instance_current.argtypes = [C.POINTER(_Globals), C.POINTER(_Slot), C.c_int64, C.c_double, _dp, _dp]
+        sig = [C.POINTER(_Globals), C.POINTER(_Nodes), C.POINTER(_Slot), C.c_int]
+        L.orc_init.argtypes = sig
+        L.orc_cur.argtypes = sig
+        L.orc_events.argtypes = [C.POINTER(_Globals), C.POINTER(_Slot), C.c_int, C.c_int64, C.c_double]
+        L.orc_vclamp.argtypes = [C.POINTER(_Nodes), C.c_double]
+        L.orc_visolated.argtypes = [C.POINTER(_Globals), C.POINTER(_Nodes), C.c_double]
+        L.orc_state.argtypes = sig + [C.c_double]
+        L.orc_run.argtypes = sig + [C.c_int64, C.c_int64, C.c_double, C.c_int]
+        L.orc_run.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a, t=_dp):
+    return None if a is None else a.ctypes.data_as(t)
+
+
+# ------------------------------------------------------------ scalar API --
+def hh_inf_tau(v: float, celsius: float = 6.3) -> np.ndarray:
+    o = np.zeros(6)
+    lib().orc_hh_inf_tau(v, celsius, _ptr(o))
+    return o
+
+
+def hh_rates(v: float) -> np.ndarray:
+    o = np.zeros(6)
+    lib().orc_hh_rates(v, _ptr(o))
+    return o
+
+
+def ih_inf_tau(v: float) -> np.ndarray:
+    o = np.zeros(2)
+    lib().orc_ih_inf_tau(v, _ptr(o))
+    return o
+
+
+def cahva_inf_tau(v: float) -> np.ndarray:
+    o = np.zeros(4)
+    lib().orc_cahva_inf_tau(v, _ptr(o))
+    return o
+
+
+def mg_block(v: float, mg: float = 1.0) -> float:
+    return lib().orc_mg_block(v, mg)
+
+
+def syn_peak_factor(tau_r: float, tau_d: float):
+    tp = C.c_double(0.0)
+    f = lib().orc_syn_peak_factor(tau_r, tau_d, C.byref(tp))
+    return f, tp.value
+
+
+def nernst_ca(cai: float, cao: float, celsius: float) -> float:
+    return lib().orc_nernst_ca(cai, cao, celsius)
+
+
+def ca_kappa(gamma: float, depth: float) -> float:
+    return lib().orc_ca_kappa(gamma, depth)
+
+
+def event_hash(seed: int, gid: int, k: int) -> int:
+    return int(lib().orc_event_hash(seed, gid, k))
+
+
+def event_threshold(rate_hz: float, dt: float) -> int:
+    return int(lib().orc_event_threshold(rate_hz, dt))
+
+
+# ----------------------------------------------------------------- model --
+class Model:
+    """Owns FP64 copies of one workload's arrays and runs the oracle on them.
+
+    ``states[s][name]`` are the STATE arrays of slot s in the caller's
+    instance order; ``v``, ``rhs``, ``d``, ``spikes`` are node arrays."""
+
+    def __init__(self, w):
+        self.w = w
+        self.n_nodes = int(w.n_nodes)
+        n = self.n_nodes
+        self.v = np.full(n, float(w.v_init))
+        self.rhs = np.zeros(n)
+        self.d = np.zeros(n)
+        self.spikes = np.zeros(n, dtype=np.int32)
+        f64 = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+        self.area, self.cm = f64(w.area), f64(w.cm)
+        self.clamp = [f64(getattr(w, "clamp_" + k)) for k in ("off", "amp", "freq", "phase")]
+        self.globals = dict(w.globals)
+        self.dt = float(w.dt)
+        self.vmode = w.vmode
+        self.states: List[Dict[str, np.ndarray]] = []
+        self.ica: List[np.ndarray] = []
+        self._keep = []
+        self._slots = (_Slot * max(1, len(w.slots)))()
+        for i, s in enumerate(w.slots):
+            node = np.ascontiguousarray(s.node, dtype=np.int32)
+            if node.size and (node.min() < 0 or node.max() >= n):
+                raise ValueError("node index out of range")
+            gid = None if s.gid is None else np.ascontiguousarray(s.gid, dtype=np.int64)
+            st = {name: np.zeros(node.shape[0]) for name in STATES[s.kind]}
+            par = [np.ascontiguousarray(s.params[p], dtype=np.float64) for p in PARAMS[s.kind]]
+            ica = np.zeros(node.shape[0])
+            self.states.append(st)
+            self.ica.append(ica)
+            self._keep.append((node, gid, par))
+            sl = self._slots[i]
+            sl.kind = KIND[s.kind]
+            sl.n = node.shape[0]
+            sl.node = _ptr(node, _ip)
+            sl.gid = _ptr(gid, _lp) if gid is not None else None
+            for j, name in enumerate(STATES[s.kind]):
+                sl.st[j] = _ptr(st[name])
+            for j, a in enumerate(par):
+                sl.par[j] = _ptr(a)
+            sl.ica = _ptr(ica)
+        self.nslots = len(w.slots)
+        self._nodes = _Nodes(n, _ptr(self.v), _ptr(self.rhs), _ptr(self.d), _ptr(self.area), _ptr(self.cm),
+                             *[_ptr(a) for a in self.clamp], _ptr(self.spikes, _ip))
+        self._g = self._make_globals()
+
+    def _make_globals(self):
+        g = _Globals()
+        for f in GLOBAL_FIELDS:
+            setattr(g, f, float(self.globals[f]))
+        g.event_seed = int(self.globals["event_seed"]) & ((1 << 64) - 1)
+        return g
+
+    def set_global(self, name, value):
+        self.globals[name] = value
+        self._g = self._make_globals()
+
+    def _args(self):
+        return C.byref(self._g), C.byref(self._nodes), self._slots, self.nslots
+
+    def init(self, v_init=None):
+        """v = v_init everywhere, then every STATE at its steady state."""
+        self.v[:] = self.w.v_init if v_init is None else v_init
+        lib().orc_init(*self._args())
+
+    def events(self, k: int):
+        lib().orc_events(C.byref(self._g), self._slots, self.nslots, k, self.dt)
+
+    def cur(self):
+        lib().orc_cur(*self._args())
+
+    def state(self):
+        lib().orc_state(*self._args(), self.dt)
+
+    def vclamp(self, t: float):
+        lib().orc_vclamp(C.byref(self._nodes), t)
+
+    def visolated(self):
+        lib().orc_visolated(C.byref(self._g), C.byref(self._nodes), self.dt)
+
+    def run(self, k0: int, nsteps: int, vmode=None):
+        vm = VMODE[vmode or self.vmode]
+        if vm == 1 and any(a is None for a in self.clamp):
+            raise ValueError("clamp mode needs clamp arrays")
+        if vm == 2 and self.cm is None:
+            raise ValueError("isolated mode needs cm")
+        r = lib().orc_run(*self._args(), k0, nsteps, self.dt, vm)
+        if r != 0:
+            raise ValueError("orc_run rejected its arguments")
+
+    def instance_current(self, s: int, i: int, v: float):
+        cur, cond = C.c_double(), C.c_double()
+        lib().orc_instance_current(C.byref(self._g), C.byref(self._slots[s]), i, v, C.byref(cur), C.byref(cond))
+        return cur.value, cond.value

@@ -1,0 +1,390 @@
+"""Pins of the FP64 CPU oracle against facts fixed outside it.
+
+Each test checks the oracle against a published value (tests/golden/), a
+closed form of the mathematics, an invariant of the method, or brute force in
+numpy, chosen so that a dropped term, a wrong sign, offset or index, or a
+swapped operand in the oracle fails at least one of them.
+
+Paper references: section 3 (BREAKPOINT current / conductance, DERIVATIVE +
+SOLVE state update, density vs point-process mechanisms); section 5.2 (cnexp:
+analytic solution with coefficients constant over a step; the numerically
+approximated conductance).
+
+Parity unpinned: the Ih and Ca-HVA rate constants are this project's own
+synthetic definitions; beyond the closed forms and invariants below (their
+limits, symmetric points, steady states and bounds) nothing external pins
+them.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_1905_02241_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append(line.split())
+    return rows
+
+
+# ------------------------------------------------------------------- hh --
+def test_hh_resting_state_matches_textbook(oracle):
+    m, h, n = oracle.hh_inf_tau(-65.0, 6.3)[:3]
+    got = {"m_inf_rest": m, "h_inf_rest": h, "n_inf_rest": n}
+    for name, val, tol in _golden("hh_resting_state.txt"):
+        assert abs(got[name] - float(val)) <= float(tol), name
+
+
+def test_hh_rates_at_their_reference_points(oracle):
+    # exp(0) = 1 at the reference potential of every exponential rate
+    r = oracle.hh_rates(-65.0)
+    assert r[1] == 4.0 and r[2] == 0.07 and r[5] == 0.125
+    assert oracle.hh_rates(-35.0)[3] == 0.5          # beta_h = 1/(1+1)
+    # far from the singular points the vtrap rates approach their linear asymptote
+    r = oracle.hh_rates(60.0)
+    assert abs(r[0] - 0.1 * 100 / (1 - math.exp(-10))) < 1e-13
+    assert abs(r[4] - 0.01 * 115 / (1 - math.exp(-11.5))) < 1e-15
+
+
+def test_hh_removable_singularities(oracle):
+    # alpha = a x/(1 - e^{-x/k}) -> a k at x = 0 (l'Hopital), and near it the
+    # Bernoulli series a k (1 + u/2 + u^2/12), u = x/k
+    assert oracle.hh_rates(-40.0)[0] == 1.0
+    assert oracle.hh_rates(-55.0)[4] == 0.1
+    for dx in (1e-9, -1e-9, 1e-6, -1e-6, 1e-3):
+        u = dx / 10.0
+        ser = 1 + u / 2 + u * u / 12
+        assert abs(oracle.hh_rates(-40.0 + dx)[0] - ser) < 2e-15
+        assert abs(oracle.hh_rates(-55.0 + dx)[4] - 0.1 * ser) < 2e-16
+
+
+def test_q10_scales_time_constants_only(oracle):
+    a = oracle.hh_inf_tau(-50.0, 6.3)
+    b = oracle.hh_inf_tau(-50.0, 16.3)  # q10 = 3 exactly one decade up
+    assert np.allclose(a[:3], b[:3], rtol=0, atol=0)
+    assert np.allclose(a[3:] / 3.0, b[3:], rtol=1e-15)
+
+
+def _single(kind, v_clamp, nsteps, params=None, dt=0.025, v_init=-65.0, **g):
+    w = W.Workload("one", 1, [W._slot(kind, np.array([0]), params)], "clamp", dt, nsteps, v_init=v_init,
+                   area=np.array([100.0]), cm=np.array([1.0]), clamp_off=np.array([v_clamp]),
+                   clamp_amp=np.zeros(1), clamp_freq=np.zeros(1), clamp_phase=np.zeros(1))
+    w.globals.update(g)
+    return w
+
+
+def test_cnexp_equals_closed_form_under_clamp(oracle):
+    # With v held, x' = (x_inf - x)/tau has x(t) = x_inf + (x0 - x_inf) e^{-t/tau};
+    # the cnexp iterate must reproduce it at every step to rounding.
+    w = _single("hh", -20.0, 1000)
+    M = oracle.Model(w)
+    M.init()
+    x0 = np.array([M.states[0][k][0] for k in "mhn"])
+    inf_tau = oracle.hh_inf_tau(-20.0, 6.3)
+    for block in range(4):
+        M.run(block * 250, 250)
+        t = (block + 1) * 250 * w.dt
+        ref = inf_tau[:3] + (x0 - inf_tau[:3]) * np.exp(-t / inf_tau[3:])
+        got = np.array([M.states[0][k][0] for k in "mhn"])
+        assert np.all(np.abs(got - ref) <= 2e-15 + 1e-13 * np.abs(ref))
+
+
+def test_steady_state_is_a_fixed_point(oracle):
+    rng = np.random.default_rng(1)
+    for kind in ("hh", "ih", "cahva"):
+        for v in rng.uniform(-90, 30, 5):
+            w = _single(kind, v, 50, v_init=v)
+            if kind == "cahva":
+                w.slots[0].params["gbar"][:] = 0.0   # keep cai at cai0
+            M = oracle.Model(w)
+            M.init(v)
+            before = {k: a.copy() for k, a in M.states[0].items()}
+            M.run(0, 50)
+            for k, a in M.states[0].items():
+                if kind == "cahva" and k == "cai":
+                    continue
+                assert np.array_equal(a, before[k]), (kind, k, v)
+
+
+def test_gates_stay_in_unit_interval(oracle):
+    w = W.make_tiny(3, kinds=("hh", "ih", "cahva"), n_nodes=40, shuffle=False, nsteps=400)
+    w.clamp_amp[:] = 80.0   # swing the clamp over -145..15 mV
+    M = oracle.Model(w)
+    M.init()
+    for _ in range(8):
+        M.run(_ * 50, 50)
+        for s, st in zip(w.slots, M.states):
+            for name, a in st.items():
+                if name != "cai":
+                    assert np.all((a >= 0.0) & (a <= 1.0)), (s.kind, name)
+
+
+# ----------------------------------------------------- currents and FD --
+def test_current_vanishes_at_reversal(oracle):
+    # pas at v = e; hh terms one at a time at their reversal; Ih at eh; synapse at e_syn
+    w = _single("pas", 0.0, 1, params={"g": np.array([3e-3]), "e": np.array([-61.5])})
+    M = oracle.Model(w)
+    assert M.instance_current(0, 0, -61.5)[0] == 0.0
+    w = _single("hh", 0.0, 1, params={"gkbar": np.array([0.0]), "gl": np.array([0.0])})
+    M = oracle.Model(w)
+    M.init()
+    assert M.instance_current(0, 0, 50.0)[0] == 0.0          # ina at ena
+    w = _single("hh", 0.0, 1, params={"gnabar": np.array([0.0]), "gl": np.array([0.0])})
+    M = oracle.Model(w)
+    M.init()
+    assert M.instance_current(0, 0, -77.0)[0] == 0.0         # ik at ek
+    w = _single("hh", 0.0, 1, params={"gnabar": np.array([0.0]), "gkbar": np.array([0.0])})
+    M = oracle.Model(w)
+    M.init()
+    assert M.instance_current(0, 0, -54.3)[0] == 0.0         # il at el
+    w = _single("ih", 0.0, 1)
+    M = oracle.Model(w)
+    M.init()
+    assert M.instance_current(0, 0, -45.0)[0] == 0.0
+    w = _single("syn", 0.0, 1)
+    M = oracle.Model(w)
+    M.init()
+    for j, name in enumerate(("A_ampa", "B_ampa", "A_nmda", "B_nmda")):
+        M.states[0][name][0] = [0.1, 0.7, 0.2, 0.9][j]
+    assert M.instance_current(0, 0, 0.0)[0] == 0.0
+    assert M.instance_current(0, 0, -65.0)[0] < 0.0          # inward at rest
+
+
+def test_fd_conductance_matches_analytic(oracle):
+    # ohmic currents: di/dv is the sum of the conductance products; the FD
+    # error is rounding only, eps |i| / dv ~ 1e-11 relative
+    w = _single("hh", 0.0, 1)
+    M = oracle.Model(w)
+    M.init(-30.0)
+    m, h, n = (M.states[0][k][0] for k in "mhn")
+    ga = 0.12 * m ** 3 * h + 0.036 * n ** 4 + 0.0003
+    for v in (-80.0, -30.0, 10.0, 40.0):
+        i, g = M.instance_current(0, 0, v)
+        assert abs(g - ga) <= 1e-9 * ga
+        # and i is linear in v with that slope
+        assert abs(i - (0.12 * m ** 3 * h * (v - 50) + 0.036 * n ** 4 * (v + 77) + 0.0003 * (v + 54.3))) < 1e-13
+    # NMDA: analytic g = 1e-3 (ga + gn (B + (v - e) B')), B' = 0.062 B (1 - B)
+    w = _single("syn", 0.0, 1)
+    M = oracle.Model(w)
+    M.init()
+    for name, val in zip(("A_ampa", "B_ampa", "A_nmda", "B_nmda"), (0.2, 1.0, 0.1, 0.6)):
+        M.states[0][name][0] = val
+    for v in (-70.0, -20.0, 5.0):
+        B = 1.0 / (1.0 + math.exp(-0.062 * v) / 3.57)
+        ga_an = 1e-3 * (0.8 + 0.5 * (B + v * 0.062 * B * (1 - B)))
+        i, g = M.instance_current(0, 0, v)
+        # O(dv) truncation of the forward difference: |i''| dv/2
+        assert abs(g - ga_an) < 2e-7
+        assert abs(i - 1e-3 * (0.8 + 0.5 * B) * v) < 1e-15
+
+
+def test_mg_block_closed_forms(oracle):
+    assert abs(oracle.mg_block(0.0, 1.0) - 3.57 / 4.57) < 4e-16   # two roundings apart
+    assert oracle.mg_block(0.0, 0.0) == 1.0                 # no magnesium, no block
+    vs = np.linspace(-120, 60, 50)
+    b = np.array([oracle.mg_block(v, 1.0) for v in vs])
+    assert np.all(np.diff(b) > 0) and b[0] < 3e-3 and b[-1] > 0.97
+
+
+def test_synapse_peak_normalisation(oracle):
+    for tr, td in ((0.2, 1.7), (0.29, 43.0)):
+        f, tp = oracle.syn_peak_factor(tr, td)
+        t = np.linspace(0, 10 * td, 2_000_001)
+        g = f * (np.exp(-t / td) - np.exp(-t / tr))
+        assert abs(g.max() - 1.0) < 1e-9
+        assert abs(t[g.argmax()] - tp) < 2 * (t[1] - t[0])
+
+
+def test_synapse_impulse_response(oracle):
+    # a single event of weight w at step 0 gives g(t_n) = w f (e^{-t/td} - e^{-t/tr}) at t_n = n dt
+    w = _single("syn", -65.0, 1, v_init=-65.0, params={"weight": np.array([1.7])})
+    w.globals["event_rate_hz"] = 1e9    # p >= 1: fires at every step
+    M = oracle.Model(w)
+    M.init(-65.0)
+    M.events(0)
+    M.set_global("event_rate_hz", 0.0)
+    fa, _ = oracle.syn_peak_factor(0.2, 1.7)
+    fn, _ = oracle.syn_peak_factor(0.29, 43.0)
+    st = M.states[0]
+    assert st["A_ampa"][0] == st["B_ampa"][0] == 1.7 * fa
+    for k in range(1, 401):
+        M.run(k, 1)
+        t = k * 0.025
+        ga = st["B_ampa"][0] - st["A_ampa"][0]
+        gn = st["B_nmda"][0] - st["A_nmda"][0]
+        assert abs(ga - 1.7 * fa * (math.exp(-t / 1.7) - math.exp(-t / 0.2))) < 1e-13
+        assert abs(gn - 1.7 * fn * (math.exp(-t / 43.0) - math.exp(-t / 0.29))) < 1e-13
+
+
+def test_calcium_pool_relaxes_to_rest(oracle):
+    w = _single("cahva", -65.0, 1, params={"gbar": np.array([0.0])})
+    M = oracle.Model(w)
+    M.init(-65.0)
+    c0 = 3e-4
+    M.states[0]["cai"][0] = c0
+    M.run(0, 2000)
+    t = 2000 * 0.025
+    ref = 5e-5 + (c0 - 5e-5) * math.exp(-t / 80.0)
+    assert abs(M.states[0]["cai"][0] - ref) < 1e-15
+
+
+def test_calcium_influx_rate_from_si_units(oracle):
+    # d cai/dt at cai = cai0 equals -kappa ica.  Independent SI derivation:
+    # ica (mA/cm2) over 1 cm2 is ica*1e-3 A -> ica*1e-3/(2F) mol/s into a
+    # shell of depth*1e-4 cm * 1 cm2 = depth*1e-7 L, free fraction gamma.
+    F = 96485.33212
+    gamma, depth = 0.05, 0.1
+    ica = -2e-3
+    mol_per_s = -ica * 1e-3 / (2 * F)
+    mM_per_ms = gamma * mol_per_s / (depth * 1e-7) * 1e3 / 1e3
+    assert abs(oracle.ca_kappa(gamma, depth) * -ica - mM_per_ms) < 1e-15 * mM_per_ms + 1e-20
+
+
+def test_nernst_slope_matches_textbook(oracle):
+    (celsius, slope, tol), = _golden("nernst_slope.txt")
+    got = oracle.nernst_ca(1.0, 10.0, float(celsius))
+    assert abs(got - float(slope)) <= float(tol)
+    assert abs(oracle.nernst_ca(5e-5, 2.0, 6.3) - 1e3 * 8.314462618 * 279.45 / (2 * F_()) * math.log(4e4)) < 1e-10
+
+
+def F_():
+    return 96485.33212
+
+
+# ------------------------------------------------------ Ih and Ca-HVA --
+def test_ih_closed_forms(oracle):
+    # alpha = beta at -90 mV: m_inf = 1/2 and tau = 1/(0.01) = 100 ms;
+    # m_inf(v) = 1/(1 + e^{(v+90)/10}) by dividing alpha and beta
+    mi, tau = oracle.ih_inf_tau(-90.0)
+    assert mi == 0.5 and abs(tau - 100.0) < 1e-12
+    for v in (-120.0, -70.0, -40.0):
+        assert abs(oracle.ih_inf_tau(v)[0] - 1.0 / (1.0 + math.exp((v + 90) / 10))) < 1e-15
+
+
+def test_cahva_closed_forms(oracle):
+    # at v = -20 alpha_m hits its removable singularity (limit 0.5) and beta_h = 0.006/2
+    o = oracle.cahva_inf_tau(-20.0)
+    bm = 0.8 * math.exp(-25.0 / 15.0)
+    assert abs(o[0] - 0.5 / (0.5 + bm)) < 1e-15
+    ah = 0.0005 * math.exp(-40.0 / 25.0)
+    assert abs(o[1] - ah / (ah + 0.003)) < 1e-15
+
+
+# ------------------------------------------------------------- events --
+def test_event_hash_matches_splitmix64_reference(oracle):
+    for n, hx in _golden("splitmix64_seed0.txt"):
+        # output number n of the stream seeded 0 is event draw (gid 0, k = n - 1)
+        assert oracle.event_hash(0, 0, int(n) - 1) == int(hx, 16)
+
+
+def test_event_rate_is_poisson(oracle):
+    p_rate, dt = 5.0, 0.025
+    T = oracle.event_threshold(p_rate, dt)
+    assert T == math.floor(5.0 * 0.025 * 1e-3 * 2.0 ** 64)
+    w = W.make_tiny(7, kinds=("syn",), n_nodes=2000, syn_per_node=5.0, event_rate_hz=200.0, vmode="clamp")
+    M = oracle.Model(w)
+    M.init()
+    n_syn = w.slots[0].n
+    fires = 0
+    for k in range(200):
+        M.states[0]["A_ampa"][:] = 0.0
+        M.events(k)
+        fires += int(np.count_nonzero(M.states[0]["A_ampa"]))
+    p = 200.0 * 0.025e-3
+    mean = p * n_syn * 200
+    assert abs(fires - mean) < 5 * math.sqrt(mean)
+
+
+# ------------------------------------------------------------ scatter --
+def test_scatter_equals_numpy_add_at_bit_exact(oracle):
+    # dyadic g, e, v, dv: every product and sum is exact, so the oracle's
+    # rhs/d must equal numpy's unordered np.add.at bit for bit
+    rng = np.random.default_rng(11)
+    n_nodes = 37
+    node = rng.integers(0, n_nodes, 300).astype(np.int32)
+    g = rng.integers(1, 64, 300) * 2.0 ** -12
+    e = rng.integers(-90, 10, 300).astype(float)
+    w = W.Workload("scatter", n_nodes, [W._slot("pas", node, {"g": g, "e": e})], "external", 0.025, 1)
+    w.globals["fd_dv"] = 2.0 ** -10
+    M = oracle.Model(w)
+    M.v[:] = rng.integers(-100, 40, n_nodes).astype(float)
+    M.cur()
+    rhs = np.zeros(n_nodes)
+    d = np.zeros(n_nodes)
+    np.add.at(rhs, node, -g * (M.v[node] - e))
+    np.add.at(d, node, g)
+    assert np.array_equal(M.rhs, rhs)
+    assert np.array_equal(M.d, d)
+
+
+def test_point_process_scatter_scales_by_area(oracle):
+    w = W.make_tiny(5, kinds=("syn",), n_nodes=30, syn_per_node=4.0, shuffle=True)
+    M = oracle.Model(w)
+    M.init()
+    rng = np.random.default_rng(2)
+    for name in ("A_ampa", "B_ampa", "A_nmda", "B_nmda"):
+        M.states[0][name][:] = rng.uniform(0, 2, w.slots[0].n)
+    M.v[:] = rng.uniform(-80, 20, w.n_nodes)
+    M.cur()
+    node = w.slots[0].node
+    I = np.array([M.instance_current(0, i, M.v[node[i]]) for i in range(w.slots[0].n)])
+    rhs = np.zeros(w.n_nodes)
+    d = np.zeros(w.n_nodes)
+    np.add.at(rhs, node, -(1e2 / w.area[node]) * I[:, 0])
+    np.add.at(d, node, (1e2 / w.area[node]) * I[:, 1])
+    assert np.allclose(M.rhs, rhs, rtol=1e-13, atol=1e-18)
+    assert np.allclose(M.d, d, rtol=1e-13, atol=1e-18)
+
+
+# ------------------------------------------------------ voltage glue --
+def test_isolated_backward_euler_closed_form(oracle):
+    # pas only: v_{k+1} - e = (v_k - e) c/(c + g), c = 1e-3 cm/dt
+    w = _single("pas", 0.0, 1, params={"g": np.array([2e-3]), "e": np.array([-70.0])})
+    w.vmode = "isolated"
+    w.cm = np.array([1.3])
+    M = oracle.Model(w)
+    M.init(-20.0)
+    M.run(0, 200)
+    c = 1e-3 * 1.3 / 0.025
+    assert abs(M.v[0] - (-70.0 + 50.0 * (c / (c + 2e-3)) ** 200)) < 1e-12
+
+
+def test_spike_count_equals_brute_force_crossings(oracle):
+    w = W.make_tiny(9, kinds=("pas", "hh", "syn"), n_nodes=24, syn_per_node=6.0, vmode="isolated",
+                    event_rate_hz=300.0, shuffle=False)
+    w.area[:] = 100.0
+    w.slots[-1].params["weight"][:] *= 8.0
+    M = oracle.Model(w)
+    M.init()
+    R = oracle.Model(w)
+    R.init()
+    crossings = np.zeros(w.n_nodes, dtype=np.int64)
+    for k in range(800):
+        R.events(k)
+        R.cur()
+        v_old = R.v.copy()
+        R.visolated()
+        R.state()
+        crossings += (v_old < -20.0) & (R.v >= -20.0)
+    M.run(0, 800)
+    assert crossings.sum() > 0
+    assert np.array_equal(M.spikes, crossings)
+    assert np.array_equal(M.v, R.v)
+
+
+def test_clamp_waveform(oracle):
+    w = W.make_tiny(4, kinds=("pas",), n_nodes=10)
+    M = oracle.Model(w)
+    t = 3.725
+    M.vclamp(t)
+    ref = w.clamp_off + w.clamp_amp * np.sin(2 * np.pi * w.clamp_freq * t / 1000 + w.clamp_phase)
+    assert np.allclose(M.v, ref, rtol=0, atol=1e-12)
