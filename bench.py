@@ -1,0 +1,190 @@
+"""Throughput of the mechanism path (nrn_cur + nrn_state + voltage provision)
+on one MI355X, in mechanism-instance updates per second.
+
+A step is one timestep of every instance of the workload: synapse events,
+current update with finite-difference conductance and node reduction,
+voltage provision, cnexp state update.  Default workload: 30 M isolated
+compartments carrying 40 M hh, 30 M pas, 10 M Ca-HVA + calcium pool and
+20 M AMPA/NMDA synapses (about 7.5 GB of algorithmic HBM traffic per FP64
+step).  Three variants run on the same inputs: FP64 plain (per-type,
+per-phase launches), FP64 batched (one fused launch per step, HIP graphs,
+autotuned shape) and FP32-mixed batched.  The headline value is FP64 batched.
+
+Prints progress on stderr and one JSON line on stdout.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per instance per step (index, STATEs read + written,
+# PARAMETERs read, ASSIGNED ica read + written) and per node per step (v
+# read + written, rhs and d written, area, cm), for the fused step.
+BYTES_PER_INSTANCE = {
+    "fp64": {"pas": 4 + 8 + 8, "hh": 4 + 48 + 24 + 8, "ih": 4 + 16 + 8, "cahva": 4 + 48 + 8 + 16, "syn": 4 + 64},
+    "fp32": {"pas": 4 + 4 + 8, "hh": 4 + 24 + 12 + 8, "ih": 4 + 8 + 4, "cahva": 4 + 24 + 4 + 8, "syn": 4 + 32},
+}
+
+
+def node_bytes(w) -> int:
+    b = 8 + 8 + 8 + 8            # v read, v written, rhs written, d written
+    if w.area is not None and any(s.kind == "syn" for s in w.slots):
+        b += 8
+    if w.vmode == "isolated":
+        b += 8                   # cm
+    if w.vmode == "clamp":
+        b += 32                  # clamp waveform (off, amp, freq, phase)
+    return b
+
+
+def alg_bytes_per_step(w, prec: str) -> int:
+    tot = w.n_nodes * node_bytes(w)
+    for s in w.slots:
+        tot += s.n * BYTES_PER_INSTANCE[prec][s.kind]
+    return tot
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def time_variant(w, prec, path, steps, warmup, autotune, torch, mech):
+    t0 = time.perf_counter()
+    m = mech.from_workload(w, prec)
+    torch.cuda.synchronize()
+    log(f"{prec}-{path}: context ready in {time.perf_counter() - t0:.1f}s ({m.nbytes / 1e9:.2f} GB)")
+    tuned = None
+    if path == "batched" and autotune:
+        ms = m.autotune(w.dt, w.vmode, nsteps=5, reps=3)
+        tuned = {"launch": m.get_launch(), "ms_per_step": ms}
+        log(f"{prec}-{path}: autotuned {tuned}")
+    m.step(warmup, 0, w.dt, w.vmode, path)
+    m.sync()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    stream = m.stream
+    torch.cuda.synchronize()
+    e0.record(stream)
+    m.step(steps, warmup, w.dt, w.vmode, path)
+    e1.record(stream)
+    e1.synchronize()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    m.sync()
+    spikes = int(m.spike_counts().sum()) if w.vmode == "isolated" else None
+    info = m.info()
+    m.close()
+    del m
+    torch.cuda.empty_cache()
+    ms_step = ms / steps
+    ups = w.n_instances / (ms_step * 1e-3)
+    gbs = alg_bytes_per_step(w, prec) / (ms_step * 1e-3) / 1e9
+    log(f"{prec}-{path}: {ms_step:.4f} ms/step, {ups:.4g} updates/s, {gbs:.0f} GB/s algorithmic")
+    return {"ms_per_step": ms_step, "updates_per_s": ups, "alg_GBps": gbs,
+            "alg_bytes_per_step": alg_bytes_per_step(w, prec), "tuned": tuned, "spikes": spikes,
+            "tiles": info["n_tiles"]}
+
+
+def cpu_baseline(w, target_s: float, nodes: int):
+    """The oracle (single thread) on a node sample of the same workload."""
+    import numpy as np
+    from oracle import oracle as O
+    from paper_1905_02241_amd import workloads as W
+    rng = np.random.default_rng(7)
+    sub, _ = W.subset(w, rng.choice(w.n_nodes, size=min(nodes, w.n_nodes), replace=False))
+    M = O.Model(sub)
+    M.init()
+    t = time.perf_counter()
+    M.run(0, 20)
+    per = (time.perf_counter() - t) / 20
+    steps = int(max(20, min(5000, target_s / max(per, 1e-9))))
+    t = time.perf_counter()
+    M.run(20, steps)
+    dt = time.perf_counter() - t
+    return {"value": sub.n_instances * steps / dt, "unit": "instance-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sub.n_nodes} nodes ({sub.n_instances} instances) of the same workload, {steps} steps, "
+                      f"single-threaded FP64 C, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--config", type=int, default=5)
+    ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--variants", default="fp64-plain,fp64-batched,fp32-batched")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-nodes", type=int, default=20000)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the mechanism path has no "
+              "multi-GPU mode in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1905_02241_amd import mech, workloads as W
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    mech.load_library()
+    torch.cuda.set_device(0)
+
+    t0 = time.perf_counter()
+    w = W.make_config(args.config, scale=args.scale)
+    log(f"workload {w.name}: {w.n_nodes} nodes, {w.instance_counts()}, built in {time.perf_counter() - t0:.1f}s")
+
+    res = {}
+    for v in args.variants.split(","):
+        prec, path = v.split("-")
+        res[v] = time_variant(w, prec, path, args.steps, args.warmup, not args.no_autotune, torch, mech)
+
+    head_key = "fp64-batched" if "fp64-batched" in res else next(iter(res))
+    head = res[head_key]
+    prec = head_key.split("-")[0]
+    achieved = head["alg_GBps"]
+    out = {
+        "metric": "mechanism-instance updates/s (cur+state) + % HBM peak, FP64 plain vs FP32 batched",
+        "value": head["updates_per_s"],
+        "unit": "instance-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_nodes": w.n_nodes, "instances": w.instance_counts(),
+                   "dt_ms": w.dt, "vmode": w.vmode, "path": head_key, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_fused (state+cur, isolated)",
+                     "alg_bytes_per_launch": head["alg_bytes_per_step"]},
+        "variants": res,
+    }
+    if "fp32-batched" in res and "fp64-plain" in res:
+        out["fp32_batched_over_fp64_plain"] = res["fp32-batched"]["updates_per_s"] / res["fp64-plain"]["updates_per_s"]
+    if "fp64-batched" in res and "fp64-plain" in res:
+        out["fp64_batched_over_fp64_plain"] = res["fp64-batched"]["updates_per_s"] / res["fp64-plain"]["updates_per_s"]
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, args.cpu_nodes)
+        log(f"cpu baseline {out['cpu_baseline']['value']:.4g} updates/s")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

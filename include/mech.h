@@ -1,0 +1,205 @@
+/*
+ * mech.h -- C ABI of the MI355X mechanism-kernel library (libmech.so).
+ *
+ * The library advances the membrane mechanisms of a compartmental neuron
+ * model by one or many fixed timesteps on one GPU.  Its two kernels are the
+ * ones the paper's NMODL compiler generates and accelerates (section 1 and
+ * section 8, "current update" and "state update"):
+ *
+ *   nrn_cur   (mech_cur)   -- BREAKPOINT block (section 3): gather the node
+ *             voltage v through each instance's node index, evaluate the
+ *             channel or synapse current i(v) with every STATE frozen, its
+ *             conductance g = (i(v+dv) - i(v))/dv by finite difference (the
+ *             default run-time approximation named in section 5.2), and
+ *             reduce rhs[node] -= s*i, d[node] += s*g;
+ *   nrn_state (mech_state) -- DERIVATIVE + SOLVE ... METHOD cnexp (sections 3
+ *             and 5.2): every gating or decay STATE x' = (x_inf - x)/tau is
+ *             advanced by its analytic solution with coefficients held
+ *             constant over the step.
+ *
+ * Mechanism types (section 3: SUFFIX = density mechanism, POINT_PROCESS =
+ * synapse; RANGE / PARAMETER / ASSIGNED / STATE variables):
+ *   MECH_PAS    density, i = g (v - e)                      params g, e
+ *   MECH_HH     density, Hodgkin-Huxley Na/K/leak           params gnabar, gkbar, gl, el
+ *                                                           states m, h, n
+ *   MECH_IH     density, one hyperpolarisation-activated gate, i = gbar m (v - eh)
+ *                                                           params gbar; states m
+ *   MECH_CAHVA  density, m^2 h calcium current with Nernst eca and a
+ *               submembrane calcium pool (cai relaxes to cai0 with tau_ca)
+ *                                                           params gbar; states m, h, cai
+ *   MECH_SYN    point process, double-exponential AMPA + NMDA conductance
+ *               with Mg block; a NET_RECEIVE-style event of weight w adds w*f
+ *               to both rise (A) and decay (B) states of each receptor
+ *                                                           params weight (nS)
+ *                                                           states A_ampa, B_ampa, A_nmda, B_nmda
+ *
+ * Units: mV, ms, mA/cm2 and S/cm2 for density mechanisms, nA and uS for the
+ * synapse (scaled by 100/area into the node vectors), um2, uF/cm2, mM, degC,
+ * Hz; synaptic weights and states in nS.
+ *
+ * Precision (MECH_FP64 / MECH_FP32_MIXED): FP64 keeps every variable in
+ * double, as the paper's generated code does (section 4.3).  FP32_MIXED
+ * stores STATEs and conductance PARAMETERs in float and computes rates and
+ * the state update in float with the hardware exponential; v, the reversal
+ * potentials, the driving force, the Nernst potential, the Mg block, the
+ * finite difference and the rhs/d reduction stay in double.
+ *
+ * Memory ownership: the caller allocates one device buffer of
+ * mech_required_bytes() bytes and passes it to mech_alloc(); the library
+ * carves every instance array out of it and never frees it.  Node vectors
+ * (v, rhs, d, area, cm, clamp waveform) are caller-owned device arrays bound
+ * by pointer.  Host arrays passed to mech_set_* are copied before return.
+ * The library may reorder instances internally (sorted by node); every host
+ * array in or out is in the caller's instance order.
+ *
+ * Streams: all device work is enqueued on the stream given to mech_alloc
+ * and is asynchronous, except mech_get_state, mech_set_state,
+ * mech_set_params, mech_spike_counts, mech_sync and mech_autotune, which
+ * return after the stream has drained.
+ *
+ * Errors: every call returns MECH_OK (0) or a negative MECH_ERR_* code and
+ * records a message for mech_last_error().  No call aborts and no C++
+ * exception crosses this interface.  A context is not thread safe; distinct
+ * contexts are independent.
+ */
+#ifndef MECH_H
+#define MECH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MECH_OK = 0,
+    MECH_ERR_INVAL = -1,       /* null pointer, bad kind / name / size / mode   */
+    MECH_ERR_RANGE = -2,       /* node index outside [0, n_nodes)               */
+    MECH_ERR_NOMEM = -3,       /* device buffer smaller than required           */
+    MECH_ERR_STATE = -4,       /* call order (e.g. a step before mech_bind_nodes) */
+    MECH_ERR_HIP = -5,         /* HIP runtime error, message in mech_last_error */
+    MECH_ERR_NONFINITE = -6    /* a kernel produced a non-finite STATE          */
+};
+
+enum { MECH_PAS = 0, MECH_HH = 1, MECH_IH = 2, MECH_CAHVA = 3, MECH_SYN = 4 };
+enum { MECH_FP64 = 0, MECH_FP32_MIXED = 1 };
+/* voltage provision between the current and the state update of a step
+ * (section 8, Table 3 "Other"):
+ *   EXTERNAL  v is left as bound (the caller owns it);
+ *   CLAMP     v[n] = off[n] + amp[n] sin(2 pi freq[n] t 1e-3 + phase[n]),
+ *             t in ms, freq in Hz;
+ *   ISOLATED  every node is an isolated compartment advanced by backward
+ *             Euler, v += rhs/(1e-3 cm/dt + d), and an upward crossing of
+ *             vthresh increments the node's spike count.                    */
+enum { MECH_V_EXTERNAL = 0, MECH_V_CLAMP = 1, MECH_V_ISOLATED = 2 };
+/* PLAIN: per step, one launch per mechanism type for the current update,
+ *        one for the voltage, one per type for the state update, issued
+ *        eagerly (the paper's per-mechanism kernel structure);
+ * BATCHED: per step one fused launch over a table of node tiles that runs
+ *        state(k-1), events(k) and cur(k) of every type and provides the
+ *        next voltage, with chunks of steps replayed from a HIP graph.      */
+enum { MECH_PATH_PLAIN = 0, MECH_PATH_BATCHED = 1 };
+
+typedef struct mech_ctx mech_ctx;
+
+/* One mechanism type and its instances.  node_index (host, int32, count
+ * entries, values in [0, n_nodes)) gives each instance's node; several
+ * instances may share a node and the order is free.                       */
+typedef struct {
+    int32_t kind;
+    int64_t count;
+    const int32_t *node_index;
+} mech_type_desc;
+
+/* Bytes of the device buffer mech_alloc needs for these types (256-byte
+ * aligned arrays, each padded to a multiple of 64 instances).             */
+int mech_required_bytes(int64_t n_nodes, const mech_type_desc *types, int n_types, int prec,
+                        size_t *out_bytes);
+
+/* Create a context.  Validates every node index on the host (MECH_ERR_RANGE),
+ * sorts instances by node (stable), carves the device buffer `dev_buf` of
+ * `dev_bytes` bytes (MECH_ERR_NOMEM if short), uploads the index arrays and
+ * the tile table, and sets every parameter to its default and every global
+ * to its default.  `hip_stream` is a hipStream_t (NULL: the null stream).
+ * At most 8 types; each count < 2^31.                                     */
+int mech_alloc(mech_ctx **out, int64_t n_nodes, const mech_type_desc *types, int n_types, int prec,
+               void *dev_buf, size_t dev_bytes, void *hip_stream);
+
+/* Bind caller-owned device node vectors (double, n_nodes each).  v, rhs, d
+ * are required; area is required if a MECH_SYN type exists; cm is required
+ * for MECH_V_ISOLATED (may be NULL otherwise).                             */
+int mech_bind_nodes(mech_ctx *ctx, double *v, double *rhs, double *d, const double *area,
+                    const double *cm);
+
+/* Bind the clamp waveform (device, double, n_nodes each) for MECH_V_CLAMP. */
+int mech_bind_clamp(mech_ctx *ctx, const double *off, const double *amp, const double *freq_hz,
+                    const double *phase);
+
+/* Set the RANGE parameter `name` of type slot `type_slot` from host memory:
+ * n == 1 broadcasts one value, n == count gives one value per instance in the
+ * caller's order.  Names: pas g,e; hh gnabar,gkbar,gl,el; ih gbar;
+ * cahva gbar; syn weight.                                                  */
+int mech_set_params(mech_ctx *ctx, int type_slot, const char *name, const double *host_vals, int64_t n);
+
+/* Set a global: celsius, ena, ek, eh, cao, cai0, tau_ca, ca_gamma, ca_depth,
+ * e_syn, mg, tau_r_ampa, tau_d_ampa, tau_r_nmda, tau_d_nmda, event_rate_hz,
+ * event_seed (an integer below 2^53), vthresh, fd_dv.                      */
+int mech_set_global(mech_ctx *ctx, const char *name, double value);
+
+/* INITIAL (section 3): every gate at its steady state x_inf(v) at the bound
+ * v, synapse states 0, cai = cai0; spike counts 0.                         */
+int mech_init(mech_ctx *ctx);
+
+/* Current update of step k (t = k*dt): synapse events of step k, then
+ * rhs[n] = -sum s*i, d[n] = sum s*g over every instance at node n
+ * (accumulate != 0 adds to the existing rhs/d instead of overwriting).    */
+int mech_cur(mech_ctx *ctx, int64_t k, double dt, int accumulate);
+
+/* State update over one step of length dt at the bound v.                 */
+int mech_state(mech_ctx *ctx, double dt);
+
+/* Steps k0 .. k0+nsteps-1, each: events(k), cur at v_k, voltage provision
+ * (vmode) to v_{k+1}, state at v_{k+1}.  In MECH_V_CLAMP mode v is set to
+ * the clamp value at t_{k0} first.  On return (asynchronously) v holds
+ * v_{k0+nsteps}, rhs/d hold the last step's current update and every STATE
+ * is at t_{k0+nsteps}.                                                     */
+int mech_step(mech_ctx *ctx, int64_t nsteps, int64_t k0, double dt, int vmode, int path);
+
+/* Launch shape of the BATCHED path: threads per block (64..1024, multiple
+ * of 64), tile work budget in instances (>= block), node span per tile
+ * (64..4096) and blocks per CU of a persistent grid (0: one block per
+ * tile).  Rebuilds the tile table.                                         */
+int mech_set_launch(mech_ctx *ctx, int block, int tile_instances, int tile_nodes, int blocks_per_cu);
+int mech_get_launch(const mech_ctx *ctx, int *block, int *tile_instances, int *tile_nodes,
+                    int *blocks_per_cu);
+
+/* Time every candidate launch shape of the BATCHED path on `nsteps` steps
+ * (HIP events, median of `reps`), keep the fastest, and return its ms per
+ * step.  STATEs, v, rhs, d and spike counts are saved before and restored
+ * after, so the call has no visible effect besides the chosen shape.      */
+int mech_autotune(mech_ctx *ctx, double dt, int vmode, int nsteps, int reps, double *best_ms_per_step);
+
+/* Copy STATE `name` (or "ica" for Ca-HVA) of type slot `type_slot` to /
+ * from host doubles in the caller's instance order; n must equal count.   */
+int mech_get_state(mech_ctx *ctx, int type_slot, const char *name, double *host_out, int64_t n);
+int mech_set_state(mech_ctx *ctx, int type_slot, const char *name, const double *host_in, int64_t n);
+
+/* Spike counts per node (ISOLATED mode) to host int32[n_nodes].            */
+int mech_spike_counts(mech_ctx *ctx, int32_t *host_out, int64_t n_nodes);
+
+/* Drain the stream and report asynchronous errors (MECH_ERR_NONFINITE when
+ * a kernel stored a non-finite STATE since the last call; the flag clears). */
+int mech_sync(mech_ctx *ctx);
+
+/* Number of tiles of the BATCHED path and the instance count of slot s.   */
+int mech_info(const mech_ctx *ctx, int64_t *n_tiles, int64_t *max_tile_nodes);
+
+const char *mech_last_error(const mech_ctx *ctx);
+const char *mech_strerror(int code);
+void mech_free(mech_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,98 @@
+// mech_internal.h -- structures shared by the host runtime and the kernels of
+// libmech.so.  Not part of the public interface (include/mech.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mech {
+
+constexpr int kMaxSlots = 8;
+constexpr int kMaxStates = 4;
+constexpr int kMaxParams = 4;
+constexpr int kPad = 64;             // instances per padding unit (one wave)
+constexpr int kAlign = 256;          // byte alignment of every carved array
+constexpr int kMinTileBudget = 64;   // smallest tile work budget (instances)
+constexpr int kMinTileNodes = 64;
+constexpr int kMaxTileNodes = 2048;  // LDS: 32 B per node -> 64 KiB per block
+
+// Step-phase flags of the fused kernel.
+enum : int { kDoState = 1, kDoCur = 2 };
+
+// One mechanism type as the kernels see it (internal, node-sorted order).
+// Storage types: S = state type (double or float); conductance PARAMETERs
+// are S as well; reversal potentials, weights and node data are double.
+struct SlotDev {
+    int kind;
+    int n;                     // instances
+    int identity;              // node_index[i] == i for all i and n == n_nodes
+    const int *ni;             // node index per instance
+    const int *gid;            // synapse event-stream id (nullptr: instance index)
+    void *st[kMaxStates];      // STATE arrays
+    const void *par[kMaxParams];
+    void *ica;                 // Ca-HVA current (S)
+};
+
+// Globals with every dt-dependent constant precomputed on the host in FP64.
+struct GlobDev {
+    double q10;                // hh temperature factor 3^((celsius-6.3)/10)
+    double ena, ek, eh;
+    double cao, cai0;
+    double nernst;             // 1e3 R T / (2 F), mV
+    double kt_ca;              // kappa * tau_ca
+    double e_syn, mg;
+    double mg_fd;              // exp(-0.062 fd_dv)
+    double fd_dv, vthresh;
+    double fa, fn;             // synapse peak-normalisation factors
+    double dt;
+    double decay[4];           // exp(-dt/tau) of A_ampa, B_ampa, A_nmda, B_nmda
+    double omdecay[4];         // 1 - decay, from expm1
+    double ca_decay, ca_omdecay;
+    uint64_t seed, threshold;  // event draws: fire when H(seed, gid, k) < threshold
+};
+
+struct NodesDev {
+    double *v, *rhs, *d;
+    const double *area, *cm;
+    const double *c_off, *c_amp, *c_freq, *c_phase;
+    int *spikes;
+    int n_nodes;
+};
+
+struct FusedArgs {
+    SlotDev slot[kMaxSlots];
+    int n_slots;
+    int has_syn;
+    const int *tiles;          // (n_tiles + 1) rows of (1 + n_slots) ints
+    int n_tiles;
+    int row;                   // 1 + n_slots
+    const long long *kdev;     // step counter in device memory
+    int kofs;                  // k = *kdev + kofs
+    int *err;
+    GlobDev g;
+    NodesDev nd;
+};
+
+struct PlainArgs {
+    SlotDev slot;
+    long long k;
+    int accumulate;            // unused by the state kernel
+    int *err;
+    GlobDev g;
+    NodesDev nd;
+};
+
+// Launchers (defined in mech_kernels.hip).  All return hipGetLastError().
+hipError_t launch_fill(double *a, double *b, int n, hipStream_t s);
+hipError_t launch_fill_int(int *a, int n, hipStream_t s);
+hipError_t launch_set_k(long long *kdev, long long value, hipStream_t s);
+hipError_t launch_bump_k(long long *kdev, long long by, hipStream_t s);
+hipError_t launch_vclamp(const NodesDev &nd, double t, hipStream_t s);
+hipError_t launch_visolated(const NodesDev &nd, const GlobDev &g, hipStream_t s);
+hipError_t launch_init(bool fp32, const PlainArgs &a, hipStream_t s);
+hipError_t launch_plain_cur(bool fp32, const PlainArgs &a, hipStream_t s);
+hipError_t launch_plain_state(bool fp32, const PlainArgs &a, hipStream_t s);
+hipError_t launch_fused(bool fp32, int phases, int vmode, const FusedArgs &a, int grid, int block,
+                        size_t lds_bytes, hipStream_t s);
+
+}  // namespace mech

@@ -1,0 +1,598 @@
+// mech_kernels.hip -- CDNA4 (gfx950) kernels of the mechanism library.
+//
+// Current update (BREAKPOINT, paper section 3) and state update (DERIVATIVE +
+// SOLVE cnexp, sections 3 and 5.2) of five mechanism types over SoA instance
+// arrays, in two launch structures:
+//
+//   plain   one kernel per mechanism type and phase, a thread per instance,
+//           node vectors reached through the node index, many-to-one
+//           reductions by FP64 global atomics (the paper's per-mechanism
+//           kernel structure; section 8 notes the cost of its atomic
+//           reductions);
+//   fused   one kernel per timestep over a table of node tiles: each block
+//           stages its nodes' v in LDS, runs state(k-1), events(k) and cur(k)
+//           of every instance in the tile (coalesced SoA streams, a thread per
+//           instance), reduces into LDS accumulators, then writes rhs/d and
+//           provides v_{k+1} for its own nodes.  No global atomics.
+//
+// The work is elementwise and exponential/division heavy (section 6 calls the
+// state kernels compute bound and the current kernels bandwidth bound); there
+// is no dense contraction, so no MFMA.  Precision: FP64 throughout, or FP32
+// STATEs / rates / conductance products with the hardware exponential and
+// FP64 v, driving force, Nernst, Mg block, finite difference and reduction.
+#include "mech_internal.h"
+#include "mech.h"
+
+#include <math.h>
+
+namespace mech {
+
+// ------------------------------------------------------------ FP32 math --
+// e^x = 2^(x log2 e) on the hardware exp2 unit (about 1 ulp).
+__device__ __forceinline__ float fexp(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// a*x/(1 - exp(-x/k)) with its removable singularity at x = 0.  Near the
+// singular point the direct form cancels in FP32, so |u| < 0.5 (u = x/k) uses
+// the Bernoulli-number series u/(1 - e^-u) = 1 + u/2 + u^2/12 - u^4/720 +
+// u^6/30240 + O(u^8) (truncation < 4e-9 there).
+__device__ __forceinline__ float linexp_f(float a, float k, float x) {
+    const float u = x * (1.0f / k);
+    const float u2 = u * u;
+    const float ser = 1.0f + 0.5f * u + u2 * (1.0f / 12.0f + u2 * (-1.0f / 720.0f + u2 * (1.0f / 30240.0f)));
+    const float dir = u * frcp(1.0f - fexp(-u));
+    return a * k * (fabsf(u) < 0.5f ? ser : dir);
+}
+
+// 1 - e^-z for z >= 0.  The direct form loses accuracy for small z, where
+// the exponential series z(1 - z/2(1 - z/3(1 - z/4(1 - z/5(1 - z/6))))) is
+// used (truncation z^7/5040, relative < 5e-8 below 0.25).
+__device__ __forceinline__ float one_minus_exp_f(float z) {
+    const float ser = z * (1.0f - z * 0.5f * (1.0f - z * (1.0f / 3.0f) *
+                      (1.0f - z * 0.25f * (1.0f - z * 0.2f * (1.0f - z * (1.0f / 6.0f))))));
+    return z < 0.25f ? ser : 1.0f - fexp(-z);
+}
+
+// ------------------------------------------------------------ FP64 math --
+__device__ __forceinline__ double linexp_d(double a, double k, double x, double lim) {
+    return x == 0.0 ? lim : a * x / (-expm1(-x / k));
+}
+
+// ----------------------------------------------------- rates and cnexp --
+// Hodgkin-Huxley gates at v; x <- x_inf + (x - x_inf) exp(-dt q10 (a + b)).
+__device__ __forceinline__ void hh_state(double v, const GlobDev &g, double &m, double &h, double &n) {
+    const double e80 = exp((v + 65.0) * (-1.0 / 80.0));
+    const double e80_2 = e80 * e80;
+    const double am = linexp_d(0.1, 10.0, v + 40.0, 1.0);
+    const double bm = 4.0 * exp((v + 65.0) * (-1.0 / 18.0));
+    const double ah = 0.07 * (e80_2 * e80_2);                 // exp(-(v+65)/20)
+    const double bh = 1.0 / (1.0 + exp((v + 35.0) * (-0.1)));
+    const double an = linexp_d(0.01, 10.0, v + 55.0, 0.1);
+    const double bn = 0.125 * e80;
+    const double sm = am + bm, sh = ah + bh, sn = an + bn;
+    const double mi = am / sm, hi = ah / sh, nI = an / sn;
+    const double c = -g.dt * g.q10;
+    m = mi + (m - mi) * exp(c * sm);
+    h = hi + (h - hi) * exp(c * sh);
+    n = nI + (n - nI) * exp(c * sn);
+}
+
+__device__ __forceinline__ void hh_state(double vd, const GlobDev &g, float &m, float &h, float &n) {
+    const float v = (float)vd;
+    const float e80 = fexp((v + 65.0f) * (-1.0f / 80.0f));
+    const float e80_2 = e80 * e80;
+    const float am = linexp_f(0.1f, 10.0f, v + 40.0f);
+    const float bm = 4.0f * fexp((v + 65.0f) * (-1.0f / 18.0f));
+    const float ah = 0.07f * (e80_2 * e80_2);
+    const float bh = frcp(1.0f + fexp((v + 35.0f) * (-0.1f)));
+    const float an = linexp_f(0.01f, 10.0f, v + 55.0f);
+    const float bn = 0.125f * e80;
+    const float sm = am + bm, sh = ah + bh, sn = an + bn;
+    const float c = (float)(g.dt * g.q10);
+    m += (am * frcp(sm) - m) * one_minus_exp_f(c * sm);
+    h += (ah * frcp(sh) - h) * one_minus_exp_f(c * sh);
+    n += (an * frcp(sn) - n) * one_minus_exp_f(c * sn);
+}
+
+__device__ __forceinline__ void hh_inf(double v, double &m, double &h, double &n) {
+    const double am = linexp_d(0.1, 10.0, v + 40.0, 1.0);
+    const double bm = 4.0 * exp(-(v + 65.0) / 18.0);
+    const double ah = 0.07 * exp(-(v + 65.0) / 20.0);
+    const double bh = 1.0 / (1.0 + exp(-(v + 35.0) / 10.0));
+    const double an = linexp_d(0.01, 10.0, v + 55.0, 0.1);
+    const double bn = 0.125 * exp(-(v + 65.0) / 80.0);
+    m = am / (am + bm);
+    h = ah / (ah + bh);
+    n = an / (an + bn);
+}
+
+// Ih: alpha = 0.005 exp(-(v+90)/20), beta = 0.005 exp((v+90)/20).
+__device__ __forceinline__ void ih_state(double v, const GlobDev &g, double &m) {
+    const double e = exp((v + 90.0) * 0.05);
+    const double a = 0.005 / e, b = 0.005 * e, s = a + b;
+    const double mi = a / s;
+    m = mi + (m - mi) * exp(-g.dt * s);
+}
+__device__ __forceinline__ void ih_state(double vd, const GlobDev &g, float &m) {
+    const float e = fexp(((float)vd + 90.0f) * 0.05f);
+    const float a = 0.005f * frcp(e), b = 0.005f * e, s = a + b;
+    m += (a * frcp(s) - m) * one_minus_exp_f((float)g.dt * s);
+}
+__device__ __forceinline__ double ih_inf(double v) {
+    const double a = 0.005 * exp(-(v + 90.0) / 20.0), b = 0.005 * exp((v + 90.0) / 20.0);
+    return a / (a + b);
+}
+
+// Ca-HVA gates: alpha_m = 0.1 (v+20)/(1 - exp(-(v+20)/5)), beta_m = 0.8
+// exp(-(v+45)/15), alpha_h = 0.0005 exp(-(v+60)/25), beta_h = 0.006/(1 +
+// exp(-(v+20)/10)); the calcium pool relaxes to cai_inf = cai0 - kappa tau
+// ica with time constant tau_ca (ica held at the value of the last current
+// update).
+__device__ __forceinline__ void ca_state(double v, const GlobDev &g, double ica, double &m, double &h,
+                                         double &cai) {
+    const double am = linexp_d(0.1, 5.0, v + 20.0, 0.5);
+    const double bm = 0.8 * exp((v + 45.0) * (-1.0 / 15.0));
+    const double ah = 0.0005 * exp((v + 60.0) * (-0.04));
+    const double bh = 0.006 / (1.0 + exp((v + 20.0) * (-0.1)));
+    const double sm = am + bm, sh = ah + bh;
+    const double mi = am / sm, hi = ah / sh;
+    m = mi + (m - mi) * exp(-g.dt * sm);
+    h = hi + (h - hi) * exp(-g.dt * sh);
+    const double ci = g.cai0 - g.kt_ca * ica;
+    cai = ci + (cai - ci) * g.ca_decay;
+}
+__device__ __forceinline__ void ca_state(double vd, const GlobDev &g, float ica, float &m, float &h,
+                                         float &cai) {
+    const float v = (float)vd;
+    const float am = linexp_f(0.1f, 5.0f, v + 20.0f);
+    const float bm = 0.8f * fexp((v + 45.0f) * (-1.0f / 15.0f));
+    const float ah = 0.0005f * fexp((v + 60.0f) * (-0.04f));
+    const float bh = 0.006f * frcp(1.0f + fexp((v + 20.0f) * (-0.1f)));
+    const float sm = am + bm, sh = ah + bh;
+    const float dt = (float)g.dt;
+    m += (am * frcp(sm) - m) * one_minus_exp_f(dt * sm);
+    h += (ah * frcp(sh) - h) * one_minus_exp_f(dt * sh);
+    const float ci = (float)g.cai0 - (float)g.kt_ca * ica;
+    cai += (ci - cai) * (float)g.ca_omdecay;
+}
+__device__ __forceinline__ void ca_inf(double v, double &m, double &h) {
+    const double am = linexp_d(0.1, 5.0, v + 20.0, 0.5);
+    const double bm = 0.8 * exp(-(v + 45.0) / 15.0);
+    const double ah = 0.0005 * exp(-(v + 60.0) / 25.0);
+    const double bh = 0.006 / (1.0 + exp(-(v + 20.0) / 10.0));
+    m = am / (am + bm);
+    h = ah / (ah + bh);
+}
+
+// Synapse decay: A <- A e^{-dt/tau}; in FP32 A <- A - A (1 - e^{-dt/tau}),
+// which keeps the rounding of the factor from being amplified by tau/dt.
+__device__ __forceinline__ void syn_decay(double *x, const GlobDev &g) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) x[j] *= g.decay[j];
+}
+__device__ __forceinline__ void syn_decay(float *x, const GlobDev &g) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) x[j] -= x[j] * (float)g.omdecay[j];
+}
+
+// ------------------------------------------------------------- events --
+// SplitMix64 (Steele, Lea & Flood 2014): output n of the generator seeded
+// with `seed` is mix(seed + n * golden_gamma); the draw of event stream gid
+// at step k is output gid * 2^32 + k + 1.
+__device__ __forceinline__ unsigned long long splitmix(unsigned long long seed, unsigned long long gid,
+                                                       unsigned long long k) {
+    unsigned long long z = seed + ((gid << 32) + k + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// ------------------------------------------------------------ currents --
+// Each returns i(v) and the finite-difference conductance (i(v+dv) - i(v))/dv
+// with STATEs frozen.  Conductance products are formed in the storage type;
+// the driving force and everything after it in FP64.
+template <class S>
+__device__ __forceinline__ void hh_cur(double v, S m, S h, S n, S gnabar, S gkbar, S gl, double el,
+                                       const GlobDev &g, double &i0, double &gg) {
+    const double gna = (double)(gnabar * m * m * m * h);
+    const double gk = (double)(gkbar * n * n * n * n);
+    const double gll = (double)gl;
+    i0 = gna * (v - g.ena) + gk * (v - g.ek) + gll * (v - el);
+    const double vd = v + g.fd_dv;
+    const double i1 = gna * (vd - g.ena) + gk * (vd - g.ek) + gll * (vd - el);
+    gg = (i1 - i0) / g.fd_dv;
+}
+
+template <class S>
+__device__ __forceinline__ void lin_cur(double v, S gbar_x, double e, const GlobDev &g, double &i0,
+                                        double &gg) {
+    const double gc = (double)gbar_x;
+    i0 = gc * (v - e);
+    const double i1 = gc * (v + g.fd_dv - e);
+    gg = (i1 - i0) / g.fd_dv;
+}
+
+// Calcium current with the Nernst potential eca = RT/(2F) ln(cao/cai).
+template <class S>
+__device__ __forceinline__ double ca_cur(double v, S m, S h, S cai, S gbar, const GlobDev &g, double &i0,
+                                         double &gg) {
+    const double eca = g.nernst * log(g.cao / (double)cai);
+    const double gc = (double)(gbar * m * m * h);
+    i0 = gc * (v - eca);
+    const double i1 = gc * (v + g.fd_dv - eca);
+    gg = (i1 - i0) / g.fd_dv;
+    return i0;
+}
+
+// AMPA + NMDA with Mg block B(v) = 1/(1 + exp(-0.062 v) mg/3.57); nS*mV =
+// pA, 1e-3 gives nA.  B(v+dv) reuses exp(-0.062 v) times exp(-0.062 dv).
+template <class S>
+__device__ __forceinline__ void syn_cur(double v, const S *x, const GlobDev &g, double &i0, double &gg) {
+    const double ga = (double)(x[1] - x[0]);
+    const double gn = (double)(x[3] - x[2]);
+    const double ex = exp(-0.062 * v);
+    const double b0 = 1.0 / (1.0 + ex * g.mg / 3.57);
+    const double b1 = 1.0 / (1.0 + ex * g.mg_fd * g.mg / 3.57);
+    const double vd = v + g.fd_dv;
+    i0 = 1e-3 * (ga + gn * b0) * (v - g.e_syn);
+    const double i1 = 1e-3 * (ga + gn * b1) * (vd - g.e_syn);
+    gg = (i1 - i0) / g.fd_dv;
+}
+
+template <class S> __device__ __forceinline__ int bad(S x) { return isfinite(x) ? 0 : 1; }
+
+// -------------------------------------------------- instance update ----
+// One instance of a slot: state update (if PH has kDoState) at v, events and
+// current (if kDoCur) at the same v.  Returns the current and conductance
+// contributions for the node and stores the new STATEs.
+template <class S, int KIND, int PH>
+__device__ __forceinline__ void instance(const SlotDev &sl, int i, double v, const GlobDev &g, long long k,
+                                         double &ci, double &cg, int &flag) {
+    ci = 0.0;
+    cg = 0.0;
+    if constexpr (KIND == MECH_PAS) {
+        if (PH & kDoCur) {
+            const S gp = ((const S *)sl.par[0])[i];
+            const double e = ((const double *)sl.par[1])[i];
+            lin_cur<S>(v, gp, e, g, ci, cg);
+        }
+    } else if constexpr (KIND == MECH_HH) {
+        S *M = (S *)sl.st[0], *H = (S *)sl.st[1], *N = (S *)sl.st[2];
+        S m = M[i], h = H[i], n = N[i];
+        if (PH & kDoState) {
+            hh_state(v, g, m, h, n);
+            flag |= bad(m) | bad(h) | bad(n);
+            M[i] = m; H[i] = h; N[i] = n;
+        }
+        if (PH & kDoCur) {
+            const S gnabar = ((const S *)sl.par[0])[i];
+            const S gkbar = ((const S *)sl.par[1])[i];
+            const S gl = ((const S *)sl.par[2])[i];
+            const double el = ((const double *)sl.par[3])[i];
+            hh_cur<S>(v, m, h, n, gnabar, gkbar, gl, el, g, ci, cg);
+        }
+    } else if constexpr (KIND == MECH_IH) {
+        S *M = (S *)sl.st[0];
+        S m = M[i];
+        if (PH & kDoState) {
+            ih_state(v, g, m);
+            flag |= bad(m);
+            M[i] = m;
+        }
+        if (PH & kDoCur) {
+            const S gbar = ((const S *)sl.par[0])[i];
+            lin_cur<S>(v, (S)(gbar * m), g.eh, g, ci, cg);
+        }
+    } else if constexpr (KIND == MECH_CAHVA) {
+        S *M = (S *)sl.st[0], *H = (S *)sl.st[1], *CAI = (S *)sl.st[2], *ICA = (S *)sl.ica;
+        S m = M[i], h = H[i], cai = CAI[i];
+        if (PH & kDoState) {
+            ca_state(v, g, ICA[i], m, h, cai);
+            flag |= bad(m) | bad(h) | bad(cai);
+            M[i] = m; H[i] = h; CAI[i] = cai;
+        }
+        if (PH & kDoCur) {
+            const S gbar = ((const S *)sl.par[0])[i];
+            ICA[i] = (S)ca_cur<S>(v, m, h, cai, gbar, g, ci, cg);
+        }
+    } else if constexpr (KIND == MECH_SYN) {
+        S x[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[j] = ((S *)sl.st[j])[i];
+        if (PH & kDoState) syn_decay(x, g);
+        if (PH & kDoCur) {
+            const unsigned long long id = sl.gid ? (unsigned long long)(long long)sl.gid[i]
+                                                 : (unsigned long long)i;
+            if (splitmix(g.seed, id, (unsigned long long)k) < g.threshold) {
+                const double w = ((const double *)sl.par[0])[i];
+                x[0] += (S)(w * g.fa);
+                x[1] += (S)(w * g.fa);
+                x[2] += (S)(w * g.fn);
+                x[3] += (S)(w * g.fn);
+            }
+            syn_cur<S>(v, x, g, ci, cg);
+        }
+        flag |= bad(x[0]) | bad(x[1]) | bad(x[2]) | bad(x[3]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) ((S *)sl.st[j])[i] = x[j];
+    }
+}
+
+// ---------------------------------------------------------- plain path --
+template <class S, int KIND>
+__global__ __launch_bounds__(256) void k_plain_cur(PlainArgs a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int flag = 0;
+    if (i < a.slot.n) {
+        const int ni = a.slot.ni[i];
+        const double v = a.nd.v[ni];
+        double ci, cg;
+        instance<S, KIND, kDoCur>(a.slot, i, v, a.g, a.k, ci, cg, flag);
+        if (KIND == MECH_SYN) {
+            const double sc = 1e2 / a.nd.area[ni];
+            ci *= sc;
+            cg *= sc;
+        }
+        if (a.slot.identity) {
+            a.nd.rhs[ni] -= ci;
+            a.nd.d[ni] += cg;
+        } else {
+            unsafeAtomicAdd(&a.nd.rhs[ni], -ci);
+            unsafeAtomicAdd(&a.nd.d[ni], cg);
+        }
+    }
+    if (flag) atomicOr(a.err, 1);
+}
+
+template <class S, int KIND>
+__global__ __launch_bounds__(256) void k_plain_state(PlainArgs a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int flag = 0;
+    if (i < a.slot.n) {
+        const double v = a.nd.v[a.slot.ni[i]];
+        double ci, cg;
+        instance<S, KIND, kDoState>(a.slot, i, v, a.g, a.k, ci, cg, flag);
+    }
+    if (flag) atomicOr(a.err, 1);
+}
+
+// INITIAL: gates at steady state at the bound v (computed in FP64 for both
+// storage types), synapse states 0, cai = cai0, ica = 0.
+template <class S, int KIND>
+__global__ __launch_bounds__(256) void k_init(PlainArgs a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.slot.n) return;
+    const double v = a.nd.v[a.slot.ni[i]];
+    S **st = (S **)a.slot.st;
+    if constexpr (KIND == MECH_HH) {
+        double m, h, n;
+        hh_inf(v, m, h, n);
+        st[0][i] = (S)m; st[1][i] = (S)h; st[2][i] = (S)n;
+    } else if constexpr (KIND == MECH_IH) {
+        st[0][i] = (S)ih_inf(v);
+    } else if constexpr (KIND == MECH_CAHVA) {
+        double m, h;
+        ca_inf(v, m, h);
+        st[0][i] = (S)m; st[1][i] = (S)h; st[2][i] = (S)a.g.cai0;
+        ((S *)a.slot.ica)[i] = (S)0;
+    } else if constexpr (KIND == MECH_SYN) {
+        for (int j = 0; j < 4; ++j) st[j][i] = (S)0;
+    }
+}
+
+__global__ void k_fill(double *a, double *b, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) { a[i] = 0.0; b[i] = 0.0; }
+}
+__global__ void k_fill_int(int *a, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = 0;
+}
+__global__ void k_set_k(long long *kdev, long long value) {
+    if (threadIdx.x == 0) *kdev = value;
+}
+__global__ void k_bump_k(long long *kdev, long long by) {
+    if (threadIdx.x == 0) *kdev += by;
+}
+
+__device__ __forceinline__ double clamp_v(const NodesDev &nd, int n, double t) {
+    return nd.c_off[n] + nd.c_amp[n] * sin(2.0 * 3.14159265358979323846 * nd.c_freq[n] * t * 1e-3 + nd.c_phase[n]);
+}
+
+__global__ void k_vclamp(NodesDev nd, double t) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n < nd.n_nodes) nd.v[n] = clamp_v(nd, n, t);
+}
+
+// Backward Euler of an isolated compartment, 1e-3 cm (v1 - v0)/dt = rhs -
+// d (v1 - v0), and an upward crossing of vthresh counts a spike.
+__device__ __forceinline__ double isolated_v(const NodesDev &nd, const GlobDev &g, int n, double v0, double r,
+                                             double dd) {
+    const double v1 = v0 + r / (1e-3 * nd.cm[n] / g.dt + dd);
+    if (v0 < g.vthresh && v1 >= g.vthresh) nd.spikes[n] += 1;
+    return v1;
+}
+
+__global__ void k_visolated(NodesDev nd, GlobDev g) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n < nd.n_nodes) nd.v[n] = isolated_v(nd, g, n, nd.v[n], nd.rhs[n], nd.d[n]);
+}
+
+// ---------------------------------------------------------- fused path --
+// LDS per tile node: v, 100/area, rhs and d accumulators (4 doubles).
+template <class S, int KIND, int PH>
+__device__ __forceinline__ void tile_slot(const SlotDev &sl, int lo, int hi, int nlo, const double *vl,
+                                          const double *sc, double *ar, double *ad, const GlobDev &g,
+                                          long long k, int &flag) {
+    for (int i = lo + (int)threadIdx.x; i < hi; i += (int)blockDim.x) {
+        const int j = sl.ni[i] - nlo;
+        double ci, cg;
+        instance<S, KIND, PH>(sl, i, vl[j], g, k, ci, cg, flag);
+        if (PH & kDoCur) {
+            if (KIND == MECH_SYN) {
+                ci *= sc[j];
+                cg *= sc[j];
+            }
+            atomicAdd(&ar[j], -ci);
+            atomicAdd(&ad[j], cg);
+        }
+    }
+}
+
+template <class S, int PH, int VM>
+__global__ __launch_bounds__(1024) void k_fused(FusedArgs a, int tn) {
+    extern __shared__ double lds[];
+    double *vl = lds, *sc = lds + tn, *ar = lds + 2 * tn, *ad = lds + 3 * tn;
+    const long long k = *a.kdev + a.kofs;
+    int flag = 0;
+    for (int t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
+        const int *r0 = a.tiles + (size_t)t * a.row;
+        const int *r1 = r0 + a.row;
+        const int nlo = r0[0], nn = r1[0] - nlo;
+        for (int j = threadIdx.x; j < nn; j += blockDim.x) {
+            vl[j] = a.nd.v[nlo + j];
+            if (PH & kDoCur) {
+                ar[j] = 0.0;
+                ad[j] = 0.0;
+                if (a.has_syn) sc[j] = 1e2 / a.nd.area[nlo + j];
+            }
+        }
+        __syncthreads();
+        for (int s = 0; s < a.n_slots; ++s) {
+            const SlotDev &sl = a.slot[s];
+            const int lo = r0[1 + s], hi = r1[1 + s];
+            switch (sl.kind) {
+            case MECH_PAS:
+                if (PH & kDoCur) tile_slot<S, MECH_PAS, PH>(sl, lo, hi, nlo, vl, sc, ar, ad, a.g, k, flag);
+                break;
+            case MECH_HH: tile_slot<S, MECH_HH, PH>(sl, lo, hi, nlo, vl, sc, ar, ad, a.g, k, flag); break;
+            case MECH_IH: tile_slot<S, MECH_IH, PH>(sl, lo, hi, nlo, vl, sc, ar, ad, a.g, k, flag); break;
+            case MECH_CAHVA: tile_slot<S, MECH_CAHVA, PH>(sl, lo, hi, nlo, vl, sc, ar, ad, a.g, k, flag); break;
+            case MECH_SYN: tile_slot<S, MECH_SYN, PH>(sl, lo, hi, nlo, vl, sc, ar, ad, a.g, k, flag); break;
+            default: break;
+            }
+        }
+        if (PH & kDoCur) {
+            __syncthreads();
+            for (int j = threadIdx.x; j < nn; j += blockDim.x) {
+                const int n = nlo + j;
+                const double r = ar[j], dd = ad[j];
+                a.nd.rhs[n] = r;
+                a.nd.d[n] = dd;
+                if (VM == MECH_V_ISOLATED) a.nd.v[n] = isolated_v(a.nd, a.g, n, vl[j], r, dd);
+                if (VM == MECH_V_CLAMP) a.nd.v[n] = clamp_v(a.nd, n, (double)(k + 1) * a.g.dt);
+            }
+        }
+        __syncthreads();
+    }
+    if (flag) atomicOr(a.err, 1);
+}
+
+// ------------------------------------------------------------ launchers --
+static inline int blocks(int n, int b) { return (n + b - 1) / b; }
+
+hipError_t launch_fill(double *a, double *b, int n, hipStream_t s) {
+    if (n > 0) k_fill<<<blocks(n, 256), 256, 0, s>>>(a, b, n);
+    return hipGetLastError();
+}
+hipError_t launch_fill_int(int *a, int n, hipStream_t s) {
+    if (n > 0) k_fill_int<<<blocks(n, 256), 256, 0, s>>>(a, n);
+    return hipGetLastError();
+}
+hipError_t launch_set_k(long long *kdev, long long value, hipStream_t s) {
+    k_set_k<<<1, 64, 0, s>>>(kdev, value);
+    return hipGetLastError();
+}
+hipError_t launch_bump_k(long long *kdev, long long by, hipStream_t s) {
+    k_bump_k<<<1, 64, 0, s>>>(kdev, by);
+    return hipGetLastError();
+}
+hipError_t launch_vclamp(const NodesDev &nd, double t, hipStream_t s) {
+    if (nd.n_nodes > 0) k_vclamp<<<blocks(nd.n_nodes, 256), 256, 0, s>>>(nd, t);
+    return hipGetLastError();
+}
+hipError_t launch_visolated(const NodesDev &nd, const GlobDev &g, hipStream_t s) {
+    if (nd.n_nodes > 0) k_visolated<<<blocks(nd.n_nodes, 256), 256, 0, s>>>(nd, g);
+    return hipGetLastError();
+}
+
+template <class S>
+static hipError_t init_t(const PlainArgs &a, hipStream_t s) {
+    const int gr = blocks(a.slot.n, 256);
+    switch (a.slot.kind) {
+    case MECH_HH: k_init<S, MECH_HH><<<gr, 256, 0, s>>>(a); break;
+    case MECH_IH: k_init<S, MECH_IH><<<gr, 256, 0, s>>>(a); break;
+    case MECH_CAHVA: k_init<S, MECH_CAHVA><<<gr, 256, 0, s>>>(a); break;
+    case MECH_SYN: k_init<S, MECH_SYN><<<gr, 256, 0, s>>>(a); break;
+    default: break;
+    }
+    return hipGetLastError();
+}
+hipError_t launch_init(bool fp32, const PlainArgs &a, hipStream_t s) {
+    if (a.slot.n == 0) return hipSuccess;
+    return fp32 ? init_t<float>(a, s) : init_t<double>(a, s);
+}
+
+template <class S>
+static hipError_t cur_t(const PlainArgs &a, hipStream_t s) {
+    const int gr = blocks(a.slot.n, 256);
+    switch (a.slot.kind) {
+    case MECH_PAS: k_plain_cur<S, MECH_PAS><<<gr, 256, 0, s>>>(a); break;
+    case MECH_HH: k_plain_cur<S, MECH_HH><<<gr, 256, 0, s>>>(a); break;
+    case MECH_IH: k_plain_cur<S, MECH_IH><<<gr, 256, 0, s>>>(a); break;
+    case MECH_CAHVA: k_plain_cur<S, MECH_CAHVA><<<gr, 256, 0, s>>>(a); break;
+    case MECH_SYN: k_plain_cur<S, MECH_SYN><<<gr, 256, 0, s>>>(a); break;
+    default: break;
+    }
+    return hipGetLastError();
+}
+hipError_t launch_plain_cur(bool fp32, const PlainArgs &a, hipStream_t s) {
+    if (a.slot.n == 0) return hipSuccess;
+    return fp32 ? cur_t<float>(a, s) : cur_t<double>(a, s);
+}
+
+template <class S>
+static hipError_t state_t(const PlainArgs &a, hipStream_t s) {
+    const int gr = blocks(a.slot.n, 256);
+    switch (a.slot.kind) {
+    case MECH_HH: k_plain_state<S, MECH_HH><<<gr, 256, 0, s>>>(a); break;
+    case MECH_IH: k_plain_state<S, MECH_IH><<<gr, 256, 0, s>>>(a); break;
+    case MECH_CAHVA: k_plain_state<S, MECH_CAHVA><<<gr, 256, 0, s>>>(a); break;
+    case MECH_SYN: k_plain_state<S, MECH_SYN><<<gr, 256, 0, s>>>(a); break;
+    default: break;  // pas has no STATE
+    }
+    return hipGetLastError();
+}
+hipError_t launch_plain_state(bool fp32, const PlainArgs &a, hipStream_t s) {
+    if (a.slot.n == 0) return hipSuccess;
+    return fp32 ? state_t<float>(a, s) : state_t<double>(a, s);
+}
+
+template <class S, int PH>
+static hipError_t fused_vm(int vmode, const FusedArgs &a, int grid, int block, size_t lds, int tn,
+                           hipStream_t s) {
+    switch (vmode) {
+    case MECH_V_CLAMP: k_fused<S, PH, MECH_V_CLAMP><<<grid, block, lds, s>>>(a, tn); break;
+    case MECH_V_ISOLATED: k_fused<S, PH, MECH_V_ISOLATED><<<grid, block, lds, s>>>(a, tn); break;
+    default: k_fused<S, PH, MECH_V_EXTERNAL><<<grid, block, lds, s>>>(a, tn); break;
+    }
+    return hipGetLastError();
+}
+template <class S>
+static hipError_t fused_t(int phases, int vmode, const FusedArgs &a, int grid, int block, size_t lds, int tn,
+                          hipStream_t s) {
+    switch (phases) {
+    case kDoCur: return fused_vm<S, kDoCur>(vmode, a, grid, block, lds, tn, s);
+    case kDoState: k_fused<S, kDoState, MECH_V_EXTERNAL><<<grid, block, lds, s>>>(a, tn); return hipGetLastError();
+    default: return fused_vm<S, kDoCur | kDoState>(vmode, a, grid, block, lds, tn, s);
+    }
+}
+hipError_t launch_fused(bool fp32, int phases, int vmode, const FusedArgs &a, int grid, int block,
+                        size_t lds_bytes, hipStream_t s) {
+    if (a.n_tiles == 0 || grid == 0) return hipSuccess;
+    const int tn = (int)(lds_bytes / (4 * sizeof(double)));
+    return fp32 ? fused_t<float>(phases, vmode, a, grid, block, lds_bytes, tn, s)
+                : fused_t<double>(phases, vmode, a, grid, block, lds_bytes, tn, s);
+}
+
+}  // namespace mech

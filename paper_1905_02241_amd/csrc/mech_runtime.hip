@@ -1,0 +1,859 @@
+// mech_runtime.hip -- host side of libmech.so: the C ABI of include/mech.h.
+//
+// Responsibilities: argument validation, stable node sort of every mechanism
+// type, carving of the caller's device buffer into 256-byte aligned SoA
+// arrays, the tile table of the fused path, the per-step launch sequences of
+// the plain and batched paths (the latter replayed from HIP graphs), the
+// launch-shape autotuner and host copies of STATEs in the caller's order.
+#include "mech.h"
+#include "mech_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace mech;
+
+namespace {
+
+// ----------------------------------------------------------- type table --
+struct VarDesc {
+    const char *name;
+    bool is_double;  // stored as double in both precisions (else the state type)
+};
+struct KindDesc {
+    const char *name;
+    bool point_process;
+    int n_state;
+    const char *state[kMaxStates];
+    int n_param;
+    VarDesc param[kMaxParams];
+    double defaults[kMaxParams];
+};
+
+const KindDesc kKinds[5] = {
+    {"pas", false, 0, {}, 2, {{"g", false}, {"e", true}}, {1e-3, -70.0}},
+    {"hh", false, 3, {"m", "h", "n"}, 4,
+     {{"gnabar", false}, {"gkbar", false}, {"gl", false}, {"el", true}}, {0.12, 0.036, 0.0003, -54.3}},
+    {"ih", false, 1, {"m"}, 1, {{"gbar", false}}, {1e-4}},
+    {"cahva", false, 3, {"m", "h", "cai"}, 1, {{"gbar", false}}, {5e-5}},
+    {"syn", true, 4, {"A_ampa", "B_ampa", "A_nmda", "B_nmda"}, 1, {{"weight", true}}, {1.0}},
+};
+
+struct Globals {
+    double celsius = 6.3, ena = 50.0, ek = -77.0, eh = -45.0;
+    double cao = 2.0, cai0 = 5e-5, tau_ca = 80.0, ca_gamma = 0.05, ca_depth = 0.1;
+    double e_syn = 0.0, mg = 1.0;
+    double tau_r_ampa = 0.2, tau_d_ampa = 1.7, tau_r_nmda = 0.29, tau_d_nmda = 43.0;
+    double event_rate_hz = 5.0, vthresh = -20.0, fd_dv = 1e-3;
+    uint64_t event_seed = 0;
+};
+
+struct SlotHost {
+    int kind = 0;
+    int64_t n = 0, np = 0;
+    bool identity = false;
+    bool perm_identity = true;
+    std::vector<int32_t> perm;     // internal -> caller index (empty when identity)
+    std::vector<int32_t> ni;       // node index, internal (sorted) order
+    size_t off_ni = 0, off_gid = 0, off_ica = 0;
+    size_t off_st[kMaxStates] = {}, off_par[kMaxParams] = {};
+    bool has_gid = false, has_ica = false;
+};
+
+struct Layout {
+    size_t total = 0;
+    size_t inst_end = 0;           // end of the per-instance region
+    size_t off_spikes = 0, off_err = 0, off_kdev = 0, off_tiles = 0;
+    int64_t max_tile_rows = 0;
+};
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+void compute_layout(int64_t n_nodes, std::vector<SlotHost> &slots, int prec, Layout &L) {
+    const size_t ss = prec == MECH_FP32_MIXED ? 4 : 8;
+    size_t off = 0;
+    int64_t total_inst = 0;
+    for (auto &s : slots) {
+        const KindDesc &K = kKinds[s.kind];
+        s.np = (s.n + kPad - 1) / kPad * kPad;
+        total_inst += s.n;
+        s.off_ni = off; off = align_up(off + 4 * (size_t)s.np);
+        s.has_gid = K.point_process;
+        if (s.has_gid) { s.off_gid = off; off = align_up(off + 4 * (size_t)s.np); }
+        for (int j = 0; j < K.n_state; ++j) { s.off_st[j] = off; off = align_up(off + ss * (size_t)s.np); }
+        for (int j = 0; j < K.n_param; ++j) {
+            s.off_par[j] = off;
+            off = align_up(off + (K.param[j].is_double ? 8 : ss) * (size_t)s.np);
+        }
+        s.has_ica = s.kind == MECH_CAHVA;
+        if (s.has_ica) { s.off_ica = off; off = align_up(off + ss * (size_t)s.np); }
+    }
+    L.inst_end = off;
+    L.off_spikes = off; off = align_up(off + 4 * (size_t)std::max<int64_t>(n_nodes, 1));
+    L.off_err = off; off = align_up(off + 4);
+    L.off_kdev = off; off = align_up(off + 8);
+    L.max_tile_rows = 2 * ((total_inst + kMinTileBudget - 1) / kMinTileBudget) +
+                      (n_nodes + kMinTileNodes - 1) / kMinTileNodes + 2;
+    L.off_tiles = off;
+    off = align_up(off + 4 * (size_t)L.max_tile_rows * (1 + slots.size()));
+    L.total = off;
+}
+
+}  // namespace
+
+struct mech_ctx {
+    int64_t n_nodes = 0;
+    int prec = MECH_FP64;
+    bool fp32 = false;
+    char *buf = nullptr;
+    size_t bytes = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t capture_stream = nullptr;
+    std::vector<SlotHost> slots;
+    Layout L;
+    Globals gl;
+    NodesDev nd{};
+    bool nodes_bound = false, clamp_bound = false, has_syn = false;
+    // fused-path launch shape and tile table
+    int block = 256, tile_budget = 2048, tile_nodes = 1024, blocks_per_cu = 0;
+    int64_t n_tiles = 0, max_tile_nodes = 0;
+    int n_cu = 256;
+    // graphs of kGraphSteps fused steps, keyed by (vmode, dt)
+    std::map<std::pair<int, uint64_t>, hipGraphExec_t> graphs;
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(mech_ctx *c, int code, const char *fmt, ...) {
+    char msg[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(msg, sizeof msg, fmt, ap);
+    va_end(ap);
+    if (c) c->err = msg;
+    g_last_error = msg;
+    return code;
+}
+
+#define HIPCHK(c, expr)                                                                   \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail((c), MECH_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_));       \
+    } while (0)
+
+constexpr int kGraphSteps = 64;
+
+void clear_graphs(mech_ctx *c) {
+    for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+}
+
+GlobDev make_glob(const mech_ctx *c, double dt) {
+    const Globals &G = c->gl;
+    GlobDev g{};
+    g.q10 = std::pow(3.0, (G.celsius - 6.3) / 10.0);
+    g.ena = G.ena; g.ek = G.ek; g.eh = G.eh;
+    g.cao = G.cao; g.cai0 = G.cai0;
+    const double R = 8.314462618, F = 96485.33212;
+    g.nernst = 1e3 * R * (G.celsius + 273.15) / (2.0 * F);
+    const double kappa = 1e4 * G.ca_gamma / (2.0 * F * G.ca_depth);
+    g.kt_ca = kappa * G.tau_ca;
+    g.e_syn = G.e_syn; g.mg = G.mg;
+    g.mg_fd = std::exp(-0.062 * G.fd_dv);
+    g.fd_dv = G.fd_dv; g.vthresh = G.vthresh;
+    auto peak = [](double tr, double td) {
+        const double tp = tr * td / (td - tr) * std::log(td / tr);
+        return 1.0 / (std::exp(-tp / td) - std::exp(-tp / tr));
+    };
+    g.fa = peak(G.tau_r_ampa, G.tau_d_ampa);
+    g.fn = peak(G.tau_r_nmda, G.tau_d_nmda);
+    g.dt = dt;
+    const double taus[4] = {G.tau_r_ampa, G.tau_d_ampa, G.tau_r_nmda, G.tau_d_nmda};
+    for (int j = 0; j < 4; ++j) {
+        g.decay[j] = std::exp(-dt / taus[j]);
+        g.omdecay[j] = -std::expm1(-dt / taus[j]);
+    }
+    g.ca_decay = std::exp(-dt / G.tau_ca);
+    g.ca_omdecay = -std::expm1(-dt / G.tau_ca);
+    g.seed = G.event_seed;
+    // fire with probability p = rate*dt: draws below floor(p * 2^64)
+    const double p = G.event_rate_hz * dt * 1e-3;
+    g.threshold = !(p > 0.0) ? 0 : p >= 1.0 ? UINT64_MAX : (uint64_t)std::floor(p * 18446744073709551616.0);
+    return g;
+}
+
+SlotDev slot_dev(const mech_ctx *c, int s) {
+    const SlotHost &h = c->slots[s];
+    const KindDesc &K = kKinds[h.kind];
+    SlotDev d{};
+    d.kind = h.kind;
+    d.n = (int)h.n;
+    d.identity = h.identity ? 1 : 0;
+    d.ni = (const int *)(c->buf + h.off_ni);
+    d.gid = (h.has_gid && !h.perm_identity) ? (const int *)(c->buf + h.off_gid) : nullptr;
+    for (int j = 0; j < K.n_state; ++j) d.st[j] = c->buf + h.off_st[j];
+    for (int j = 0; j < K.n_param; ++j) d.par[j] = c->buf + h.off_par[j];
+    d.ica = h.has_ica ? (void *)(c->buf + h.off_ica) : nullptr;
+    return d;
+}
+
+int build_tiles(mech_ctx *c) {
+    const int ns = (int)c->slots.size();
+    const int row = 1 + ns;
+    std::vector<int32_t> rows;
+    rows.reserve(1024);
+    std::vector<int64_t> ptr(ns, 0);
+    auto push = [&](int64_t node) {
+        rows.push_back((int32_t)node);
+        for (int s = 0; s < ns; ++s) rows.push_back((int32_t)ptr[s]);
+    };
+    push(0);
+    int64_t cost = 0, nodes = 0, max_nodes = 0;
+    int64_t nxt[kMaxSlots];
+    for (int64_t n = 0; n < c->n_nodes; ++n) {
+        int64_t cn = 0;
+        for (int s = 0; s < ns; ++s) {
+            const auto &ni = c->slots[s].ni;
+            nxt[s] = ptr[s];
+            while (nxt[s] < (int64_t)ni.size() && ni[nxt[s]] == n) ++nxt[s];
+            cn += nxt[s] - ptr[s];
+        }
+        if (nodes > 0 && (cost + cn > c->tile_budget || nodes >= c->tile_nodes)) {
+            push(n);
+            max_nodes = std::max(max_nodes, nodes);
+            cost = 0;
+            nodes = 0;
+        }
+        for (int s = 0; s < ns; ++s) ptr[s] = nxt[s];
+        cost += cn;
+        ++nodes;
+    }
+    max_nodes = std::max(max_nodes, nodes);
+    push(c->n_nodes);
+    const int64_t nrows = (int64_t)rows.size() / row;
+    if (nrows > c->L.max_tile_rows)
+        return fail(c, MECH_ERR_NOMEM, "tile table needs %lld rows, room for %lld", (long long)nrows,
+                    (long long)c->L.max_tile_rows);
+    c->n_tiles = c->n_nodes > 0 ? nrows - 1 : 0;
+    c->max_tile_nodes = max_nodes;
+    HIPCHK(c, hipMemcpyAsync(c->buf + c->L.off_tiles, rows.data(), rows.size() * 4, hipMemcpyHostToDevice,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    clear_graphs(c);
+    return MECH_OK;
+}
+
+// Reject a step with unbound inputs before anything is enqueued.
+int check_ready(mech_ctx *c, int vmode) {
+    if (!c->nodes_bound) return fail(c, MECH_ERR_STATE, "node vectors not bound (mech_bind_nodes)");
+    if (vmode == MECH_V_CLAMP && !c->clamp_bound)
+        return fail(c, MECH_ERR_STATE, "clamp waveform not bound (mech_bind_clamp)");
+    if (vmode == MECH_V_ISOLATED && !c->nd.cm)
+        return fail(c, MECH_ERR_STATE, "isolated mode needs cm (mech_bind_nodes)");
+    if (vmode < MECH_V_EXTERNAL || vmode > MECH_V_ISOLATED) return fail(c, MECH_ERR_INVAL, "bad vmode %d", vmode);
+    return MECH_OK;
+}
+
+int find_slot_var(mech_ctx *c, int slot, const char *name, bool state, size_t *off, bool *is_double) {
+    if (!c || !name) return fail(c, MECH_ERR_INVAL, "null argument");
+    if (slot < 0 || slot >= (int)c->slots.size()) return fail(c, MECH_ERR_INVAL, "bad type slot %d", slot);
+    const SlotHost &h = c->slots[slot];
+    const KindDesc &K = kKinds[h.kind];
+    if (state) {
+        for (int j = 0; j < K.n_state; ++j)
+            if (!strcmp(K.state[j], name)) { *off = h.off_st[j]; *is_double = !c->fp32; return MECH_OK; }
+        if (h.has_ica && !strcmp(name, "ica")) { *off = h.off_ica; *is_double = !c->fp32; return MECH_OK; }
+    } else {
+        for (int j = 0; j < K.n_param; ++j)
+            if (!strcmp(K.param[j].name, name)) {
+                *off = h.off_par[j];
+                *is_double = K.param[j].is_double || !c->fp32;
+                return MECH_OK;
+            }
+    }
+    return fail(c, MECH_ERR_INVAL, "%s has no %s '%s'", K.name, state ? "state" : "parameter", name);
+}
+
+// Copy host doubles (caller order) into a device array (internal order).
+int upload_var(mech_ctx *c, int slot, size_t off, bool is_double, const double *vals, int64_t n) {
+    const SlotHost &h = c->slots[slot];
+    if (n != 1 && n != h.n)
+        return fail(c, MECH_ERR_INVAL, "expected 1 or %lld values, got %lld", (long long)h.n, (long long)n);
+    if (h.n == 0) return MECH_OK;
+    std::vector<double> tmp(h.np, 0.0);
+    for (int64_t i = 0; i < h.n; ++i) {
+        const int64_t u = h.perm_identity ? i : h.perm[i];
+        tmp[i] = n == 1 ? vals[0] : vals[u];
+    }
+    if (is_double) {
+        HIPCHK(c, hipMemcpyAsync(c->buf + off, tmp.data(), 8 * h.np, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    } else {
+        std::vector<float> f(h.np);
+        for (int64_t i = 0; i < h.np; ++i) f[i] = (float)tmp[i];
+        HIPCHK(c, hipMemcpyAsync(c->buf + off, f.data(), 4 * h.np, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return MECH_OK;
+}
+
+int launch_plain_phase(mech_ctx *c, bool cur, int64_t k, const GlobDev &g, int accumulate) {
+    PlainArgs a{};
+    a.k = k;
+    a.accumulate = accumulate;
+    a.err = (int *)(c->buf + c->L.off_err);
+    a.g = g;
+    a.nd = c->nd;
+    if (cur && !accumulate) HIPCHK(c, launch_fill(c->nd.rhs, c->nd.d, (int)c->n_nodes, c->stream));
+    for (int s = 0; s < (int)c->slots.size(); ++s) {
+        a.slot = slot_dev(c, s);
+        if (cur) HIPCHK(c, launch_plain_cur(c->fp32, a, c->stream));
+        else HIPCHK(c, launch_plain_state(c->fp32, a, c->stream));
+    }
+    return MECH_OK;
+}
+
+FusedArgs fused_args(mech_ctx *c, const GlobDev &g, int kofs) {
+    FusedArgs a{};
+    for (int s = 0; s < (int)c->slots.size(); ++s) a.slot[s] = slot_dev(c, s);
+    a.n_slots = (int)c->slots.size();
+    a.has_syn = c->has_syn ? 1 : 0;
+    a.tiles = (const int *)(c->buf + c->L.off_tiles);
+    a.n_tiles = (int)c->n_tiles;
+    a.row = 1 + (int)c->slots.size();
+    a.kdev = (const long long *)(c->buf + c->L.off_kdev);
+    a.kofs = kofs;
+    a.err = (int *)(c->buf + c->L.off_err);
+    a.g = g;
+    a.nd = c->nd;
+    return a;
+}
+
+void fused_shape(const mech_ctx *c, int *grid, size_t *lds) {
+    int gr = (int)c->n_tiles;
+    if (c->blocks_per_cu > 0) gr = (int)std::min<int64_t>(c->n_tiles, (int64_t)c->blocks_per_cu * c->n_cu);
+    *grid = gr;
+    *lds = 4 * sizeof(double) * (size_t)std::max<int64_t>(c->max_tile_nodes, 1);
+}
+
+int launch_fused_phase(mech_ctx *c, int phases, int vmode, const GlobDev &g, int kofs, hipStream_t s) {
+    int grid;
+    size_t lds;
+    fused_shape(c, &grid, &lds);
+    HIPCHK(c, launch_fused(c->fp32, phases, vmode, fused_args(c, g, kofs), grid, c->block, lds, s));
+    return MECH_OK;
+}
+
+int get_graph(mech_ctx *c, int vmode, double dt, const GlobDev &g, hipGraphExec_t *out) {
+    uint64_t bits;
+    memcpy(&bits, &dt, 8);
+    auto key = std::make_pair(vmode, bits);
+    auto it = c->graphs.find(key);
+    if (it != c->graphs.end()) { *out = it->second; return MECH_OK; }
+    if (!c->capture_stream)
+        HIPCHK(c, hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+    HIPCHK(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+    int rc = MECH_OK;
+    for (int j = 0; j < kGraphSteps && rc == MECH_OK; ++j)
+        rc = launch_fused_phase(c, kDoState | kDoCur, vmode, g, j, c->capture_stream);
+    hipError_t e1 = rc == MECH_OK ? launch_bump_k((long long *)(c->buf + c->L.off_kdev), kGraphSteps,
+                                                  c->capture_stream)
+                                  : hipSuccess;
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(c->capture_stream, &graph);
+    if (rc != MECH_OK) { if (graph) (void)hipGraphDestroy(graph); return rc; }
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(c, MECH_ERR_HIP, "graph capture: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+    }
+    hipGraphExec_t exec = nullptr;
+    hipError_t e3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e3 != hipSuccess) return fail(c, MECH_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e3));
+    c->graphs[key] = exec;
+    *out = exec;
+    return MECH_OK;
+}
+
+int step_plain(mech_ctx *c, int64_t nsteps, int64_t k0, double dt, int vmode) {
+    const GlobDev g = make_glob(c, dt);
+    if (vmode == MECH_V_CLAMP) HIPCHK(c, launch_vclamp(c->nd, (double)k0 * dt, c->stream));
+    for (int64_t k = k0; k < k0 + nsteps; ++k) {
+        int rc = launch_plain_phase(c, true, k, g, 0);
+        if (rc) return rc;
+        if (vmode == MECH_V_CLAMP) HIPCHK(c, launch_vclamp(c->nd, (double)(k + 1) * dt, c->stream));
+        if (vmode == MECH_V_ISOLATED) HIPCHK(c, launch_visolated(c->nd, g, c->stream));
+        rc = launch_plain_phase(c, false, k, g, 0);
+        if (rc) return rc;
+    }
+    return MECH_OK;
+}
+
+int step_batched(mech_ctx *c, int64_t nsteps, int64_t k0, double dt, int vmode, bool use_graph) {
+    const GlobDev g = make_glob(c, dt);
+    long long *kdev = (long long *)(c->buf + c->L.off_kdev);
+    if (vmode == MECH_V_CLAMP) HIPCHK(c, launch_vclamp(c->nd, (double)k0 * dt, c->stream));
+    HIPCHK(c, launch_set_k(kdev, k0, c->stream));
+    int rc = launch_fused_phase(c, kDoCur, vmode, g, 0, c->stream);
+    if (rc) return rc;
+    // middle passes: state(k-1) + events(k) + cur(k) for k = k0+1 .. k0+nsteps-1
+    int64_t mids = nsteps - 1;
+    HIPCHK(c, launch_set_k(kdev, k0 + 1, c->stream));
+    if (use_graph && mids >= kGraphSteps) {
+        hipGraphExec_t exec;
+        rc = get_graph(c, vmode, dt, g, &exec);
+        if (rc) return rc;
+        while (mids >= kGraphSteps) {
+            HIPCHK(c, hipGraphLaunch(exec, c->stream));
+            mids -= kGraphSteps;
+        }
+    }
+    for (int64_t j = 0; j < mids; ++j) {
+        rc = launch_fused_phase(c, kDoState | kDoCur, vmode, g, (int)j, c->stream);
+        if (rc) return rc;
+    }
+    // closing state update at v_{k0+nsteps}
+    return launch_fused_phase(c, kDoState, MECH_V_EXTERNAL, g, 0, c->stream);
+}
+
+}  // namespace
+
+// ================================================================ C ABI ==
+extern "C" {
+
+const char *mech_strerror(int code) {
+    switch (code) {
+    case MECH_OK: return "ok";
+    case MECH_ERR_INVAL: return "invalid argument";
+    case MECH_ERR_RANGE: return "node index out of range";
+    case MECH_ERR_NOMEM: return "device buffer too small";
+    case MECH_ERR_STATE: return "call out of order";
+    case MECH_ERR_HIP: return "HIP runtime error";
+    case MECH_ERR_NONFINITE: return "non-finite state";
+    default: return "unknown error";
+    }
+}
+
+const char *mech_last_error(const mech_ctx *c) { return c ? c->err.c_str() : g_last_error.c_str(); }
+
+static int validate_types(int64_t n_nodes, const mech_type_desc *types, int n_types, int prec) {
+    if (n_nodes < 0 || n_nodes >= (int64_t(1) << 31)) return fail(nullptr, MECH_ERR_INVAL, "bad n_nodes");
+    if (n_types < 0 || n_types > kMaxSlots) return fail(nullptr, MECH_ERR_INVAL, "n_types must be 0..%d", kMaxSlots);
+    if (n_types > 0 && !types) return fail(nullptr, MECH_ERR_INVAL, "null types");
+    if (prec != MECH_FP64 && prec != MECH_FP32_MIXED) return fail(nullptr, MECH_ERR_INVAL, "bad precision %d", prec);
+    for (int s = 0; s < n_types; ++s) {
+        if (types[s].kind < MECH_PAS || types[s].kind > MECH_SYN)
+            return fail(nullptr, MECH_ERR_INVAL, "type %d: bad kind %d", s, types[s].kind);
+        if (types[s].count < 0 || types[s].count >= (int64_t(1) << 31))
+            return fail(nullptr, MECH_ERR_INVAL, "type %d: bad count", s);
+        if (types[s].count > 0 && !types[s].node_index)
+            return fail(nullptr, MECH_ERR_INVAL, "type %d: null node_index", s);
+    }
+    return MECH_OK;
+}
+
+int mech_required_bytes(int64_t n_nodes, const mech_type_desc *types, int n_types, int prec, size_t *out) {
+    int rc = validate_types(n_nodes, types, n_types, prec);
+    if (rc) return rc;
+    if (!out) return fail(nullptr, MECH_ERR_INVAL, "null out");
+    std::vector<SlotHost> slots(n_types);
+    for (int s = 0; s < n_types; ++s) { slots[s].kind = types[s].kind; slots[s].n = types[s].count; }
+    Layout L;
+    compute_layout(n_nodes, slots, prec, L);
+    *out = L.total;
+    return MECH_OK;
+}
+
+int mech_alloc(mech_ctx **out, int64_t n_nodes, const mech_type_desc *types, int n_types, int prec,
+               void *dev_buf, size_t dev_bytes, void *hip_stream) {
+    if (!out) return fail(nullptr, MECH_ERR_INVAL, "null out");
+    *out = nullptr;
+    int rc = validate_types(n_nodes, types, n_types, prec);
+    if (rc) return rc;
+    if (!dev_buf || ((uintptr_t)dev_buf % kAlign) != 0)
+        return fail(nullptr, MECH_ERR_INVAL, "device buffer must be non-null and %d-byte aligned", kAlign);
+    mech_ctx *c = new (std::nothrow) mech_ctx();
+    if (!c) return fail(nullptr, MECH_ERR_INVAL, "host allocation failed");
+    c->n_nodes = n_nodes;
+    c->prec = prec;
+    c->fp32 = prec == MECH_FP32_MIXED;
+    c->buf = (char *)dev_buf;
+    c->bytes = dev_bytes;
+    c->stream = (hipStream_t)hip_stream;
+    c->slots.resize(n_types);
+    for (int s = 0; s < n_types; ++s) {
+        SlotHost &h = c->slots[s];
+        h.kind = types[s].kind;
+        h.n = types[s].count;
+        if (h.kind == MECH_SYN) c->has_syn = true;
+        const int32_t *ni = types[s].node_index;
+        // range check, sortedness, identity
+        bool sorted = true, ident = h.n == n_nodes;
+        for (int64_t i = 0; i < h.n; ++i) {
+            if (ni[i] < 0 || ni[i] >= n_nodes) {
+                int code = fail(nullptr, MECH_ERR_RANGE, "type %d instance %lld: node %d outside [0, %lld)", s,
+                                (long long)i, ni[i], (long long)n_nodes);
+                delete c;
+                return code;
+            }
+            if (i > 0 && ni[i] < ni[i - 1]) sorted = false;
+            if (ni[i] != i) ident = false;
+        }
+        h.identity = ident;
+        if (sorted) {
+            h.perm_identity = true;
+            h.ni.assign(ni, ni + h.n);
+        } else {
+            // stable counting sort by node
+            h.perm_identity = false;
+            std::vector<int64_t> cnt(n_nodes + 1, 0);
+            for (int64_t i = 0; i < h.n; ++i) ++cnt[ni[i] + 1];
+            for (int64_t n = 0; n < n_nodes; ++n) cnt[n + 1] += cnt[n];
+            h.perm.resize(h.n);
+            h.ni.resize(h.n);
+            for (int64_t i = 0; i < h.n; ++i) {
+                const int64_t p = cnt[ni[i]]++;
+                h.perm[p] = (int32_t)i;
+                h.ni[p] = ni[i];
+            }
+        }
+    }
+    compute_layout(n_nodes, c->slots, prec, c->L);
+    if (dev_bytes < c->L.total) {
+        int code = fail(nullptr, MECH_ERR_NOMEM, "device buffer has %zu bytes, %zu required", dev_bytes, c->L.total);
+        delete c;
+        return code;
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int cu = 0;
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cu > 0)
+            c->n_cu = cu;
+    }
+    // upload index arrays (padded lanes point at node 0 and are never read)
+    for (int s = 0; s < n_types && rc == MECH_OK; ++s) {
+        SlotHost &h = c->slots[s];
+        std::vector<int32_t> tmp(h.np, 0);
+        std::copy(h.ni.begin(), h.ni.end(), tmp.begin());
+        hipError_t e = hipMemcpy(c->buf + h.off_ni, tmp.data(), 4 * h.np, hipMemcpyHostToDevice);
+        if (e == hipSuccess && h.has_gid) {
+            for (int64_t i = 0; i < h.n; ++i) tmp[i] = h.perm_identity ? (int32_t)i : h.perm[i];
+            e = hipMemcpy(c->buf + h.off_gid, tmp.data(), 4 * h.np, hipMemcpyHostToDevice);
+        }
+        if (e != hipSuccess) rc = fail(c, MECH_ERR_HIP, "hipMemcpy: %s", hipGetErrorString(e));
+        const KindDesc &K = kKinds[h.kind];
+        for (int j = 0; j < K.n_param && rc == MECH_OK; ++j) {
+            size_t off;
+            bool isd;
+            rc = find_slot_var(c, s, K.param[j].name, false, &off, &isd);
+            if (rc == MECH_OK) rc = upload_var(c, s, off, isd, &K.defaults[j], 1);
+        }
+    }
+    if (rc == MECH_OK) {
+        hipError_t e = launch_set_k((long long *)(c->buf + c->L.off_kdev), 0, c->stream);
+        if (e == hipSuccess) e = launch_fill_int((int *)(c->buf + c->L.off_err), 1, c->stream);
+        if (e == hipSuccess) e = launch_fill_int((int *)(c->buf + c->L.off_spikes), (int)std::max<int64_t>(n_nodes, 1), c->stream);
+        if (e != hipSuccess) rc = fail(c, MECH_ERR_HIP, "init fill: %s", hipGetErrorString(e));
+    }
+    if (rc == MECH_OK) {
+        c->nd.n_nodes = (int)n_nodes;
+        c->nd.spikes = (int *)(c->buf + c->L.off_spikes);
+        rc = build_tiles(c);
+    }
+    if (rc != MECH_OK) {
+        g_last_error = c->err;
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return MECH_OK;
+}
+
+int mech_bind_nodes(mech_ctx *c, double *v, double *rhs, double *d, const double *area, const double *cm) {
+    if (!c) return fail(nullptr, MECH_ERR_INVAL, "null ctx");
+    if (c->n_nodes > 0 && (!v || !rhs || !d)) return fail(c, MECH_ERR_INVAL, "v, rhs and d are required");
+    if (c->has_syn && c->n_nodes > 0 && !area) return fail(c, MECH_ERR_INVAL, "area is required with synapses");
+    c->nd.v = v;
+    c->nd.rhs = rhs;
+    c->nd.d = d;
+    c->nd.area = area;
+    c->nd.cm = cm;
+    c->nodes_bound = true;
+    clear_graphs(c);
+    return MECH_OK;
+}
+
+int mech_bind_clamp(mech_ctx *c, const double *off, const double *amp, const double *freq, const double *phase) {
+    if (!c) return fail(nullptr, MECH_ERR_INVAL, "null ctx");
+    if (c->n_nodes > 0 && (!off || !amp || !freq || !phase))
+        return fail(c, MECH_ERR_INVAL, "all four clamp arrays are required");
+    c->nd.c_off = off;
+    c->nd.c_amp = amp;
+    c->nd.c_freq = freq;
+    c->nd.c_phase = phase;
+    c->clamp_bound = true;
+    clear_graphs(c);
+    return MECH_OK;
+}
+
+int mech_set_params(mech_ctx *c, int slot, const char *name, const double *vals, int64_t n) {
+    if (!c || !vals) return fail(c, MECH_ERR_INVAL, "null argument");
+    size_t off;
+    bool isd;
+    int rc = find_slot_var(c, slot, name, false, &off, &isd);
+    if (rc) return rc;
+    return upload_var(c, slot, off, isd, vals, n);
+}
+
+int mech_set_global(mech_ctx *c, const char *name, double value) {
+    if (!c || !name) return fail(c, MECH_ERR_INVAL, "null argument");
+    Globals &G = c->gl;
+    struct { const char *n; double *p; } tab[] = {
+        {"celsius", &G.celsius}, {"ena", &G.ena}, {"ek", &G.ek}, {"eh", &G.eh}, {"cao", &G.cao},
+        {"cai0", &G.cai0}, {"tau_ca", &G.tau_ca}, {"ca_gamma", &G.ca_gamma}, {"ca_depth", &G.ca_depth},
+        {"e_syn", &G.e_syn}, {"mg", &G.mg}, {"tau_r_ampa", &G.tau_r_ampa}, {"tau_d_ampa", &G.tau_d_ampa},
+        {"tau_r_nmda", &G.tau_r_nmda}, {"tau_d_nmda", &G.tau_d_nmda}, {"event_rate_hz", &G.event_rate_hz},
+        {"vthresh", &G.vthresh}, {"fd_dv", &G.fd_dv}};
+    if (!strcmp(name, "event_seed")) {
+        if (!(value >= 0.0) || value >= 9007199254740992.0 || value != std::floor(value))
+            return fail(c, MECH_ERR_INVAL, "event_seed must be an integer in [0, 2^53)");
+        G.event_seed = (uint64_t)value;
+        clear_graphs(c);
+        return MECH_OK;
+    }
+    for (auto &t : tab)
+        if (!strcmp(t.n, name)) {
+            if (!std::isfinite(value)) return fail(c, MECH_ERR_INVAL, "%s must be finite", name);
+            *t.p = value;
+            clear_graphs(c);
+            return MECH_OK;
+        }
+    return fail(c, MECH_ERR_INVAL, "unknown global '%s'", name);
+}
+
+int mech_init(mech_ctx *c) {
+    if (!c) return fail(nullptr, MECH_ERR_INVAL, "null ctx");
+    if (!c->nodes_bound) return fail(c, MECH_ERR_STATE, "node vectors not bound (mech_bind_nodes)");
+    PlainArgs a{};
+    a.err = (int *)(c->buf + c->L.off_err);
+    a.g = make_glob(c, 0.025);
+    a.nd = c->nd;
+    for (int s = 0; s < (int)c->slots.size(); ++s) {
+        a.slot = slot_dev(c, s);
+        HIPCHK(c, launch_init(c->fp32, a, c->stream));
+    }
+    HIPCHK(c, launch_fill_int(c->nd.spikes, (int)std::max<int64_t>(c->n_nodes, 1), c->stream));
+    return MECH_OK;
+}
+
+int mech_cur(mech_ctx *c, int64_t k, double dt, int accumulate) {
+    if (!c) return fail(nullptr, MECH_ERR_INVAL, "null ctx");
+    int rc = check_ready(c, MECH_V_EXTERNAL);
+    if (rc) return rc;
+    if (!(dt > 0.0) || k < 0) return fail(c, MECH_ERR_INVAL, "need dt > 0 and k >= 0");
+    return launch_plain_phase(c, true, k, make_glob(c, dt), accumulate);
+}
+
+int mech_state(mech_ctx *c, double dt) {
+    if (!c) return fail(nullptr, MECH_ERR_INVAL, "null ctx");
+    int rc = check_ready(c, MECH_V_EXTERNAL);
+    if (rc) return rc;
+    if (!(dt > 0.0)) return fail(c, MECH_ERR_INVAL, "need dt > 0");
+    return launch_plain_phase(c, false, 0, make_glob(c, dt), 0);
+}
+
+int mech_step(mech_ctx *c, int64_t nsteps, int64_t k0, double dt, int vmode, int path) {
+    if (!c) return fail(nullptr, MECH_ERR_INVAL, "null ctx");
+    int rc = check_ready(c, vmode);
+    if (rc) return rc;
+    if (!(dt > 0.0) || k0 < 0 || nsteps < 0 || k0 + nsteps >= (int64_t(1) << 32))
+        return fail(c, MECH_ERR_INVAL, "need dt > 0, k0 >= 0, nsteps >= 0, k0 + nsteps < 2^32");
+    if (nsteps == 0) return MECH_OK;
+    if (path == MECH_PATH_PLAIN) return step_plain(c, nsteps, k0, dt, vmode);
+    if (path == MECH_PATH_BATCHED) return step_batched(c, nsteps, k0, dt, vmode, true);
+    return fail(c, MECH_ERR_INVAL, "bad path %d", path);
+}
+
+int mech_set_launch(mech_ctx *c, int block, int tile_instances, int tile_nodes, int blocks_per_cu) {
+    if (!c) return fail(nullptr, MECH_ERR_INVAL, "null ctx");
+    if (block < 64 || block > 1024 || block % 64)
+        return fail(c, MECH_ERR_INVAL, "block must be a multiple of 64 in [64, 1024]");
+    if (tile_instances < std::max(block, kMinTileBudget))
+        return fail(c, MECH_ERR_INVAL, "tile_instances must be >= block");
+    if (tile_nodes < kMinTileNodes || tile_nodes > kMaxTileNodes)
+        return fail(c, MECH_ERR_INVAL, "tile_nodes must be in [%d, %d]", kMinTileNodes, kMaxTileNodes);
+    if (blocks_per_cu < 0 || blocks_per_cu > 64) return fail(c, MECH_ERR_INVAL, "blocks_per_cu must be 0..64");
+    c->block = block;
+    c->tile_budget = tile_instances;
+    c->tile_nodes = tile_nodes;
+    c->blocks_per_cu = blocks_per_cu;
+    return build_tiles(c);
+}
+
+int mech_get_launch(const mech_ctx *c, int *block, int *tile_instances, int *tile_nodes, int *blocks_per_cu) {
+    if (!c) return fail(nullptr, MECH_ERR_INVAL, "null ctx");
+    if (block) *block = c->block;
+    if (tile_instances) *tile_instances = c->tile_budget;
+    if (tile_nodes) *tile_nodes = c->tile_nodes;
+    if (blocks_per_cu) *blocks_per_cu = c->blocks_per_cu;
+    return MECH_OK;
+}
+
+int mech_info(const mech_ctx *c, int64_t *n_tiles, int64_t *max_tile_nodes) {
+    if (!c) return fail(nullptr, MECH_ERR_INVAL, "null ctx");
+    if (n_tiles) *n_tiles = c->n_tiles;
+    if (max_tile_nodes) *max_tile_nodes = c->max_tile_nodes;
+    return MECH_OK;
+}
+
+int mech_autotune(mech_ctx *c, double dt, int vmode, int nsteps, int reps, double *best_ms) {
+    if (!c) return fail(nullptr, MECH_ERR_INVAL, "null ctx");
+    int rc = check_ready(c, vmode);
+    if (rc) return rc;
+    if (!(dt > 0.0) || nsteps < 1 || reps < 1) return fail(c, MECH_ERR_INVAL, "need dt > 0, nsteps >= 1, reps >= 1");
+    // save everything a step writes
+    const size_t nb = 8 * (size_t)c->n_nodes;
+    const size_t save_bytes = c->L.inst_end + 3 * nb + 4 * (size_t)c->n_nodes;
+    char *save = nullptr;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMalloc(&save, std::max<size_t>(save_bytes, 1)));
+    auto copy_all = [&](bool to_save) -> hipError_t {
+        struct { void *dev; size_t n; } parts[] = {
+            {c->buf, c->L.inst_end}, {c->nd.v, nb}, {c->nd.rhs, nb}, {c->nd.d, nb},
+            {c->nd.spikes, 4 * (size_t)c->n_nodes}};
+        size_t o = 0;
+        for (auto &p : parts) {
+            if (p.n == 0) continue;
+            hipError_t e = to_save ? hipMemcpyAsync(save + o, p.dev, p.n, hipMemcpyDeviceToDevice, c->stream)
+                                   : hipMemcpyAsync(p.dev, save + o, p.n, hipMemcpyDeviceToDevice, c->stream);
+            if (e != hipSuccess) return e;
+            o += p.n;
+        }
+        return hipStreamSynchronize(c->stream);
+    };
+    hipError_t e = copy_all(true);
+    if (e != hipSuccess) { (void)hipFree(save); return fail(c, MECH_ERR_HIP, "autotune save: %s", hipGetErrorString(e)); }
+    const int orig[4] = {c->block, c->tile_budget, c->tile_nodes, c->blocks_per_cu};
+    int best[4] = {orig[0], orig[1], orig[2], orig[3]};
+    double best_t = 1e300;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    const int blocks_c[] = {128, 256, 512};
+    const int ipt_c[] = {1, 2, 4, 8};
+    const int bpc_c[] = {0, 8};
+    for (int b : blocks_c)
+        for (int ipt : ipt_c)
+            for (int bpc : bpc_c) {
+                if (rc) break;
+                const int budget = b * ipt;
+                const int tn = std::min(kMaxTileNodes, std::max(kMinTileNodes, budget));
+                rc = mech_set_launch(c, b, budget, tn, bpc);
+                if (rc) break;
+                rc = step_batched(c, 1, 0, dt, vmode, false);  // warm-up
+                std::vector<double> ts;
+                for (int r = 0; r < reps && rc == MECH_OK; ++r) {
+                    (void)hipEventRecord(e0, c->stream);
+                    rc = step_batched(c, nsteps, 1, dt, vmode, false);
+                    (void)hipEventRecord(e1, c->stream);
+                    (void)hipEventSynchronize(e1);
+                    float ms = 0;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    ts.push_back(ms / nsteps);
+                }
+                if (rc) break;
+                std::sort(ts.begin(), ts.end());
+                const double med = ts[ts.size() / 2];
+                if (med < best_t) {
+                    best_t = med;
+                    best[0] = b; best[1] = budget; best[2] = tn; best[3] = bpc;
+                }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    int rc2 = mech_set_launch(c, best[0], best[1], best[2], best[3]);
+    e = copy_all(false);
+    (void)hipFree(save);
+    if (rc) return rc;
+    if (rc2) return rc2;
+    if (e != hipSuccess) return fail(c, MECH_ERR_HIP, "autotune restore: %s", hipGetErrorString(e));
+    if (best_ms) *best_ms = best_t;
+    return MECH_OK;
+}
+
+int mech_get_state(mech_ctx *c, int slot, const char *name, double *host_out, int64_t n) {
+    if (!c || !host_out) return fail(c, MECH_ERR_INVAL, "null argument");
+    size_t off;
+    bool isd;
+    int rc = find_slot_var(c, slot, name, true, &off, &isd);
+    if (rc) return rc;
+    const SlotHost &h = c->slots[slot];
+    if (n != h.n) return fail(c, MECH_ERR_INVAL, "expected %lld values", (long long)h.n);
+    if (h.n == 0) return MECH_OK;
+    std::vector<double> tmp(h.n);
+    if (isd) {
+        HIPCHK(c, hipMemcpyAsync(tmp.data(), c->buf + off, 8 * h.n, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    } else {
+        std::vector<float> f(h.n);
+        HIPCHK(c, hipMemcpyAsync(f.data(), c->buf + off, 4 * h.n, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int64_t i = 0; i < h.n; ++i) tmp[i] = f[i];
+    }
+    for (int64_t i = 0; i < h.n; ++i) host_out[h.perm_identity ? i : h.perm[i]] = tmp[i];
+    return MECH_OK;
+}
+
+int mech_set_state(mech_ctx *c, int slot, const char *name, const double *host_in, int64_t n) {
+    if (!c || !host_in) return fail(c, MECH_ERR_INVAL, "null argument");
+    size_t off;
+    bool isd;
+    int rc = find_slot_var(c, slot, name, true, &off, &isd);
+    if (rc) return rc;
+    if (n != c->slots[slot].n) return fail(c, MECH_ERR_INVAL, "expected %lld values", (long long)c->slots[slot].n);
+    return upload_var(c, slot, off, isd, host_in, n);
+}
+
+int mech_spike_counts(mech_ctx *c, int32_t *host_out, int64_t n) {
+    if (!c || !host_out) return fail(c, MECH_ERR_INVAL, "null argument");
+    if (n != c->n_nodes) return fail(c, MECH_ERR_INVAL, "expected %lld nodes", (long long)c->n_nodes);
+    if (n == 0) return MECH_OK;
+    HIPCHK(c, hipMemcpyAsync(host_out, c->nd.spikes, 4 * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return MECH_OK;
+}
+
+int mech_sync(mech_ctx *c) {
+    if (!c) return fail(nullptr, MECH_ERR_INVAL, "null ctx");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipGetLastError());
+    int flag = 0;
+    HIPCHK(c, hipMemcpy(&flag, c->buf + c->L.off_err, 4, hipMemcpyDeviceToHost));
+    if (flag) {
+        HIPCHK(c, launch_fill_int((int *)(c->buf + c->L.off_err), 1, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        return fail(c, MECH_ERR_NONFINITE, "a kernel stored a non-finite state");
+    }
+    return MECH_OK;
+}
+
+void mech_free(mech_ctx *c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    clear_graphs(c);
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+    delete c;
+}
+
+}  // extern "C"

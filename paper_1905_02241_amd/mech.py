@@ -1,0 +1,274 @@
+"""ctypes binding of libmech.so (include/mech.h).
+
+Argument marshalling only: every step of the mechanism path runs in the HIP
+kernels of the library.  PyTorch provides device memory (one flat buffer for
+the instance arrays, plus the node vectors) and the stream.  Importing this
+module does not touch the GPU; loading the library does, and it raises if
+``libmech.so`` has not been built -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, List, Optional
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libmech.so")
+
+OK, ERR_INVAL, ERR_RANGE, ERR_NOMEM, ERR_STATE, ERR_HIP, ERR_NONFINITE = 0, -1, -2, -3, -4, -5, -6
+KIND = {"pas": 0, "hh": 1, "ih": 2, "cahva": 3, "syn": 4}
+PREC = {"fp64": 0, "fp32": 1}
+VMODE = {"external": 0, "clamp": 1, "isolated": 2}
+PATH = {"plain": 0, "batched": 1}
+GLOBAL_NAMES = ("celsius", "ena", "ek", "eh", "cao", "cai0", "tau_ca", "ca_gamma", "ca_depth", "e_syn",
+                "mg", "tau_r_ampa", "tau_d_ampa", "tau_r_nmda", "tau_d_nmda", "event_rate_hz", "event_seed",
+                "vthresh", "fd_dv")
+
+# Exported symbols of include/mech.h (checked by the CPU tests).
+SYMBOLS = ("mech_required_bytes", "mech_alloc", "mech_bind_nodes", "mech_bind_clamp", "mech_set_params",
+           "mech_set_global", "mech_init", "mech_cur", "mech_state", "mech_step", "mech_set_launch",
+           "mech_get_launch", "mech_autotune", "mech_get_state", "mech_set_state", "mech_spike_counts",
+           "mech_sync", "mech_info", "mech_last_error", "mech_strerror", "mech_free")
+
+
+class MechError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"mech error {code}: {msg}")
+        self.code = code
+
+
+class TypeDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("count", C.c_int64), ("node_index", C.POINTER(C.c_int32))]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libmech.so (after torch, so both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1905_02241_amd.build` "
+                          "(there is no CPU fallback)")
+    try:
+        import torch  # noqa: F401  -- loads the HIP runtime the library links against
+    except ImportError:
+        pass
+    L = C.CDLL(path)
+    vp, dp, ip, lp = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int64)
+    sig = {
+        "mech_required_bytes": [C.c_int64, C.POINTER(TypeDesc), C.c_int, C.c_int, C.POINTER(C.c_size_t)],
+        "mech_alloc": [C.POINTER(vp), C.c_int64, C.POINTER(TypeDesc), C.c_int, C.c_int, vp, C.c_size_t, vp],
+        "mech_bind_nodes": [vp, vp, vp, vp, vp, vp],
+        "mech_bind_clamp": [vp, vp, vp, vp, vp],
+        "mech_set_params": [vp, C.c_int, C.c_char_p, dp, C.c_int64],
+        "mech_set_global": [vp, C.c_char_p, C.c_double],
+        "mech_init": [vp],
+        "mech_cur": [vp, C.c_int64, C.c_double, C.c_int],
+        "mech_state": [vp, C.c_double],
+        "mech_step": [vp, C.c_int64, C.c_int64, C.c_double, C.c_int, C.c_int],
+        "mech_set_launch": [vp, C.c_int, C.c_int, C.c_int, C.c_int],
+        "mech_get_launch": [vp, ip, ip, ip, ip],
+        "mech_autotune": [vp, C.c_double, C.c_int, C.c_int, C.c_int, dp],
+        "mech_get_state": [vp, C.c_int, C.c_char_p, dp, C.c_int64],
+        "mech_set_state": [vp, C.c_int, C.c_char_p, dp, C.c_int64],
+        "mech_spike_counts": [vp, ip, C.c_int64],
+        "mech_sync": [vp],
+        "mech_info": [vp, lp, lp],
+        "mech_last_error": [vp],
+        "mech_strerror": [C.c_int],
+        "mech_free": [vp],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    L.mech_last_error.restype = C.c_char_p
+    L.mech_strerror.restype = C.c_char_p
+    L.mech_free.restype = None
+    _lib = L
+    return L
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Mechanisms:
+    """One mechanism context on the current CUDA/HIP device.
+
+    ``types`` is a list of (kind, node_index) pairs; node arrays are torch
+    float64 tensors on the device owned by this object (``v``, ``rhs``,
+    ``d``, ``area``, ``cm``, ``clamp``)."""
+
+    def __init__(self, n_nodes: int, types, prec: str = "fp64", stream=None, device: str = "cuda"):
+        import torch
+        self.torch = torch
+        self.L = load_library()
+        self.n_nodes = int(n_nodes)
+        self.prec = prec
+        self.kinds = [k for k, _ in types]
+        self._nodeidx = [np.ascontiguousarray(ni, dtype=np.int32) for _, ni in types]
+        self.counts = [int(a.shape[0]) for a in self._nodeidx]
+        descs = (TypeDesc * max(1, len(types)))()
+        for i, (k, _) in enumerate(types):
+            descs[i].kind = KIND[k]
+            descs[i].count = self.counts[i]
+            descs[i].node_index = self._nodeidx[i].ctypes.data_as(C.POINTER(C.c_int32))
+        self._descs = descs
+        nbytes = C.c_size_t(0)
+        self._check(self.L.mech_required_bytes(self.n_nodes, descs, len(types), PREC[prec], C.byref(nbytes)), None)
+        self.nbytes = int(nbytes.value)
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # torch's caching allocator returns 512-byte aligned blocks
+        self.buf = torch.empty(max(self.nbytes, 256), dtype=torch.uint8, device=self.device)
+        f64 = dict(dtype=torch.float64, device=self.device)
+        self.v = torch.full((self.n_nodes,), -65.0, **f64)
+        self.rhs = torch.zeros(self.n_nodes, **f64)
+        self.d = torch.zeros(self.n_nodes, **f64)
+        self.area = torch.full((self.n_nodes,), 500.0, **f64)
+        self.cm = torch.ones(self.n_nodes, **f64)
+        self.clamp = [torch.zeros(self.n_nodes, **f64) for _ in range(4)]
+        ctx = C.c_void_p()
+        self._check(self.L.mech_alloc(C.byref(ctx), self.n_nodes, descs, len(types), PREC[prec],
+                                      self.buf.data_ptr(), self.nbytes, self.stream.cuda_stream), None)
+        self.ctx = ctx
+        self._check(self.L.mech_bind_nodes(ctx, _ptr(self.v), _ptr(self.rhs), _ptr(self.d), _ptr(self.area),
+                                           _ptr(self.cm)))
+        self._check(self.L.mech_bind_clamp(ctx, *[_ptr(t) for t in self.clamp]))
+
+    # ----------------------------------------------------------- helpers --
+    def _check(self, rc: int, ctx="self"):
+        if rc != OK:
+            c = self.ctx if ctx == "self" else ctx
+            msg = self.L.mech_last_error(c).decode()
+            raise MechError(rc, msg)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.L.mech_free(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------- setup --
+    def set_node_array(self, name: str, values):
+        t = getattr(self, name)
+        t.copy_(self.torch.as_tensor(np.asarray(values, dtype=np.float64)).to(self.device))
+
+    def set_clamp(self, off, amp, freq, phase):
+        for t, a in zip(self.clamp, (off, amp, freq, phase)):
+            t.copy_(self.torch.as_tensor(np.asarray(a, dtype=np.float64)).to(self.device))
+
+    def set_params(self, slot: int, name: str, values):
+        a = np.ascontiguousarray(np.atleast_1d(np.asarray(values, dtype=np.float64)))
+        self._check(self.L.mech_set_params(self.ctx, slot, name.encode(), _dp(a), a.shape[0]))
+
+    def set_global(self, name: str, value: float):
+        self._check(self.L.mech_set_global(self.ctx, name.encode(), float(value)))
+
+    def set_globals(self, g: Dict[str, float]):
+        for k in GLOBAL_NAMES:
+            if k in g:
+                self.set_global(k, g[k])
+
+    def init(self):
+        self._check(self.L.mech_init(self.ctx))
+
+    # -------------------------------------------------------------- step --
+    def cur(self, k: int, dt: float, accumulate: bool = False):
+        self._check(self.L.mech_cur(self.ctx, k, dt, int(accumulate)))
+
+    def state(self, dt: float):
+        self._check(self.L.mech_state(self.ctx, dt))
+
+    def step(self, nsteps: int, k0: int, dt: float, vmode: str = "clamp", path: str = "batched"):
+        self._check(self.L.mech_step(self.ctx, nsteps, k0, dt, VMODE[vmode], PATH[path]))
+
+    def set_launch(self, block: int, tile_instances: int, tile_nodes: int, blocks_per_cu: int = 0):
+        self._check(self.L.mech_set_launch(self.ctx, block, tile_instances, tile_nodes, blocks_per_cu))
+
+    def get_launch(self):
+        v = [C.c_int32() for _ in range(4)]
+        self._check(self.L.mech_get_launch(self.ctx, *[C.byref(x) for x in v]))
+        return tuple(x.value for x in v)
+
+    def info(self):
+        a, b = C.c_int64(), C.c_int64()
+        self._check(self.L.mech_info(self.ctx, C.byref(a), C.byref(b)))
+        return {"n_tiles": a.value, "max_tile_nodes": b.value}
+
+    def autotune(self, dt: float, vmode: str, nsteps: int = 10, reps: int = 3) -> float:
+        ms = C.c_double(0.0)
+        self._check(self.L.mech_autotune(self.ctx, dt, VMODE[vmode], nsteps, reps, C.byref(ms)))
+        return ms.value
+
+    def sync(self):
+        self._check(self.L.mech_sync(self.ctx))
+
+    # ------------------------------------------------------------ output --
+    def get_state(self, slot: int, name: str) -> np.ndarray:
+        out = np.empty(self.counts[slot], dtype=np.float64)
+        self._check(self.L.mech_get_state(self.ctx, slot, name.encode(), _dp(out), out.shape[0]))
+        return out
+
+    def set_state(self, slot: int, name: str, values):
+        a = np.ascontiguousarray(values, dtype=np.float64)
+        self._check(self.L.mech_set_state(self.ctx, slot, name.encode(), _dp(a), a.shape[0]))
+
+    def spike_counts(self) -> np.ndarray:
+        out = np.empty(self.n_nodes, dtype=np.int32)
+        self._check(self.L.mech_spike_counts(self.ctx, out.ctypes.data_as(C.POINTER(C.c_int32)), self.n_nodes))
+        return out
+
+    def nodes(self) -> Dict[str, np.ndarray]:
+        self.sync()
+        return {k: getattr(self, k).cpu().numpy() for k in ("v", "rhs", "d")}
+
+
+STATE_NAMES = {"pas": (), "hh": ("m", "h", "n"), "ih": ("m",), "cahva": ("m", "h", "cai"),
+               "syn": ("A_ampa", "B_ampa", "A_nmda", "B_nmda")}
+
+
+def from_workload(w, prec: str = "fp64", init: bool = True) -> Mechanisms:
+    """Build a context from a workload (paper_1905_02241_amd.workloads):
+    node index, parameters, globals, node arrays; v = v_init everywhere and,
+    if `init`, every STATE at its steady state there."""
+    m = Mechanisms(w.n_nodes, [(s.kind, s.node) for s in w.slots], prec=prec)
+    m.set_globals(w.globals)
+    for i, s in enumerate(w.slots):
+        for name, vals in s.params.items():
+            m.set_params(i, name, vals)
+    if w.area is not None:
+        m.set_node_array("area", w.area)
+    if w.cm is not None:
+        m.set_node_array("cm", w.cm)
+    if w.clamp_off is not None:
+        m.set_clamp(w.clamp_off, w.clamp_amp, w.clamp_freq, w.clamp_phase)
+    m.v.fill_(float(w.v_init))
+    if init:
+        m.init()
+    return m
+
+
+def states_of(m: Mechanisms) -> List[Dict[str, np.ndarray]]:
+    out = []
+    for i, k in enumerate(m.kinds):
+        d = {name: m.get_state(i, name) for name in STATE_NAMES[k]}
+        if k == "cahva":
+            d["ica"] = m.get_state(i, "ica")
+        out.append(d)
+    return out

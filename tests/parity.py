@@ -1,0 +1,113 @@
+"""Helpers of the GPU-vs-oracle parity tests: run one workload through the
+C ABI (via the ctypes binding) and through the CPU oracle on the same seeded
+inputs, then compare element by element.
+
+Tolerances (derived in DESIGN.md, "Parity bars"):
+  FP64  STATEs   |gpu - ref| <= 1e-12 |ref| + 1e-300
+        rhs, d   |gpu - ref| <= 1e-11 S_n
+  FP32  gates and synapse states (nS)   |gpu - ref| <= 1e-5
+        cai                             |gpu - ref| <= 1e-4 |ref|
+        rhs, d   |gpu - ref| <= 2e-3 S_n
+  node index handling and event decisions: exact (spike counts bit-exact in
+  FP64).
+S_n = sum over the node's instances of |s| (|i| + 200 mV |g|), an upper bound
+of the magnitude of the terms that cancel in rhs and of the finite
+difference's numerator scaled by dv.
+"""
+from __future__ import annotations
+
+import sys
+import time
+
+import numpy as np
+
+from oracle import oracle as O
+
+STATE_TOL = {"fp64": (1e-12, 0.0), "fp32": (0.0, 1e-5)}   # (rel, abs)
+CAI_REL = {"fp64": 1e-12, "fp32": 1e-4}
+NODE_TOL = {"fp64": 1e-11, "fp32": 2e-3}
+
+
+def log(msg: str):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(w, nsteps, path="batched", prec="fp64", k0=0, launch=None, vmode=None):
+    from paper_1905_02241_amd import mech
+    m = mech.from_workload(w, prec)
+    if launch is not None:
+        m.set_launch(*launch)
+    m.step(nsteps, k0, w.dt, vmode or w.vmode, path)
+    m.sync()
+    out = {"states": mech.states_of(m), **m.nodes(), "spikes": m.spike_counts()}
+    return out, m
+
+
+def run_oracle(w, nsteps, k0=0):
+    M = O.Model(w)
+    M.init()
+    M.run(k0, nsteps)
+    return M
+
+
+def node_scale(M) -> np.ndarray:
+    """S_n from the oracle's final states and voltages."""
+    S = np.zeros(M.n_nodes)
+    for s, sl in enumerate(M.w.slots):
+        node = np.asarray(sl.node)
+        for i in range(sl.n):
+            n = node[i]
+            I, g = M.instance_current(s, i, M.v[n])
+            sc = 1e2 / M.area[n] if sl.kind == "syn" else 1.0
+            S[n] += sc * (abs(I) + 200.0 * abs(g))
+    return S
+
+
+def compare_states(got, M, prec, keep=None, label=""):
+    """Max violation ratio per state (<= 1 passes)."""
+    worst = {}
+    rel, ab = STATE_TOL[prec]
+    for s, sl in enumerate(M.w.slots):
+        for name, ref in M.states[s].items():
+            g = got["states"][s][name]
+            if keep is not None:
+                g = g[keep[s]]
+            if name == "cai":
+                tol = CAI_REL[prec] * np.abs(ref)
+            else:
+                tol = rel * np.abs(ref) + ab + 1e-300
+            err = np.abs(g - ref)
+            r = float(np.max(err / tol)) if err.size else 0.0
+            worst[f"{s}:{sl.kind}.{name}"] = (r, float(err.max()) if err.size else 0.0)
+    bad = {k: v for k, v in worst.items() if not v[0] <= 1.0}
+    assert not bad, f"{label} state parity: {bad}"
+    return worst
+
+
+def compare_nodes(got, M, prec, nodes=None, label="", check_v=True):
+    S = node_scale(M)
+    out = {}
+    for key in ("rhs", "d"):
+        g = got[key] if nodes is None else got[key][nodes]
+        ref = getattr(M, key)
+        tol = NODE_TOL[prec] * S + 1e-300
+        r = float(np.max(np.abs(g - ref) / tol)) if ref.size else 0.0
+        out[key] = r
+        assert r <= 1.0, f"{label} {key} parity ratio {r}"
+    if check_v:
+        g = got["v"] if nodes is None else got["v"][nodes]
+        tol = (1e-12 if prec == "fp64" else 1e-4) * (np.abs(M.v) + 1.0)
+        r = float(np.max(np.abs(g - M.v) / tol)) if M.v.size else 0.0
+        out["v"] = r
+        assert r <= 1.0, f"{label} v parity ratio {r}"
+    return out
+
+
+class Timer:
+    def __enter__(self):
+        self.t = time.perf_counter()
+        return self
+
+    def __exit__(self, *a):
+        self.dt = time.perf_counter() - self.t

@@ -1,0 +1,100 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/mech.h declares, and its host-side validation (which runs before any
+device call) rejects bad input with the documented codes."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1905_02241_amd import mech
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mech.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mech_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(mech.LIB_PATH):
+        from paper_1905_02241_amd import build
+        build.build()
+    return mech.load_library()
+
+
+def test_header_declares_the_binding_symbols():
+    assert declared_functions() == sorted(mech.SYMBOLS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_strerror_codes(lib):
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert lib.mech_strerror(code)
+    assert lib.mech_strerror(0) == b"ok"
+    assert lib.mech_strerror(-2) == b"node index out of range"
+
+
+def _descs(types):
+    d = (mech.TypeDesc * max(1, len(types)))()
+    keep = []
+    for i, (k, ni) in enumerate(types):
+        a = np.ascontiguousarray(ni, dtype=np.int32)
+        keep.append(a)
+        d[i].kind = mech.KIND[k] if isinstance(k, str) else k
+        d[i].count = a.shape[0]
+        d[i].node_index = a.ctypes.data_as(C.POINTER(C.c_int32))
+    return d, keep
+
+
+def test_required_bytes_layout(lib):
+    out = C.c_size_t()
+    d, keep = _descs([("hh", np.arange(1000))])
+    assert lib.mech_required_bytes(1000, d, 1, 0, C.byref(out)) == 0
+    fp64 = out.value
+    assert lib.mech_required_bytes(1000, d, 1, 1, C.byref(out)) == 0
+    fp32 = out.value
+    # 1024 padded instances: index 4 B, 3 states, 3 conductances in the state
+    # type, el in double
+    inst64 = 1024 * (4 + 3 * 8 + 3 * 8 + 8)
+    inst32 = 1024 * (4 + 3 * 4 + 3 * 4 + 8)
+    assert fp64 - fp32 == inst64 - inst32
+    assert fp64 % 256 == 0 and fp64 > inst64
+
+
+def test_validation_codes(lib):
+    out = C.c_size_t()
+    d, keep = _descs([(9, np.arange(4))])
+    assert lib.mech_required_bytes(4, d, 1, 0, C.byref(out)) == mech.ERR_INVAL
+    d, keep = _descs([("hh", np.arange(4))])
+    assert lib.mech_required_bytes(4, d, 1, 7, C.byref(out)) == mech.ERR_INVAL
+    assert lib.mech_required_bytes(-1, d, 1, 0, C.byref(out)) == mech.ERR_INVAL
+    assert lib.mech_required_bytes(4, d, 9, 0, C.byref(out)) == mech.ERR_INVAL
+    # mech_alloc rejects on the host, before any device call: a fake aligned
+    # buffer address is never dereferenced on these paths
+    ctx = C.c_void_p()
+    fake = 1 << 20
+    d, keep = _descs([("hh", np.array([0, 1, 4]))])
+    assert lib.mech_alloc(C.byref(ctx), 4, d, 1, 0, fake, 1 << 30, None) == mech.ERR_RANGE
+    assert b"outside" in lib.mech_last_error(None)
+    d, keep = _descs([("hh", np.array([0, 1, -1]))])
+    assert lib.mech_alloc(C.byref(ctx), 4, d, 1, 0, fake, 1 << 30, None) == mech.ERR_RANGE
+    d, keep = _descs([("hh", np.array([0, 1, 2]))])
+    assert lib.mech_alloc(C.byref(ctx), 4, d, 1, 0, fake, 16, None) == mech.ERR_NOMEM
+    assert lib.mech_alloc(C.byref(ctx), 4, d, 1, 0, fake + 8, 1 << 30, None) == mech.ERR_INVAL
+    assert lib.mech_alloc(C.byref(ctx), 4, d, 1, 0, None, 1 << 30, None) == mech.ERR_INVAL
+    assert not ctx.value
+    # null-context calls
+    assert lib.mech_init(None) == mech.ERR_INVAL
+    assert lib.mech_step(None, 1, 0, 0.025, 1, 1) == mech.ERR_INVAL
+    assert lib.mech_sync(None) == mech.ERR_INVAL
+    lib.mech_free(None)

@@ -1,0 +1,322 @@
+"""GPU parity: the HIP kernels (through include/mech.h's C ABI) against the FP64
+CPU oracle on the same seeded inputs, element by element.
+
+Paper references: section 3 (BREAKPOINT, DERIVATIVE/SOLVE, SUFFIX vs
+POINT_PROCESS), section 5.2 (cnexp; numerically approximated conductance),
+section 8 / Table 3 (current update, state update, "other").
+"""
+import numpy as np
+import pytest
+
+from paper_1905_02241_amd import workloads as W
+from tests.parity import (Timer, compare_nodes, compare_states, log, run_gpu, run_oracle)
+
+pytestmark = pytest.mark.gpu
+
+PATHS = ["plain", "batched"]
+PRECS = ["fp64", "fp32"]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("path", PATHS)
+def test_tiny_all_kinds_clamp(path, prec):
+    """All five mechanism types, two instances per node for the density
+    types, shuffled node index, sinusoidal clamp, events at 400 Hz."""
+    w = W.make_tiny(1, per_node=2, nsteps=60)
+    log(f"tiny clamp {path} {prec}: {w.instance_counts()}")
+    got, m = run_gpu(w, 60, path, prec)
+    M = run_oracle(w, 60)
+    ws = compare_states(got, M, prec, label="tiny")
+    wn = compare_nodes(got, M, prec, label="tiny")
+    log(f"  worst state ratio {max(v[0] for v in ws.values()):.3g}, nodes {wn}")
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_tiny_isolated_fp64_spikes(path):
+    """Free voltage (isolated compartments): FP64 states, v and spike counts."""
+    w = W.make_tiny(2, kinds=("pas", "hh", "cahva", "syn"), n_nodes=40, syn_per_node=6.0,
+                    vmode="isolated", event_rate_hz=300.0, nsteps=600)
+    w.area[:] = np.linspace(100.0, 400.0, w.n_nodes)
+    w.slots[-1].params["weight"][:] *= 6.0
+    got, m = run_gpu(w, 600, path, "fp64")
+    M = run_oracle(w, 600)
+    log(f"isolated {path}: spikes gpu {got['spikes'].sum()} oracle {M.spikes.sum()}")
+    assert M.spikes.sum() > 0
+    assert np.array_equal(got["spikes"], M.spikes)
+    compare_states(got, M, "fp64", label="isolated")
+    compare_nodes(got, M, "fp64", label="isolated")
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_tiny_isolated_fp32_reports(path):
+    """FP32-mixed in free-voltage mode: reported, spike counts must mostly agree."""
+    w = W.make_tiny(2, kinds=("pas", "hh", "cahva", "syn"), n_nodes=40, syn_per_node=6.0,
+                    vmode="isolated", event_rate_hz=300.0, nsteps=600)
+    w.area[:] = np.linspace(100.0, 400.0, w.n_nodes)
+    w.slots[-1].params["weight"][:] *= 6.0
+    got, m = run_gpu(w, 600, path, "fp32")
+    M = run_oracle(w, 600)
+    match = np.mean(got["spikes"] == M.spikes)
+    log(f"isolated fp32 {path}: spike match {match:.3f}, max |dv| {np.max(np.abs(got['v'] - M.v)):.3g} mV")
+    assert match >= 0.9
+
+
+def test_external_phase_calls():
+    """mech_cur / mech_state one phase at a time with the caller moving v."""
+    from paper_1905_02241_amd import mech
+    from oracle import oracle as O
+    w = W.make_tiny(3, per_node=1, vmode="external", nsteps=10)
+    m = mech.from_workload(w, "fp64")
+    M = O.Model(w)
+    M.init()
+    rng = np.random.default_rng(0)
+    for k in range(10):
+        m.cur(k, w.dt)
+        M.events(k)
+        M.cur()
+        got = {**m.nodes(), "states": mech.states_of(m)}
+        compare_nodes(got, M, "fp64", label=f"cur k={k}", check_v=False)
+        v = rng.uniform(-80, 30, w.n_nodes)
+        m.set_node_array("v", v)
+        M.v[:] = v
+        m.state(w.dt)
+        M.state()
+        compare_states({"states": mech.states_of(m)}, M, "fp64", label=f"state k={k}")
+
+
+def test_accumulate_adds_to_existing_rhs():
+    from paper_1905_02241_amd import mech
+    w = W.make_tiny(4, per_node=1, vmode="external")
+    m = mech.from_workload(w, "fp64")
+    m.cur(0, w.dt)
+    a = m.nodes()
+    m.cur(0, w.dt, accumulate=True)   # events of the same step fire again: compare pas-only
+    w2 = W.make_tiny(4, kinds=("pas", "hh"), per_node=1, vmode="external")
+    m2 = mech.from_workload(w2, "fp64")
+    m2.cur(0, w2.dt)
+    r1 = m2.nodes()
+    m2.cur(0, w2.dt, accumulate=True)
+    r2 = m2.nodes()
+    assert np.allclose(r2["rhs"], 2 * r1["rhs"], rtol=1e-14, atol=1e-300)
+    assert np.allclose(r2["d"], 2 * r1["d"], rtol=1e-14, atol=1e-300)
+    assert a["rhs"].shape == (w.n_nodes,)
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_node_index_bit_exact(path):
+    """Dyadic conductances, reversals, voltages and dv make every product and
+    sum exact, so rhs and d must equal numpy's np.add.at bit for bit, whatever
+    the reduction order (global atomics, LDS atomics)."""
+    from paper_1905_02241_amd import mech
+    rng = np.random.default_rng(5)
+    n_nodes = 3000
+    node = rng.integers(0, n_nodes, 20000).astype(np.int32)
+    g = rng.integers(1, 64, node.shape[0]) * 2.0 ** -12
+    e = rng.integers(-90, 10, node.shape[0]).astype(float)
+    m = mech.Mechanisms(n_nodes, [("pas", node)], prec="fp64")
+    m.set_params(0, "g", g)
+    m.set_params(0, "e", e)
+    m.set_global("fd_dv", 2.0 ** -10)
+    m.set_launch(128, 512, 256, 0)
+    v = rng.integers(-100, 40, n_nodes).astype(float)
+    m.set_node_array("v", v)
+    m.init()
+    m.step(1, 0, 0.025, "external", path)
+    got = m.nodes()
+    rhs = np.zeros(n_nodes)
+    d = np.zeros(n_nodes)
+    np.add.at(rhs, node, -g * (v[node] - e))
+    np.add.at(d, node, g)
+    assert np.array_equal(got["rhs"], rhs)
+    assert np.array_equal(got["d"], d)
+
+
+def test_events_fire_exactly_as_oracle():
+    """Integer event decisions: after one step from rest the synapses that
+    fired are exactly the oracle's, and their states agree to rounding."""
+    w = W.make_tiny(6, kinds=("syn",), n_nodes=500, syn_per_node=8.0, event_rate_hz=2000.0, nsteps=1)
+    got, m = run_gpu(w, 1, "batched", "fp64")
+    M = run_oracle(w, 1)
+    a_gpu = got["states"][0]["B_nmda"]
+    a_orc = M.states[0]["B_nmda"]
+    assert np.count_nonzero(a_orc) > 20
+    assert np.array_equal(a_gpu != 0, a_orc != 0)
+    assert np.allclose(a_gpu, a_orc, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_launch_shapes_give_identical_states_under_clamp(prec):
+    """Under a clamp the states do not depend on rhs/d, and each instance's
+    update is independent of the launch shape: bit-identical states."""
+    w = W.make_tiny(8, per_node=2, n_nodes=700, nsteps=40)
+    base = None
+    for shape in [(64, 64, 64, 0), (256, 2048, 1024, 0), (512, 4096, 2048, 4), (128, 1024, 512, 1)]:
+        got, m = run_gpu(w, 40, "batched", prec, launch=shape)
+        if base is None:
+            base = got
+            continue
+        for s in range(len(w.slots)):
+            for name, a in got["states"][s].items():
+                assert np.array_equal(a, base["states"][s][name]), (shape, s, name)
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_medium_several_tiles_ragged(path):
+    """5000 nodes, many small tiles and a ragged tail, all types."""
+    w = W.make_tiny(10, n_nodes=5003, per_node=1, syn_per_node=2.5, nsteps=100, shuffle=True,
+                    density_fraction=0.7)
+    got, m = run_gpu(w, 100, path, "fp64", launch=(128, 384, 256, 0))
+    info = m.info()
+    log(f"medium {path}: {info}")
+    assert info["n_tiles"] > 20
+    M = run_oracle(w, 100)
+    compare_states(got, M, "fp64", label="medium")
+    compare_nodes(got, M, "fp64", label="medium")
+
+
+def test_empty_and_degenerate_inputs():
+    """No instances at all, a type with zero instances, nodes without
+    instances, zero steps."""
+    from paper_1905_02241_amd import mech
+    m = mech.Mechanisms(10, [("hh", np.zeros(0, np.int32)), ("pas", np.array([3, 3, 7], np.int32))])
+    m.init()
+    m.step(0, 0, 0.025, "clamp", "batched")
+    m.step(5, 0, 0.025, "external", "batched")
+    m.step(5, 0, 0.025, "external", "plain")
+    got = m.nodes()
+    assert np.count_nonzero(got["rhs"]) <= 2
+    m2 = mech.Mechanisms(4, [])
+    m2.init()
+    m2.step(3, 0, 0.025, "isolated", "batched")
+    m2.sync()
+
+
+def test_error_paths():
+    from paper_1905_02241_amd import mech
+    m = mech.Mechanisms(8, [("hh", np.arange(8, dtype=np.int32))])
+    with pytest.raises(mech.MechError) as e:
+        m.set_params(0, "nope", [1.0])
+    assert e.value.code == mech.ERR_INVAL
+    with pytest.raises(mech.MechError) as e:
+        m.set_params(0, "gnabar", [1.0, 2.0])
+    assert e.value.code == mech.ERR_INVAL
+    with pytest.raises(mech.MechError) as e:
+        m.step(1, 0, -0.025, "clamp", "plain")
+    assert e.value.code == mech.ERR_INVAL
+    with pytest.raises(mech.MechError) as e:
+        m.set_launch(100, 128, 128, 0)
+    assert e.value.code == mech.ERR_INVAL
+    # a planted non-finite state is reported at the next sync
+    m.init()
+    m.set_state(0, "m", np.full(8, np.nan))
+    m.step(1, 0, 0.025, "clamp", "batched")
+    with pytest.raises(mech.MechError) as e:
+        m.sync()
+    assert e.value.code == mech.ERR_NONFINITE
+    m.sync()   # the flag clears
+
+
+def test_checkpoint_resume_is_exact():
+    """get_state after k steps, set_state into a fresh context, continue:
+    identical to the uninterrupted run (clamp mode, batched path)."""
+    from paper_1905_02241_amd import mech
+    w = W.make_tiny(12, per_node=1, nsteps=80)
+    full, _ = run_gpu(w, 80, "batched", "fp64")
+    a = mech.from_workload(w, "fp64")
+    a.step(30, 0, w.dt, "clamp", "batched")
+    saved = mech.states_of(a)
+    b = mech.from_workload(w, "fp64")
+    for s, st in enumerate(saved):
+        for name, vals in st.items():
+            b.set_state(s, name, vals)
+    b.step(50, 30, w.dt, "clamp", "batched")
+    b.sync()
+    res = mech.states_of(b)
+    for s in range(len(w.slots)):
+        for name, vals in res[s].items():
+            if name == "ica":
+                continue
+            assert np.array_equal(vals, full["states"][s][name]), (s, name)
+
+
+def test_autotune_keeps_results():
+    from paper_1905_02241_amd import mech
+    w = W.make_tiny(13, n_nodes=3000, per_node=1, nsteps=20)
+    m = mech.from_workload(w, "fp64")
+    before = mech.states_of(m)
+    ms = m.autotune(w.dt, "clamp", nsteps=4, reps=2)
+    after = mech.states_of(m)
+    assert ms > 0
+    for s in range(len(w.slots)):
+        for name in before[s]:
+            assert np.array_equal(before[s][name], after[s][name])
+    got, _ = run_gpu(w, 20, "batched", "fp64", launch=m.get_launch())
+    M = run_oracle(w, 20)
+    compare_states(got, M, "fp64", label="autotuned")
+
+
+# ------------------------------------------------------------ configs --
+@pytest.mark.parametrize("path", PATHS)
+def test_config1_hh_clamp_full(path):
+    """hh on 10,000 nodes, constant clamps U[-80, 40] mV, 1000 steps, FP64."""
+    w = W.make_c1()
+    with Timer() as tg:
+        got, m = run_gpu(w, w.nsteps, path, "fp64")
+    with Timer() as to:
+        M = run_oracle(w, w.nsteps)
+    ws = compare_states(got, M, "fp64", label="c1")
+    log(f"c1 {path}: gpu {tg.dt:.2f}s oracle {to.dt:.2f}s worst {max(v[0] for v in ws.values()):.3g}")
+
+
+def test_config1_fp32_within_1e5():
+    w = W.make_c1()
+    got, m = run_gpu(w, w.nsteps, "batched", "fp32")
+    M = run_oracle(w, w.nsteps)
+    ws = compare_states(got, M, "fp32", label="c1 fp32")
+    log(f"c1 fp32: max abs err {max(v[1] for v in ws.values()):.3g}")
+
+
+def _sampled(cfg, nsteps, prec, path, n_sample, seed=99):
+    w = W.make_config(cfg)
+    with Timer() as tg:
+        got, m = run_gpu(w, nsteps, path, prec)
+    rng = np.random.default_rng(seed)
+    nodes = np.sort(rng.choice(w.n_nodes, size=n_sample, replace=False))
+    sub, keep = W.subset(w, nodes)
+    with Timer() as to:
+        M = run_oracle(sub, nsteps)
+    ws = compare_states(got, M, prec, keep=keep, label=f"c{cfg}")
+    sub_got = {k: got[k] for k in ("v", "rhs", "d")}
+    wn = compare_nodes(sub_got, M, prec, nodes=nodes, label=f"c{cfg}", check_v=(w.vmode != "isolated" or prec == "fp64"))
+    log(f"c{cfg} {prec} {path}: gpu {tg.dt:.1f}s oracle(sample {n_sample}) {to.dt:.1f}s "
+        f"worst state {max(v[0] for v in ws.values()):.3g} nodes {wn}")
+    return got, M, nodes
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_config2_sampled(prec):
+    _sampled(2, 4000, prec, "batched", 1500)
+
+
+def test_config2_plain_fp64_sampled():
+    _sampled(2, 1000, "fp64", "plain", 800)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_config3_sampled(prec):
+    _sampled(3, 2000, prec, "batched", 300)
+
+
+def test_config3_plain_fp64_sampled():
+    _sampled(3, 500, "fp64", "plain", 200)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_config4_sampled(prec):
+    _sampled(4, 2000, prec, "batched", 800)
+
+
+def test_config5_fp64_sampled_spikes():
+    got, M, nodes = _sampled(5, 2000, "fp64", "batched", 1500)
+    assert np.array_equal(got["spikes"][nodes], M.spikes)
+    log(f"c5 spikes on sample: {int(M.spikes.sum())}")
