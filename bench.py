@@ -56,13 +56,16 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def time_variant(w, prec, path, steps, warmup, autotune, torch, mech):
+def time_variant(w, prec, path, steps, warmup, autotune, torch, mech, launch=None):
     t0 = time.perf_counter()
     m = mech.from_workload(w, prec)
     torch.cuda.synchronize()
     log(f"{prec}-{path}: context ready in {time.perf_counter() - t0:.1f}s ({m.nbytes / 1e9:.2f} GB)")
     tuned = None
-    if path == "batched" and autotune:
+    if path == "batched" and launch is not None:
+        m.set_launch(*launch)
+        tuned = {"launch": m.get_launch(), "ms_per_step": None}
+    elif path == "batched" and autotune:
         ms = m.autotune(w.dt, w.vmode, nsteps=5, reps=3)
         tuned = {"launch": m.get_launch(), "ms_per_step": ms}
         log(f"{prec}-{path}: autotuned {tuned}")
@@ -126,6 +129,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-nodes", type=int, default=20000)
+    ap.add_argument("--launch", default=None,
+                    help="fixed batched launch shape 'block,tile_instances,tile_nodes,blocks_per_cu' (no autotune)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -148,7 +153,8 @@ def main():
     res = {}
     for v in args.variants.split(","):
         prec, path = v.split("-")
-        res[v] = time_variant(w, prec, path, args.steps, args.warmup, not args.no_autotune, torch, mech)
+        launch = tuple(int(x) for x in args.launch.split(",")) if args.launch else None
+        res[v] = time_variant(w, prec, path, args.steps, args.warmup, not args.no_autotune, torch, mech, launch)
 
     head_key = "fp64-batched" if "fp64-batched" in res else next(iter(res))
     head = res[head_key]
