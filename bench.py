@@ -56,19 +56,27 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def time_variant(w, prec, path, steps, warmup, autotune, torch, mech, launch=None):
+def time_variant(w, prec, path, steps, warmup, autotune, torch, mech, launch=None, save_tuning=None):
     t0 = time.perf_counter()
     m = mech.from_workload(w, prec)
     torch.cuda.synchronize()
     log(f"{prec}-{path}: context ready in {time.perf_counter() - t0:.1f}s ({m.nbytes / 1e9:.2f} GB)")
     tuned = None
-    if path == "batched" and launch is not None:
-        m.set_launch(*launch)
-        tuned = {"launch": m.get_launch(), "ms_per_step": None}
-    elif path == "batched" and autotune:
-        ms = m.autotune(w.dt, w.vmode, nsteps=5, reps=3)
-        tuned = {"launch": m.get_launch(), "ms_per_step": ms}
-        log(f"{prec}-{path}: autotuned {tuned}")
+    if path == "batched":
+        from paper_1905_02241_amd import tuning
+        cached = tuning.lookup(w, prec)
+        if launch is not None:
+            m.set_launch(*launch)
+            tuned = {"launch": m.get_launch(), "source": "--launch"}
+        elif cached is not None and not autotune:
+            m.set_launch(*cached)
+            tuned = {"launch": m.get_launch(), "source": "tuning cache"}
+        else:
+            ms = m.autotune(w.dt, w.vmode, nsteps=5, reps=3)
+            tuned = {"launch": m.get_launch(), "source": "autotuned", "ms_per_step": ms}
+            if save_tuning:
+                tuning.record(w, prec, m.get_launch(), ms, path=save_tuning)
+        log(f"{prec}-{path}: launch {tuned}")
     m.step(warmup, 0, w.dt, w.vmode, path)
     m.sync()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -125,7 +133,10 @@ def main():
     ap.add_argument("--config", type=int, default=5)
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--variants", default="fp64-plain,fp64-batched,fp32-batched")
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the launch-shape autotuner even when the tuning cache has an entry")
+    ap.add_argument("--save-tuning", default=None, help="JSON file to record autotuned shapes in")
+    ap.add_argument("--no-probe", action="store_true", help="skip the streaming-copy ceiling probe")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-nodes", type=int, default=20000)
@@ -154,7 +165,13 @@ def main():
     for v in args.variants.split(","):
         prec, path = v.split("-")
         launch = tuple(int(x) for x in args.launch.split(",")) if args.launch else None
-        res[v] = time_variant(w, prec, path, args.steps, args.warmup, not args.no_autotune, torch, mech, launch)
+        res[v] = time_variant(w, prec, path, args.steps, args.warmup, args.autotune, torch, mech, launch,
+                              args.save_tuning)
+
+    probe = None
+    if not args.no_probe:
+        probe = max(mech.probe_stream("copy", 1 << 32, unroll=u, blocks_per_cu=b) for u in (2, 4, 8) for b in (4, 16))
+        log(f"copy probe: {probe:.0f} GB/s (read + write, 4 GiB, best of unroll 2/4/8 x 4/16 blocks per CU)")
 
     head_key = "fp64-batched" if "fp64-batched" in res else next(iter(res))
     head = res[head_key]
@@ -178,7 +195,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_fused (state+cur, isolated)",
-                     "alg_bytes_per_launch": head["alg_bytes_per_step"]},
+                     "alg_bytes_per_launch": head["alg_bytes_per_step"],
+                     "copy_probe_GBps": probe,
+                     "frac_of_copy_probe": (achieved / probe) if probe else None},
         "variants": res,
     }
     if "fp32-batched" in res and "fp64-plain" in res:

@@ -168,11 +168,18 @@ int mech_step(mech_ctx *ctx, int64_t nsteps, int64_t k0, double dt, int vmode, i
 
 /* Launch shape of the BATCHED path: threads per block (64..1024, multiple
  * of 64), tile work budget in instances (>= block), node span per tile
- * (64..4096) and blocks per CU of a persistent grid (0: one block per
- * tile).  Rebuilds the tile table.                                         */
-int mech_set_launch(mech_ctx *ctx, int block, int tile_instances, int tile_nodes, int blocks_per_cu);
+ * (64..2048), blocks per CU of a persistent grid (0: one block per tile)
+ * and flags (MECH_LAUNCH_XCD_ORDER: consecutive tiles on the same XCD, so
+ * the cache lines two neighbouring tiles share stay in one L2;
+ * MECH_LAUNCH_NONTEMPORAL: instance arrays streamed with the non-temporal
+ * hint, as they are touched once per step).  Rebuilds
+ * the tile table.  Results do not depend on the shape except for the
+ * rounding order of rhs/d.                                                 */
+enum { MECH_LAUNCH_XCD_ORDER = 1, MECH_LAUNCH_NONTEMPORAL = 2 };
+int mech_set_launch(mech_ctx *ctx, int block, int tile_instances, int tile_nodes, int blocks_per_cu,
+                    int flags);
 int mech_get_launch(const mech_ctx *ctx, int *block, int *tile_instances, int *tile_nodes,
-                    int *blocks_per_cu);
+                    int *blocks_per_cu, int *flags);
 
 /* Time every candidate launch shape of the BATCHED path on `nsteps` steps
  * (HIP events, median of `reps`), keep the fastest, and return its ms per
@@ -194,6 +201,17 @@ int mech_sync(mech_ctx *ctx);
 
 /* Number of tiles of the BATCHED path and the instance count of slot s.   */
 int mech_info(const mech_ctx *ctx, int64_t *n_tiles, int64_t *max_tile_nodes);
+
+/* Measurement aid (not part of a timestep): stream `bytes` (a multiple of
+ * 16; device pointers, 16-byte aligned) with a grid-stride kernel of
+ * blocks_per_cu * n_CU blocks of 256 threads on `hip_stream`, each thread
+ * keeping `unroll` (1, 2, 4, 8) independent 16-byte accesses in flight:
+ * op 0 copies src to dst, op 1 reads src (dst receives at most 16 bytes),
+ * op 2 writes dst, op 3 reads src[0, bytes) and src[bytes, 2 bytes) and
+ * writes their xor to dst (two reads per write).  The streaming HBM ceiling the mechanism kernels are
+ * compared with.  Asynchronous.                                            */
+int mech_probe_stream(int op, int unroll, int blocks_per_cu, void *dst, const void *src, size_t bytes,
+                      void *hip_stream);
 
 const char *mech_last_error(const mech_ctx *ctx);
 const char *mech_strerror(int code);

@@ -68,6 +68,8 @@ struct FusedArgs {
     int row;                   // 1 + n_slots
     const long long *kdev;     // step counter in device memory
     int kofs;                  // k = *kdev + kofs
+    int xcd_order;             // XCD-contiguous tile order (launch flag bit 0)
+    int nontemporal;           // non-temporal SoA streams (launch flag bit 1)
     int *err;
     GlobDev g;
     NodesDev nd;
@@ -92,6 +94,7 @@ hipError_t launch_visolated(const NodesDev &nd, const GlobDev &g, hipStream_t s)
 hipError_t launch_init(bool fp32, const PlainArgs &a, hipStream_t s);
 hipError_t launch_plain_cur(bool fp32, const PlainArgs &a, hipStream_t s);
 hipError_t launch_plain_state(bool fp32, const PlainArgs &a, hipStream_t s);
+hipError_t launch_stream(int op, int unroll, void *dst, const void *src, size_t n16, int grid, hipStream_t s);
 hipError_t launch_fused(bool fp32, int phases, int vmode, const FusedArgs &a, int grid, int block,
                         size_t lds_bytes, hipStream_t s);
 

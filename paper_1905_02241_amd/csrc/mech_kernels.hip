@@ -242,63 +242,74 @@ __device__ __forceinline__ void syn_cur(double v, const S *x, const GlobDev &g, 
 template <class S> __device__ __forceinline__ int bad(S x) { return isfinite(x) ? 0 : 1; }
 
 // -------------------------------------------------- instance update ----
+// Streamed SoA accesses, optionally with the non-temporal hint (the arrays
+// are touched once per step, so they need not displace reusable lines).
+template <bool NT, class T> __device__ __forceinline__ T ld(const T *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NT, class T> __device__ __forceinline__ void st(T *p, T v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 // One instance of a slot: state update (if PH has kDoState) at v, events and
 // current (if kDoCur) at the same v.  Returns the current and conductance
 // contributions for the node and stores the new STATEs.
-template <class S, int KIND, int PH>
+template <class S, int KIND, int PH, bool NT = false>
 __device__ __forceinline__ void instance(const SlotDev &sl, int i, double v, const GlobDev &g, long long k,
                                          double &ci, double &cg, int &flag) {
     ci = 0.0;
     cg = 0.0;
     if constexpr (KIND == MECH_PAS) {
         if (PH & kDoCur) {
-            const S gp = ((const S *)sl.par[0])[i];
-            const double e = ((const double *)sl.par[1])[i];
+            const S gp = ld<NT>((const S *)sl.par[0] + i);
+            const double e = ld<NT>((const double *)sl.par[1] + i);
             lin_cur<S>(v, gp, e, g, ci, cg);
         }
     } else if constexpr (KIND == MECH_HH) {
         S *M = (S *)sl.st[0], *H = (S *)sl.st[1], *N = (S *)sl.st[2];
-        S m = M[i], h = H[i], n = N[i];
+        S m = ld<NT>(M + i), h = ld<NT>(H + i), n = ld<NT>(N + i);
         if (PH & kDoState) {
             hh_state(v, g, m, h, n);
             flag |= bad(m) | bad(h) | bad(n);
-            M[i] = m; H[i] = h; N[i] = n;
+            st<NT>(M + i, m); st<NT>(H + i, h); st<NT>(N + i, n);
         }
         if (PH & kDoCur) {
-            const S gnabar = ((const S *)sl.par[0])[i];
-            const S gkbar = ((const S *)sl.par[1])[i];
-            const S gl = ((const S *)sl.par[2])[i];
-            const double el = ((const double *)sl.par[3])[i];
+            const S gnabar = ld<NT>((const S *)sl.par[0] + i);
+            const S gkbar = ld<NT>((const S *)sl.par[1] + i);
+            const S gl = ld<NT>((const S *)sl.par[2] + i);
+            const double el = ld<NT>((const double *)sl.par[3] + i);
             hh_cur<S>(v, m, h, n, gnabar, gkbar, gl, el, g, ci, cg);
         }
     } else if constexpr (KIND == MECH_IH) {
         S *M = (S *)sl.st[0];
-        S m = M[i];
+        S m = ld<NT>(M + i);
         if (PH & kDoState) {
             ih_state(v, g, m);
             flag |= bad(m);
-            M[i] = m;
+            st<NT>(M + i, m);
         }
         if (PH & kDoCur) {
-            const S gbar = ((const S *)sl.par[0])[i];
+            const S gbar = ld<NT>((const S *)sl.par[0] + i);
             lin_cur<S>(v, (S)(gbar * m), g.eh, g, ci, cg);
         }
     } else if constexpr (KIND == MECH_CAHVA) {
         S *M = (S *)sl.st[0], *H = (S *)sl.st[1], *CAI = (S *)sl.st[2], *ICA = (S *)sl.ica;
-        S m = M[i], h = H[i], cai = CAI[i];
+        S m = ld<NT>(M + i), h = ld<NT>(H + i), cai = ld<NT>(CAI + i);
         if (PH & kDoState) {
-            ca_state(v, g, ICA[i], m, h, cai);
+            ca_state(v, g, ld<NT>(ICA + i), m, h, cai);
             flag |= bad(m) | bad(h) | bad(cai);
-            M[i] = m; H[i] = h; CAI[i] = cai;
+            st<NT>(M + i, m); st<NT>(H + i, h); st<NT>(CAI + i, cai);
         }
         if (PH & kDoCur) {
-            const S gbar = ((const S *)sl.par[0])[i];
-            ICA[i] = (S)ca_cur<S>(v, m, h, cai, gbar, g, ci, cg);
+            const S gbar = ld<NT>((const S *)sl.par[0] + i);
+            st<NT>(ICA + i, (S)ca_cur<S>(v, m, h, cai, gbar, g, ci, cg));
         }
     } else if constexpr (KIND == MECH_SYN) {
         S x[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) x[j] = ((S *)sl.st[j])[i];
+        for (int j = 0; j < 4; ++j) x[j] = ld<NT>((const S *)sl.st[j] + i);
         if (PH & kDoState) syn_decay(x, g);
         if (PH & kDoCur) {
             const unsigned long long id = sl.gid ? (unsigned long long)(long long)sl.gid[i]
@@ -314,7 +325,7 @@ __device__ __forceinline__ void instance(const SlotDev &sl, int i, double v, con
         }
         flag |= bad(x[0]) | bad(x[1]) | bad(x[2]) | bad(x[3]);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) ((S *)sl.st[j])[i] = x[j];
+        for (int j = 0; j < 4; ++j) st<NT>((S *)sl.st[j] + i, x[j]);
     }
 }
 
@@ -420,14 +431,15 @@ __global__ void k_visolated(NodesDev nd, GlobDev g) {
 
 // ---------------------------------------------------------- fused path --
 // LDS per tile node: v, 100/area, rhs and d accumulators (4 doubles).
-template <class S, int KIND, int PH>
+template <class S, int KIND, int PH, bool NT>
 __device__ __forceinline__ void tile_slot(const SlotDev &sl, int lo, int hi, int nlo, const double *vl,
                                           const double *sc, double *ar, double *ad, const GlobDev &g,
                                           long long k, int &flag) {
     for (int i = lo + (int)threadIdx.x; i < hi; i += (int)blockDim.x) {
-        const int j = sl.ni[i] - nlo;
+        // an identity slot (instance i on node i) needs no index load
+        const int j = (sl.identity ? i : ld<NT>(sl.ni + i)) - nlo;
         double ci, cg;
-        instance<S, KIND, PH>(sl, i, vl[j], g, k, ci, cg, flag);
+        instance<S, KIND, PH, NT>(sl, i, vl[j], g, k, ci, cg, flag);
         if (PH & kDoCur) {
             if (KIND == MECH_SYN) {
                 ci *= sc[j];
@@ -439,13 +451,25 @@ __device__ __forceinline__ void tile_slot(const SlotDev &sl, int lo, int hi, int
     }
 }
 
-template <class S, int PH, int VM>
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on
+// XCD b mod 8), each with its own L2.  With XCD-contiguous ordering the
+// virtual workgroup b processes tile start(x) + b/8 of XCD x = b mod 8, so
+// neighbouring tiles, which share the cache lines at their boundaries, sit
+// in the same L2.  A bijection of [0, T) for any T.
+__device__ __forceinline__ int tile_of(int b, int T, int xcd_order) {
+    if (!xcd_order) return b;
+    const int x = b & 7, j = b >> 3, q = T >> 3, r = T & 7;
+    return x * q + min(x, r) + j;
+}
+
+template <class S, int PH, int VM, bool NT>
 __global__ __launch_bounds__(1024) void k_fused(FusedArgs a, int tn) {
     extern __shared__ double lds[];
     double *vl = lds, *sc = lds + tn, *ar = lds + 2 * tn, *ad = lds + 3 * tn;
     const long long k = *a.kdev + a.kofs;
     int flag = 0;
-    for (int t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
+    for (int b = blockIdx.x; b < a.n_tiles; b += gridDim.x) {
+        const int t = tile_of(b, a.n_tiles, a.xcd_order);
         const int *r0 = a.tiles + (size_t)t * a.row;
         const int *r1 = r0 + a.row;
         const int nlo = r0[0], nn = r1[0] - nlo;
@@ -463,12 +487,12 @@ __global__ __launch_bounds__(1024) void k_fused(FusedArgs a, int tn) {
             const int lo = r0[1 + s], hi = r1[1 + s];
             switch (sl.kind) {
             case MECH_PAS:
-                if (PH & kDoCur) tile_slot<S, MECH_PAS, PH>(sl, lo, hi, nlo, vl, sc, ar, ad, a.g, k, flag);
+                if (PH & kDoCur) tile_slot<S, MECH_PAS, PH, NT>(sl, lo, hi, nlo, vl, sc, ar, ad, a.g, k, flag);
                 break;
-            case MECH_HH: tile_slot<S, MECH_HH, PH>(sl, lo, hi, nlo, vl, sc, ar, ad, a.g, k, flag); break;
-            case MECH_IH: tile_slot<S, MECH_IH, PH>(sl, lo, hi, nlo, vl, sc, ar, ad, a.g, k, flag); break;
-            case MECH_CAHVA: tile_slot<S, MECH_CAHVA, PH>(sl, lo, hi, nlo, vl, sc, ar, ad, a.g, k, flag); break;
-            case MECH_SYN: tile_slot<S, MECH_SYN, PH>(sl, lo, hi, nlo, vl, sc, ar, ad, a.g, k, flag); break;
+            case MECH_HH: tile_slot<S, MECH_HH, PH, NT>(sl, lo, hi, nlo, vl, sc, ar, ad, a.g, k, flag); break;
+            case MECH_IH: tile_slot<S, MECH_IH, PH, NT>(sl, lo, hi, nlo, vl, sc, ar, ad, a.g, k, flag); break;
+            case MECH_CAHVA: tile_slot<S, MECH_CAHVA, PH, NT>(sl, lo, hi, nlo, vl, sc, ar, ad, a.g, k, flag); break;
+            case MECH_SYN: tile_slot<S, MECH_SYN, PH, NT>(sl, lo, hi, nlo, vl, sc, ar, ad, a.g, k, flag); break;
             default: break;
             }
         }
@@ -486,6 +510,58 @@ __global__ __launch_bounds__(1024) void k_fused(FusedArgs a, int tn) {
         __syncthreads();
     }
     if (flag) atomicOr(a.err, 1);
+}
+
+// --------------------------------------------------------- HBM probe --
+// Streaming probes that set the achievable ceiling the kernels are held to:
+// op 0 copy, op 1 read (xor-reduced so the loads stay live), op 2 write,
+// op 3 two reads and one write (dst = src_a ^ src_b, the STREAM-triad mix).
+// Each thread keeps U independent 16-byte accesses in flight per round.
+template <int OP, int U>
+__global__ __launch_bounds__(256) void k_stream(uint4 *__restrict__ dst, const uint4 *__restrict__ src, size_t n,
+                                                 uint4 *__restrict__ sink) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint4 acc = make_uint4(0u, 0u, 0u, 0u);
+    for (; i + (U - 1) * stride < n; i += U * stride) {
+        uint4 x[U], y[U];
+        if (OP != 2) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) x[u] = src[i + u * stride];
+        }
+        if (OP == 3) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) y[u] = src[n + i + u * stride];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (OP == 0) dst[i + u * stride] = x[u];
+            if (OP == 3) dst[i + u * stride] = make_uint4(x[u].x ^ y[u].x, x[u].y ^ y[u].y, x[u].z ^ y[u].z, x[u].w ^ y[u].w);
+            if (OP == 1) { acc.x ^= x[u].x; acc.y ^= x[u].y; acc.z ^= x[u].z; acc.w ^= x[u].w; }
+            if (OP == 2) dst[i + u * stride] = make_uint4((unsigned)i, 0u, 0u, (unsigned)u);
+        }
+    }
+    for (; i < n; i += stride) {
+        if (OP == 0) dst[i] = src[i];
+        if (OP == 3) { const uint4 x = src[i], y = src[n + i]; dst[i] = make_uint4(x.x ^ y.x, x.y ^ y.y, x.z ^ y.z, x.w ^ y.w); }
+        if (OP == 1) { const uint4 x = src[i]; acc.x ^= x.x; acc.y ^= x.y; acc.z ^= x.z; acc.w ^= x.w; }
+        if (OP == 2) dst[i] = make_uint4((unsigned)i, 0u, 0u, 0u);
+    }
+    if (OP == 1 && (acc.x | acc.y | acc.z | acc.w) == 0x9E3779B9u) sink[0] = acc;  // practically never
+}
+
+hipError_t launch_stream(int op, int unroll, void *dst, const void *src, size_t n16, int grid, hipStream_t s) {
+    if (n16 == 0) return hipSuccess;
+    uint4 *d = (uint4 *)dst;
+    const uint4 *r = (const uint4 *)src;
+#define MECH_STREAM_CASE(O, U) \
+    if (op == O && unroll == U) { k_stream<O, U><<<grid, 256, 0, s>>>(d, r, n16, d); return hipGetLastError(); }
+    MECH_STREAM_CASE(0, 1) MECH_STREAM_CASE(0, 2) MECH_STREAM_CASE(0, 4) MECH_STREAM_CASE(0, 8)
+    MECH_STREAM_CASE(1, 1) MECH_STREAM_CASE(1, 2) MECH_STREAM_CASE(1, 4) MECH_STREAM_CASE(1, 8)
+    MECH_STREAM_CASE(2, 1) MECH_STREAM_CASE(2, 2) MECH_STREAM_CASE(2, 4) MECH_STREAM_CASE(2, 8)
+    MECH_STREAM_CASE(3, 1) MECH_STREAM_CASE(3, 2) MECH_STREAM_CASE(3, 4) MECH_STREAM_CASE(3, 8)
+#undef MECH_STREAM_CASE
+    return hipErrorInvalidValue;
 }
 
 // ------------------------------------------------------------ launchers --
@@ -568,31 +644,36 @@ hipError_t launch_plain_state(bool fp32, const PlainArgs &a, hipStream_t s) {
     return fp32 ? state_t<float>(a, s) : state_t<double>(a, s);
 }
 
-template <class S, int PH>
+template <class S, int PH, bool NT>
 static hipError_t fused_vm(int vmode, const FusedArgs &a, int grid, int block, size_t lds, int tn,
                            hipStream_t s) {
     switch (vmode) {
-    case MECH_V_CLAMP: k_fused<S, PH, MECH_V_CLAMP><<<grid, block, lds, s>>>(a, tn); break;
-    case MECH_V_ISOLATED: k_fused<S, PH, MECH_V_ISOLATED><<<grid, block, lds, s>>>(a, tn); break;
-    default: k_fused<S, PH, MECH_V_EXTERNAL><<<grid, block, lds, s>>>(a, tn); break;
+    case MECH_V_CLAMP: k_fused<S, PH, MECH_V_CLAMP, NT><<<grid, block, lds, s>>>(a, tn); break;
+    case MECH_V_ISOLATED: k_fused<S, PH, MECH_V_ISOLATED, NT><<<grid, block, lds, s>>>(a, tn); break;
+    default: k_fused<S, PH, MECH_V_EXTERNAL, NT><<<grid, block, lds, s>>>(a, tn); break;
     }
     return hipGetLastError();
 }
-template <class S>
+template <class S, bool NT>
 static hipError_t fused_t(int phases, int vmode, const FusedArgs &a, int grid, int block, size_t lds, int tn,
                           hipStream_t s) {
     switch (phases) {
-    case kDoCur: return fused_vm<S, kDoCur>(vmode, a, grid, block, lds, tn, s);
-    case kDoState: k_fused<S, kDoState, MECH_V_EXTERNAL><<<grid, block, lds, s>>>(a, tn); return hipGetLastError();
-    default: return fused_vm<S, kDoCur | kDoState>(vmode, a, grid, block, lds, tn, s);
+    case kDoCur: return fused_vm<S, kDoCur, NT>(vmode, a, grid, block, lds, tn, s);
+    case kDoState:
+        k_fused<S, kDoState, MECH_V_EXTERNAL, NT><<<grid, block, lds, s>>>(a, tn);
+        return hipGetLastError();
+    default: return fused_vm<S, kDoCur | kDoState, NT>(vmode, a, grid, block, lds, tn, s);
     }
 }
 hipError_t launch_fused(bool fp32, int phases, int vmode, const FusedArgs &a, int grid, int block,
                         size_t lds_bytes, hipStream_t s) {
     if (a.n_tiles == 0 || grid == 0) return hipSuccess;
     const int tn = (int)(lds_bytes / (4 * sizeof(double)));
-    return fp32 ? fused_t<float>(phases, vmode, a, grid, block, lds_bytes, tn, s)
-                : fused_t<double>(phases, vmode, a, grid, block, lds_bytes, tn, s);
+    if (a.nontemporal)
+        return fp32 ? fused_t<float, true>(phases, vmode, a, grid, block, lds_bytes, tn, s)
+                    : fused_t<double, true>(phases, vmode, a, grid, block, lds_bytes, tn, s);
+    return fp32 ? fused_t<float, false>(phases, vmode, a, grid, block, lds_bytes, tn, s)
+                : fused_t<double, false>(phases, vmode, a, grid, block, lds_bytes, tn, s);
 }
 
 }  // namespace mech

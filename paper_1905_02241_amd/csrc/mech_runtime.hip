@@ -122,7 +122,7 @@ struct mech_ctx {
     NodesDev nd{};
     bool nodes_bound = false, clamp_bound = false, has_syn = false;
     // fused-path launch shape and tile table
-    int block = 256, tile_budget = 2048, tile_nodes = 1024, blocks_per_cu = 0;
+    int block = 256, tile_budget = 2048, tile_nodes = 1024, blocks_per_cu = 0, launch_flags = MECH_LAUNCH_XCD_ORDER;
     int64_t n_tiles = 0, max_tile_nodes = 0;
     int n_cu = 256;
     // graphs of kGraphSteps fused steps, keyed by (vmode, dt)
@@ -334,6 +334,8 @@ FusedArgs fused_args(mech_ctx *c, const GlobDev &g, int kofs) {
     a.row = 1 + (int)c->slots.size();
     a.kdev = (const long long *)(c->buf + c->L.off_kdev);
     a.kofs = kofs;
+    a.xcd_order = (c->launch_flags & MECH_LAUNCH_XCD_ORDER) ? 1 : 0;
+    a.nontemporal = (c->launch_flags & MECH_LAUNCH_NONTEMPORAL) ? 1 : 0;
     a.err = (int *)(c->buf + c->L.off_err);
     a.g = g;
     a.nd = c->nd;
@@ -685,8 +687,10 @@ int mech_step(mech_ctx *c, int64_t nsteps, int64_t k0, double dt, int vmode, int
     return fail(c, MECH_ERR_INVAL, "bad path %d", path);
 }
 
-int mech_set_launch(mech_ctx *c, int block, int tile_instances, int tile_nodes, int blocks_per_cu) {
+int mech_set_launch(mech_ctx *c, int block, int tile_instances, int tile_nodes, int blocks_per_cu, int flags) {
     if (!c) return fail(nullptr, MECH_ERR_INVAL, "null ctx");
+    if (flags & ~(MECH_LAUNCH_XCD_ORDER | MECH_LAUNCH_NONTEMPORAL))
+        return fail(c, MECH_ERR_INVAL, "unknown launch flags 0x%x", flags);
     if (block < 64 || block > 1024 || block % 64)
         return fail(c, MECH_ERR_INVAL, "block must be a multiple of 64 in [64, 1024]");
     if (tile_instances < std::max(block, kMinTileBudget))
@@ -698,11 +702,14 @@ int mech_set_launch(mech_ctx *c, int block, int tile_instances, int tile_nodes, 
     c->tile_budget = tile_instances;
     c->tile_nodes = tile_nodes;
     c->blocks_per_cu = blocks_per_cu;
+    c->launch_flags = flags;
     return build_tiles(c);
 }
 
-int mech_get_launch(const mech_ctx *c, int *block, int *tile_instances, int *tile_nodes, int *blocks_per_cu) {
+int mech_get_launch(const mech_ctx *c, int *block, int *tile_instances, int *tile_nodes, int *blocks_per_cu,
+                    int *flags) {
     if (!c) return fail(nullptr, MECH_ERR_INVAL, "null ctx");
+    if (flags) *flags = c->launch_flags;
     if (block) *block = c->block;
     if (tile_instances) *tile_instances = c->tile_budget;
     if (tile_nodes) *tile_nodes = c->tile_nodes;
@@ -744,8 +751,7 @@ int mech_autotune(mech_ctx *c, double dt, int vmode, int nsteps, int reps, doubl
     };
     hipError_t e = copy_all(true);
     if (e != hipSuccess) { (void)hipFree(save); return fail(c, MECH_ERR_HIP, "autotune save: %s", hipGetErrorString(e)); }
-    const int orig[4] = {c->block, c->tile_budget, c->tile_nodes, c->blocks_per_cu};
-    int best[4] = {orig[0], orig[1], orig[2], orig[3]};
+    int best[5] = {c->block, c->tile_budget, c->tile_nodes, c->blocks_per_cu, c->launch_flags};
     double best_t = 1e300;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     (void)hipEventCreate(&e0);
@@ -753,13 +759,17 @@ int mech_autotune(mech_ctx *c, double dt, int vmode, int nsteps, int reps, doubl
     const int blocks_c[] = {128, 256, 512};
     const int ipt_c[] = {1, 2, 4, 8};
     const int bpc_c[] = {0, 8};
+    // the non-temporal flag measured slower on every shape tried; it stays
+    // available through mech_set_launch but is not searched
+    const int flag_c[] = {0, MECH_LAUNCH_XCD_ORDER};
     for (int b : blocks_c)
         for (int ipt : ipt_c)
-            for (int bpc : bpc_c) {
+            for (int bpc : bpc_c)
+            for (int fl : flag_c) {
                 if (rc) break;
                 const int budget = b * ipt;
                 const int tn = std::min(kMaxTileNodes, std::max(kMinTileNodes, budget));
-                rc = mech_set_launch(c, b, budget, tn, bpc);
+                rc = mech_set_launch(c, b, budget, tn, bpc, fl);
                 if (rc) break;
                 rc = step_batched(c, 1, 0, dt, vmode, false);  // warm-up
                 std::vector<double> ts;
@@ -777,12 +787,12 @@ int mech_autotune(mech_ctx *c, double dt, int vmode, int nsteps, int reps, doubl
                 const double med = ts[ts.size() / 2];
                 if (med < best_t) {
                     best_t = med;
-                    best[0] = b; best[1] = budget; best[2] = tn; best[3] = bpc;
+                    best[0] = b; best[1] = budget; best[2] = tn; best[3] = bpc; best[4] = fl;
                 }
             }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    int rc2 = mech_set_launch(c, best[0], best[1], best[2], best[3]);
+    int rc2 = mech_set_launch(c, best[0], best[1], best[2], best[3], best[4]);
     e = copy_all(false);
     (void)hipFree(save);
     if (rc) return rc;
@@ -845,6 +855,21 @@ int mech_sync(mech_ctx *c) {
         HIPCHK(c, hipStreamSynchronize(c->stream));
         return fail(c, MECH_ERR_NONFINITE, "a kernel stored a non-finite state");
     }
+    return MECH_OK;
+}
+
+int mech_probe_stream(int op, int unroll, int blocks_per_cu, void *dst, const void *src, size_t bytes,
+                      void *hip_stream) {
+    if (op < 0 || op > 3 || (unroll != 1 && unroll != 2 && unroll != 4 && unroll != 8) || blocks_per_cu < 1 ||
+        blocks_per_cu > 64)
+        return fail(nullptr, MECH_ERR_INVAL, "probe: op 0..2, unroll 1/2/4/8, blocks_per_cu 1..64");
+    if (!dst || (op != 2 && !src) || bytes % 16 || ((uintptr_t)dst | (uintptr_t)src) % 16)
+        return fail(nullptr, MECH_ERR_INVAL, "probe needs 16-byte aligned buffers and size");
+    int dev = 0, cu = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev);
+    hipError_t e = launch_stream(op, unroll, dst, src, bytes / 16, blocks_per_cu * cu, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return fail(nullptr, MECH_ERR_HIP, "probe: %s", hipGetErrorString(e));
     return MECH_OK;
 }
 

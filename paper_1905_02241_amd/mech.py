@@ -30,7 +30,9 @@ GLOBAL_NAMES = ("celsius", "ena", "ek", "eh", "cao", "cai0", "tau_ca", "ca_gamma
 SYMBOLS = ("mech_required_bytes", "mech_alloc", "mech_bind_nodes", "mech_bind_clamp", "mech_set_params",
            "mech_set_global", "mech_init", "mech_cur", "mech_state", "mech_step", "mech_set_launch",
            "mech_get_launch", "mech_autotune", "mech_get_state", "mech_set_state", "mech_spike_counts",
-           "mech_sync", "mech_info", "mech_last_error", "mech_strerror", "mech_free")
+           "mech_sync", "mech_info", "mech_probe_stream", "mech_last_error", "mech_strerror", "mech_free")
+LAUNCH_XCD_ORDER = 1
+LAUNCH_NONTEMPORAL = 2
 
 
 class MechError(RuntimeError):
@@ -71,14 +73,15 @@ def load_library(path: str = LIB_PATH):
         "mech_cur": [vp, C.c_int64, C.c_double, C.c_int],
         "mech_state": [vp, C.c_double],
         "mech_step": [vp, C.c_int64, C.c_int64, C.c_double, C.c_int, C.c_int],
-        "mech_set_launch": [vp, C.c_int, C.c_int, C.c_int, C.c_int],
-        "mech_get_launch": [vp, ip, ip, ip, ip],
+        "mech_set_launch": [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int],
+        "mech_get_launch": [vp, ip, ip, ip, ip, ip],
         "mech_autotune": [vp, C.c_double, C.c_int, C.c_int, C.c_int, dp],
         "mech_get_state": [vp, C.c_int, C.c_char_p, dp, C.c_int64],
         "mech_set_state": [vp, C.c_int, C.c_char_p, dp, C.c_int64],
         "mech_spike_counts": [vp, ip, C.c_int64],
         "mech_sync": [vp],
         "mech_info": [vp, lp, lp],
+        "mech_probe_stream": [C.c_int, C.c_int, C.c_int, vp, vp, C.c_size_t, vp],
         "mech_last_error": [vp],
         "mech_strerror": [C.c_int],
         "mech_free": [vp],
@@ -198,11 +201,12 @@ class Mechanisms:
     def step(self, nsteps: int, k0: int, dt: float, vmode: str = "clamp", path: str = "batched"):
         self._check(self.L.mech_step(self.ctx, nsteps, k0, dt, VMODE[vmode], PATH[path]))
 
-    def set_launch(self, block: int, tile_instances: int, tile_nodes: int, blocks_per_cu: int = 0):
-        self._check(self.L.mech_set_launch(self.ctx, block, tile_instances, tile_nodes, blocks_per_cu))
+    def set_launch(self, block: int, tile_instances: int, tile_nodes: int, blocks_per_cu: int = 0,
+                   flags: int = LAUNCH_XCD_ORDER):
+        self._check(self.L.mech_set_launch(self.ctx, block, tile_instances, tile_nodes, blocks_per_cu, flags))
 
     def get_launch(self):
-        v = [C.c_int32() for _ in range(4)]
+        v = [C.c_int32() for _ in range(5)]
         self._check(self.L.mech_get_launch(self.ctx, *[C.byref(x) for x in v]))
         return tuple(x.value for x in v)
 
@@ -241,6 +245,47 @@ class Mechanisms:
 
 STATE_NAMES = {"pas": (), "hh": ("m", "h", "n"), "ih": ("m",), "cahva": ("m", "h", "cai"),
                "syn": ("A_ampa", "B_ampa", "A_nmda", "B_nmda")}
+
+
+PROBE_OPS = {"copy": 0, "read": 1, "write": 2, "triad": 3}
+
+
+def probe_stream(op: str = "copy", nbytes: int = 1 << 32, unroll: int = 4, blocks_per_cu: int = 8,
+                 reps: int = 5) -> float:
+    """Achieved GB/s of the library's streaming probe over `nbytes` of HBM
+    traffic (copy: nbytes/2 read + nbytes/2 written; triad: 2 nbytes/3 read +
+    nbytes/3 written); median of `reps`.
+    Checks every return code and, for the copy, the copied bytes."""
+    import time
+    import torch
+    L = load_library()
+    part = {"copy": 2, "triad": 3}.get(op, 1)
+    half = (nbytes // part) // 16 * 16
+    src = torch.empty(2 * half if op == "triad" else half, dtype=torch.uint8, device="cuda")
+    dst = torch.zeros(half if op != "read" else 256, dtype=torch.uint8, device="cuda")
+    src.fill_(7)
+    s = torch.cuda.current_stream()
+    args = (PROBE_OPS[op], unroll, blocks_per_cu, dst.data_ptr(), src.data_ptr(), half, s.cuda_stream)
+
+    def launch():
+        rc = L.mech_probe_stream(*args)
+        if rc != OK:
+            raise MechError(rc, L.mech_last_error(None).decode())
+
+    launch()
+    torch.cuda.synchronize()
+    if op == "copy" and not bool((dst[:: 1 << 20] == 7).all()):
+        raise RuntimeError("copy probe did not copy")
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        launch()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    ts.sort()
+    moved = part * half
+    return moved / ts[len(ts) // 2] / 1e9
 
 
 def from_workload(w, prec: str = "fp64", init: bool = True) -> Mechanisms:

@@ -32,6 +32,21 @@ def test_header_declares_the_binding_symbols():
     assert declared_functions() == sorted(mech.SYMBOLS)
 
 
+def declared_arity():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    out = {}
+    for m in re.finditer(r"\b(mech_[a-z_]+)\s*\(([^)]*)\)\s*;", src):
+        args = m.group(2).strip()
+        out[m.group(1)] = 0 if args in ("", "void") else args.count(",") + 1
+    return out
+
+
+def test_binding_argtypes_match_header_arity(lib):
+    for name, n in declared_arity().items():
+        assert len(getattr(lib, name).argtypes) == n, name
+
+
 def test_library_exports_every_declared_symbol(lib):
     for name in declared_functions():
         assert hasattr(lib, name), name
