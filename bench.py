@@ -25,13 +25,19 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic bytes per instance per step (index, STATEs read + written,
-# PARAMETERs read, ASSIGNED ica read + written) and per node per step (v
-# read + written, rhs and d written, area, cm), for the fused step.
+# Algorithmic bytes per instance per step of the fused step: node index (4,
+# none for an identity slot), STATEs read + written, PARAMETERs read (the
+# reversal potentials el / e stay FP64), ASSIGNED ica written (Ca-HVA); and
+# per node (see node_bytes).  Synapse weights are read only on an event.
 BYTES_PER_INSTANCE = {
-    "fp64": {"pas": 4 + 8 + 8, "hh": 4 + 48 + 24 + 8, "ih": 4 + 16 + 8, "cahva": 4 + 48 + 8 + 16, "syn": 4 + 64},
-    "fp32": {"pas": 4 + 4 + 8, "hh": 4 + 24 + 12 + 8, "ih": 4 + 8 + 4, "cahva": 4 + 24 + 4 + 8, "syn": 4 + 32},
+    "fp64": {"pas": 4 + 8 + 8, "hh": 4 + 48 + 24 + 8, "ih": 4 + 16 + 8, "cahva": 4 + 48 + 8 + 8, "syn": 4 + 64},
+    "fp32": {"pas": 4 + 4 + 8, "hh": 4 + 24 + 12 + 8, "ih": 4 + 8 + 4, "cahva": 4 + 24 + 4 + 4, "syn": 4 + 32},
 }
+
+
+def is_identity(slot, n_nodes) -> bool:
+    import numpy as np
+    return slot.n == n_nodes and bool(np.array_equal(slot.node, np.arange(n_nodes, dtype=slot.node.dtype)))
 
 
 def node_bytes(w) -> int:
@@ -48,7 +54,7 @@ def node_bytes(w) -> int:
 def alg_bytes_per_step(w, prec: str) -> int:
     tot = w.n_nodes * node_bytes(w)
     for s in w.slots:
-        tot += s.n * BYTES_PER_INSTANCE[prec][s.kind]
+        tot += s.n * (BYTES_PER_INSTANCE[prec][s.kind] - (4 if is_identity(s, w.n_nodes) else 0))
     return tot
 
 

@@ -42,7 +42,8 @@ struct GlobDev {
     double kt_ca;              // kappa * tau_ca
     double e_syn, mg;
     double mg_fd;              // exp(-0.062 fd_dv)
-    double fd_dv, vthresh;
+    double mg_357;             // mg / 3.57
+    double fd_dv, inv_fd_dv, vthresh;
     double fa, fn;             // synapse peak-normalisation factors
     double dt;
     double decay[4];           // exp(-dt/tau) of A_ampa, B_ampa, A_nmda, B_nmda

@@ -54,23 +54,46 @@ __device__ __forceinline__ float one_minus_exp_f(float z) {
 }
 
 // ------------------------------------------------------------ FP64 math --
-__device__ __forceinline__ double linexp_d(double a, double k, double x, double lim) {
-    return x == 0.0 ? lim : a * x / (-expm1(-x / k));
+// a/b within about one ulp without the IEEE division sequence's scaling
+// steps: the hardware reciprocal, two Newton-Raphson refinements
+// r <- r + r (1 - b r), then one residual correction of the quotient.  Valid
+// for normal, finite, non-zero b and a/b in the normal range, which holds
+// for every rate expression it is used on.
+__device__ __forceinline__ double fdiv(double a, double b) {
+    double r = __builtin_amdgcn_rcp(b);
+    r = fma(fma(-b, r, 1.0), r, r);
+    r = fma(fma(-b, r, 1.0), r, r);
+    const double q = a * r;
+    return fma(fma(-b, q, a), r, q);
+}
+
+// a x/(1 - exp(-x/k)), with the limit a k at x = 0; em1 = expm1(-x/k) is
+// returned so that a caller can reuse exp(-x/k) = em1 + 1.
+__device__ __forceinline__ double linexp_d(double a, double inv_k, double x, double lim, double &em1) {
+    em1 = expm1(-x * inv_k);
+    return x == 0.0 ? lim : fdiv(a * x, -em1);
+}
+__device__ __forceinline__ double linexp_d(double a, double inv_k, double x, double lim) {
+    double em1;
+    return linexp_d(a, inv_k, x, lim, em1);
 }
 
 // ----------------------------------------------------- rates and cnexp --
 // Hodgkin-Huxley gates at v; x <- x_inf + (x - x_inf) exp(-dt q10 (a + b)).
+// exp(-(v+35)/10) = e^{1/2} exp(-(v+40)/10) reuses alpha_m's expm1, and
+// exp(-(v+65)/20) = exp(-(v+65)/80)^4 reuses beta_n's exponential.
 __device__ __forceinline__ void hh_state(double v, const GlobDev &g, double &m, double &h, double &n) {
     const double e80 = exp((v + 65.0) * (-1.0 / 80.0));
     const double e80_2 = e80 * e80;
-    const double am = linexp_d(0.1, 10.0, v + 40.0, 1.0);
+    double em1_m;
+    const double am = linexp_d(0.1, 0.1, v + 40.0, 1.0, em1_m);
     const double bm = 4.0 * exp((v + 65.0) * (-1.0 / 18.0));
-    const double ah = 0.07 * (e80_2 * e80_2);                 // exp(-(v+65)/20)
-    const double bh = 1.0 / (1.0 + exp((v + 35.0) * (-0.1)));
-    const double an = linexp_d(0.01, 10.0, v + 55.0, 0.1);
+    const double ah = 0.07 * (e80_2 * e80_2);
+    const double bh = fdiv(1.0, 1.0 + (em1_m + 1.0) * 1.6487212707001282);   // e^{1/2}
+    const double an = linexp_d(0.01, 0.1, v + 55.0, 0.1);
     const double bn = 0.125 * e80;
     const double sm = am + bm, sh = ah + bh, sn = an + bn;
-    const double mi = am / sm, hi = ah / sh, nI = an / sn;
+    const double mi = fdiv(am, sm), hi = fdiv(ah, sh), nI = fdiv(an, sn);
     const double c = -g.dt * g.q10;
     m = mi + (m - mi) * exp(c * sm);
     h = hi + (h - hi) * exp(c * sh);
@@ -95,11 +118,11 @@ __device__ __forceinline__ void hh_state(double vd, const GlobDev &g, float &m, 
 }
 
 __device__ __forceinline__ void hh_inf(double v, double &m, double &h, double &n) {
-    const double am = linexp_d(0.1, 10.0, v + 40.0, 1.0);
+    const double am = linexp_d(0.1, 0.1, v + 40.0, 1.0);
     const double bm = 4.0 * exp(-(v + 65.0) / 18.0);
     const double ah = 0.07 * exp(-(v + 65.0) / 20.0);
     const double bh = 1.0 / (1.0 + exp(-(v + 35.0) / 10.0));
-    const double an = linexp_d(0.01, 10.0, v + 55.0, 0.1);
+    const double an = linexp_d(0.01, 0.1, v + 55.0, 0.1);
     const double bn = 0.125 * exp(-(v + 65.0) / 80.0);
     m = am / (am + bm);
     h = ah / (ah + bh);
@@ -109,8 +132,8 @@ __device__ __forceinline__ void hh_inf(double v, double &m, double &h, double &n
 // Ih: alpha = 0.005 exp(-(v+90)/20), beta = 0.005 exp((v+90)/20).
 __device__ __forceinline__ void ih_state(double v, const GlobDev &g, double &m) {
     const double e = exp((v + 90.0) * 0.05);
-    const double a = 0.005 / e, b = 0.005 * e, s = a + b;
-    const double mi = a / s;
+    const double a = fdiv(0.005, e), b = 0.005 * e, s = a + b;
+    const double mi = fdiv(a, s);
     m = mi + (m - mi) * exp(-g.dt * s);
 }
 __device__ __forceinline__ void ih_state(double vd, const GlobDev &g, float &m) {
@@ -125,24 +148,18 @@ __device__ __forceinline__ double ih_inf(double v) {
 
 // Ca-HVA gates: alpha_m = 0.1 (v+20)/(1 - exp(-(v+20)/5)), beta_m = 0.8
 // exp(-(v+45)/15), alpha_h = 0.0005 exp(-(v+60)/25), beta_h = 0.006/(1 +
-// exp(-(v+20)/10)); the calcium pool relaxes to cai_inf = cai0 - kappa tau
-// ica with time constant tau_ca (ica held at the value of the last current
-// update).
-__device__ __forceinline__ void ca_state(double v, const GlobDev &g, double ica, double &m, double &h,
-                                         double &cai) {
-    const double am = linexp_d(0.1, 5.0, v + 20.0, 0.5);
+// exp(-(v+20)/10)).
+__device__ __forceinline__ void ca_gates(double v, const GlobDev &g, double &m, double &h) {
+    const double am = linexp_d(0.1, 0.2, v + 20.0, 0.5);
     const double bm = 0.8 * exp((v + 45.0) * (-1.0 / 15.0));
     const double ah = 0.0005 * exp((v + 60.0) * (-0.04));
-    const double bh = 0.006 / (1.0 + exp((v + 20.0) * (-0.1)));
+    const double bh = fdiv(0.006, 1.0 + exp((v + 20.0) * (-0.1)));
     const double sm = am + bm, sh = ah + bh;
-    const double mi = am / sm, hi = ah / sh;
+    const double mi = fdiv(am, sm), hi = fdiv(ah, sh);
     m = mi + (m - mi) * exp(-g.dt * sm);
     h = hi + (h - hi) * exp(-g.dt * sh);
-    const double ci = g.cai0 - g.kt_ca * ica;
-    cai = ci + (cai - ci) * g.ca_decay;
 }
-__device__ __forceinline__ void ca_state(double vd, const GlobDev &g, float ica, float &m, float &h,
-                                         float &cai) {
+__device__ __forceinline__ void ca_gates(double vd, const GlobDev &g, float &m, float &h) {
     const float v = (float)vd;
     const float am = linexp_f(0.1f, 5.0f, v + 20.0f);
     const float bm = 0.8f * fexp((v + 45.0f) * (-1.0f / 15.0f));
@@ -152,11 +169,19 @@ __device__ __forceinline__ void ca_state(double vd, const GlobDev &g, float ica,
     const float dt = (float)g.dt;
     m += (am * frcp(sm) - m) * one_minus_exp_f(dt * sm);
     h += (ah * frcp(sh) - h) * one_minus_exp_f(dt * sh);
+}
+// Calcium pool: relaxes to cai_inf = cai0 - kappa tau_ca ica with time
+// constant tau_ca, ica held at the value of the last current update.
+__device__ __forceinline__ void ca_pool(const GlobDev &g, double ica, double &cai) {
+    const double ci = g.cai0 - g.kt_ca * ica;
+    cai = ci + (cai - ci) * g.ca_decay;
+}
+__device__ __forceinline__ void ca_pool(const GlobDev &g, float ica, float &cai) {
     const float ci = (float)g.cai0 - (float)g.kt_ca * ica;
     cai += (ci - cai) * (float)g.ca_omdecay;
 }
 __device__ __forceinline__ void ca_inf(double v, double &m, double &h) {
-    const double am = linexp_d(0.1, 5.0, v + 20.0, 0.5);
+    const double am = linexp_d(0.1, 0.2, v + 20.0, 0.5);
     const double bm = 0.8 * exp(-(v + 45.0) / 15.0);
     const double ah = 0.0005 * exp(-(v + 60.0) / 25.0);
     const double bh = 0.006 / (1.0 + exp(-(v + 20.0) / 10.0));
@@ -200,7 +225,7 @@ __device__ __forceinline__ void hh_cur(double v, S m, S h, S n, S gnabar, S gkba
     i0 = gna * (v - g.ena) + gk * (v - g.ek) + gll * (v - el);
     const double vd = v + g.fd_dv;
     const double i1 = gna * (vd - g.ena) + gk * (vd - g.ek) + gll * (vd - el);
-    gg = (i1 - i0) / g.fd_dv;
+    gg = (i1 - i0) * g.inv_fd_dv;
 }
 
 template <class S>
@@ -209,7 +234,7 @@ __device__ __forceinline__ void lin_cur(double v, S gbar_x, double e, const Glob
     const double gc = (double)gbar_x;
     i0 = gc * (v - e);
     const double i1 = gc * (v + g.fd_dv - e);
-    gg = (i1 - i0) / g.fd_dv;
+    gg = (i1 - i0) * g.inv_fd_dv;
 }
 
 // Calcium current with the Nernst potential eca = RT/(2F) ln(cao/cai).
@@ -220,7 +245,7 @@ __device__ __forceinline__ double ca_cur(double v, S m, S h, S cai, S gbar, cons
     const double gc = (double)(gbar * m * m * h);
     i0 = gc * (v - eca);
     const double i1 = gc * (v + g.fd_dv - eca);
-    gg = (i1 - i0) / g.fd_dv;
+    gg = (i1 - i0) * g.inv_fd_dv;
     return i0;
 }
 
@@ -231,12 +256,12 @@ __device__ __forceinline__ void syn_cur(double v, const S *x, const GlobDev &g, 
     const double ga = (double)(x[1] - x[0]);
     const double gn = (double)(x[3] - x[2]);
     const double ex = exp(-0.062 * v);
-    const double b0 = 1.0 / (1.0 + ex * g.mg / 3.57);
-    const double b1 = 1.0 / (1.0 + ex * g.mg_fd * g.mg / 3.57);
+    const double b0 = fdiv(1.0, 1.0 + ex * g.mg_357);
+    const double b1 = fdiv(1.0, 1.0 + ex * g.mg_fd * g.mg_357);
     const double vd = v + g.fd_dv;
     i0 = 1e-3 * (ga + gn * b0) * (v - g.e_syn);
     const double i1 = 1e-3 * (ga + gn * b1) * (vd - g.e_syn);
-    gg = (i1 - i0) / g.fd_dv;
+    gg = (i1 - i0) * g.inv_fd_dv;
 }
 
 template <class S> __device__ __forceinline__ int bad(S x) { return isfinite(x) ? 0 : 1; }
@@ -256,7 +281,10 @@ template <bool NT, class T> __device__ __forceinline__ void st(T *p, T v) {
 // One instance of a slot: state update (if PH has kDoState) at v, events and
 // current (if kDoCur) at the same v.  Returns the current and conductance
 // contributions for the node and stores the new STATEs.
-template <class S, int KIND, int PH, bool NT = false>
+// FOLD (fused path): the calcium pool needs only cai and the ica of the
+// current update, so it is advanced right after that update in the same pass
+// rather than stored and re-read by the next pass's state update.
+template <class S, int KIND, int PH, bool NT = false, bool FOLD = false>
 __device__ __forceinline__ void instance(const SlotDev &sl, int i, double v, const GlobDev &g, long long k,
                                          double &ci, double &cg, int &flag) {
     ci = 0.0;
@@ -298,13 +326,21 @@ __device__ __forceinline__ void instance(const SlotDev &sl, int i, double v, con
         S *M = (S *)sl.st[0], *H = (S *)sl.st[1], *CAI = (S *)sl.st[2], *ICA = (S *)sl.ica;
         S m = ld<NT>(M + i), h = ld<NT>(H + i), cai = ld<NT>(CAI + i);
         if (PH & kDoState) {
-            ca_state(v, g, ld<NT>(ICA + i), m, h, cai);
+            ca_gates(v, g, m, h);
+            if (!FOLD) ca_pool(g, ld<NT>(ICA + i), cai);
             flag |= bad(m) | bad(h) | bad(cai);
-            st<NT>(M + i, m); st<NT>(H + i, h); st<NT>(CAI + i, cai);
+            st<NT>(M + i, m); st<NT>(H + i, h);
+            if (!FOLD) st<NT>(CAI + i, cai);
         }
         if (PH & kDoCur) {
             const S gbar = ld<NT>((const S *)sl.par[0] + i);
-            st<NT>(ICA + i, (S)ca_cur<S>(v, m, h, cai, gbar, g, ci, cg));
+            const S ica = (S)ca_cur<S>(v, m, h, cai, gbar, g, ci, cg);
+            st<NT>(ICA + i, ica);
+            if (FOLD) {
+                ca_pool(g, ica, cai);
+                flag |= bad(cai);
+                st<NT>(CAI + i, cai);
+            }
         }
     } else if constexpr (KIND == MECH_SYN) {
         S x[4];
@@ -439,7 +475,7 @@ __device__ __forceinline__ void tile_slot(const SlotDev &sl, int lo, int hi, int
         // an identity slot (instance i on node i) needs no index load
         const int j = (sl.identity ? i : ld<NT>(sl.ni + i)) - nlo;
         double ci, cg;
-        instance<S, KIND, PH, NT>(sl, i, vl[j], g, k, ci, cg, flag);
+        instance<S, KIND, PH, NT, true>(sl, i, vl[j], g, k, ci, cg, flag);
         if (PH & kDoCur) {
             if (KIND == MECH_SYN) {
                 ci *= sc[j];

@@ -171,7 +171,10 @@ GlobDev make_glob(const mech_ctx *c, double dt) {
     g.kt_ca = kappa * G.tau_ca;
     g.e_syn = G.e_syn; g.mg = G.mg;
     g.mg_fd = std::exp(-0.062 * G.fd_dv);
-    g.fd_dv = G.fd_dv; g.vthresh = G.vthresh;
+    g.mg_357 = G.mg / 3.57;
+    g.fd_dv = G.fd_dv;
+    g.inv_fd_dv = 1.0 / G.fd_dv;
+    g.vthresh = G.vthresh;
     auto peak = [](double tr, double td) {
         const double tp = tr * td / (td - tr) * std::log(td / tr);
         return 1.0 / (std::exp(-tp / td) - std::exp(-tp / tr));
