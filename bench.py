@@ -58,6 +58,27 @@ def alg_bytes_per_step(w, prec: str) -> int:
     return tot
 
 
+def measured_traffic(w, prec: str):
+    """HBM bytes per launch of the fused kernel from the committed rocprofv3
+    summary (FETCH_SIZE and WRITE_SIZE, calibrated on the copy probe), or None
+    when the summary is missing or was taken on a different kernel source."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_fused_{w.name}_hbm_traffic.txt")
+    src = os.path.join(ROOT, "paper_1905_02241_amd", "csrc", "mech_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != sha:
+        return None
+    v = vals.get(f"traffic_{prec}")
+    return None if v in (None, "null") else float(v)
+
+
 def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
@@ -199,7 +220,7 @@ def main():
         "config": {"workload": w.name, "n_nodes": w.n_nodes, "instances": w.instance_counts(),
                    "dt_ms": w.dt, "vmode": w.vmode, "path": head_key, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(w, prec),
                      "kernel": "k_fused (state+cur, isolated)",
                      "alg_bytes_per_launch": head["alg_bytes_per_step"],
                      "copy_probe_GBps": probe,

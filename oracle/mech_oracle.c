@@ -175,12 +175,44 @@ static double instance_i(const orc_globals *gl, const orc_slot *s, int64_t i, do
     return 0.0;
 }
 
+/* di/dv in closed form with every STATE frozen (section 5.2: the
+ * conductance known from the AST instead of a run-time difference).  Ohmic
+ * currents give their conductance products; the NMDA term also carries the
+ * slope of the Mg block, B'(v) = 0.062 B (1 - B).                          */
+static double instance_g(const orc_globals *gl, const orc_slot *s, int64_t i, double v) {
+    switch (s->kind) {
+    case ORC_PAS:
+        return s->par[0][i];
+    case ORC_HH: {
+        double m = s->st[0][i], h = s->st[1][i], n = s->st[2][i];
+        return s->par[0][i] * m * m * m * h + s->par[1][i] * n * n * n * n + s->par[2][i];
+    }
+    case ORC_IH:
+        return s->par[0][i] * s->st[0][i];
+    case ORC_CAHVA: {
+        double m = s->st[0][i], h = s->st[1][i];
+        return s->par[0][i] * m * m * h;
+    }
+    case ORC_SYN: {
+        double ga = s->st[1][i] - s->st[0][i];
+        double gn = s->st[3][i] - s->st[2][i];
+        double B = orc_mg_block(v, gl->mg);
+        return 1e-3 * (ga + gn * (B + (v - gl->e_syn) * 0.062 * B * (1.0 - B)));
+    }
+    }
+    return 0.0;
+}
+
 void orc_instance_current(const orc_globals *gl, const orc_slot *s, int64_t i,
                           double v, double *cur, double *cond) {
     double i0 = instance_i(gl, s, i, v);
-    double i1 = instance_i(gl, s, i, v + gl->fd_dv);
     *cur = i0;
-    *cond = (i1 - i0) / gl->fd_dv;
+    if (gl->analytic_conductance) {
+        *cond = instance_g(gl, s, i, v);
+    } else {
+        double i1 = instance_i(gl, s, i, v + gl->fd_dv);
+        *cond = (i1 - i0) / gl->fd_dv;
+    }
 }
 
 /* --------------------------------------------------------------- phases -- */
@@ -276,9 +308,17 @@ void orc_visolated(const orc_globals *gl, orc_nodes *nd, double dt) {
 }
 
 /* cnexp: x' = (x_inf - x)/tau with x_inf and tau frozen over the step has the
- * exact solution x(t+dt) = x_inf + (x - x_inf) exp(-dt/tau).                */
-static double cnexp(double x, double xinf, double tau, double dt) {
-    return xinf + (x - xinf) * exp(-dt / tau);
+ * exact solution x(t+dt) = x_inf + (x - x_inf) exp(-dt/tau) (section 5.2).
+ * With pade_cnexp the factor exp(-y) is the (1,1) Pade approximant
+ * (1 - y/2)/(1 + y/2), y = dt/tau (section 5.2, optional replacement).     */
+static double decay_factor(const orc_globals *gl, double dt, double tau) {
+    double y = dt / tau;
+    if (gl->pade_cnexp) return (1.0 - y / 2.0) / (1.0 + y / 2.0);
+    return exp(-y);
+}
+
+static double cnexp(const orc_globals *gl, double x, double xinf, double tau, double dt) {
+    return xinf + (x - xinf) * decay_factor(gl, dt, tau);
 }
 
 void orc_state(const orc_globals *gl, orc_nodes *nd, orc_slot *slots, int nslots, double dt) {
@@ -291,29 +331,29 @@ void orc_state(const orc_globals *gl, orc_nodes *nd, orc_slot *slots, int nslots
             switch (sl->kind) {
             case ORC_HH:
                 orc_hh_inf_tau(v, gl->celsius, o);
-                sl->st[0][i] = cnexp(sl->st[0][i], o[0], o[3], dt);
-                sl->st[1][i] = cnexp(sl->st[1][i], o[1], o[4], dt);
-                sl->st[2][i] = cnexp(sl->st[2][i], o[2], o[5], dt);
+                sl->st[0][i] = cnexp(gl, sl->st[0][i], o[0], o[3], dt);
+                sl->st[1][i] = cnexp(gl, sl->st[1][i], o[1], o[4], dt);
+                sl->st[2][i] = cnexp(gl, sl->st[2][i], o[2], o[5], dt);
                 break;
             case ORC_IH:
                 orc_ih_inf_tau(v, o);
-                sl->st[0][i] = cnexp(sl->st[0][i], o[0], o[1], dt);
+                sl->st[0][i] = cnexp(gl, sl->st[0][i], o[0], o[1], dt);
                 break;
             case ORC_CAHVA: {
                 orc_cahva_inf_tau(v, o);
-                sl->st[0][i] = cnexp(sl->st[0][i], o[0], o[2], dt);
-                sl->st[1][i] = cnexp(sl->st[1][i], o[1], o[3], dt);
+                sl->st[0][i] = cnexp(gl, sl->st[0][i], o[0], o[2], dt);
+                sl->st[1][i] = cnexp(gl, sl->st[1][i], o[1], o[3], dt);
                 /* linear in cai with ica held at its stored value:
                  * cai_inf = cai0 - kappa*tau_ca*ica, time constant tau_ca   */
                 double cinf = gl->cai0 - kappa * gl->tau_ca * sl->ica[i];
-                sl->st[2][i] = cnexp(sl->st[2][i], cinf, gl->tau_ca, dt);
+                sl->st[2][i] = cnexp(gl, sl->st[2][i], cinf, gl->tau_ca, dt);
                 break;
             }
             case ORC_SYN:
-                sl->st[0][i] *= exp(-dt / gl->tau_r_ampa);
-                sl->st[1][i] *= exp(-dt / gl->tau_d_ampa);
-                sl->st[2][i] *= exp(-dt / gl->tau_r_nmda);
-                sl->st[3][i] *= exp(-dt / gl->tau_d_nmda);
+                sl->st[0][i] *= decay_factor(gl, dt, gl->tau_r_ampa);
+                sl->st[1][i] *= decay_factor(gl, dt, gl->tau_d_ampa);
+                sl->st[2][i] *= decay_factor(gl, dt, gl->tau_r_nmda);
+                sl->st[3][i] *= decay_factor(gl, dt, gl->tau_d_nmda);
                 break;
             default:
                 break;

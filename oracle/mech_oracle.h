@@ -73,6 +73,13 @@ typedef struct {
     double vthresh;                 /* mV                                    */
     double fd_dv;                   /* mV                                    */
     uint64_t event_seed;
+    /* section 5.2 variants, both off by default:
+     * analytic_conductance: g = di/dv in closed form instead of the finite
+     *   difference (the CONDUCTANCE statement the framework generates);
+     * pade_cnexp: the cnexp factor exp(-x), x = dt/tau, is replaced by its
+     *   (1,1) Pade approximant (1 - x/2)/(1 + x/2).                          */
+    int32_t analytic_conductance;
+    int32_t pade_cnexp;
 } orc_globals;
 
 typedef struct {

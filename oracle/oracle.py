@@ -40,8 +40,12 @@ class _Slot(C.Structure):
                 ("st", _dp * 4), ("par", _dp * 4), ("ica", _dp)]
 
 
+FLAG_FIELDS = ("analytic_conductance", "pade_cnexp")
+
+
 class _Globals(C.Structure):
-    _fields_ = [(f, C.c_double) for f in GLOBAL_FIELDS] + [("event_seed", C.c_uint64)]
+    _fields_ = ([(f, C.c_double) for f in GLOBAL_FIELDS] + [("event_seed", C.c_uint64)] +
+                [(f, C.c_int32) for f in FLAG_FIELDS])
 
 
 class _Nodes(C.Structure):
@@ -211,6 +215,8 @@ class Model:
         for f in GLOBAL_FIELDS:
             setattr(g, f, float(self.globals[f]))
         g.event_seed = int(self.globals["event_seed"]) & ((1 << 64) - 1)
+        for f in FLAG_FIELDS:
+            setattr(g, f, int(self.globals.get(f, 0)))
         return g
 
     def set_global(self, name, value):

@@ -66,6 +66,8 @@ DEFAULT_GLOBALS = {
     "vthresh": -20.0,
     "fd_dv": 1e-3,
     "event_seed": 0,
+    "analytic_conductance": 0,   # section 5.2: closed-form di/dv instead of the finite difference
+    "pade_cnexp": 0,             # section 5.2: (1,1) Pade approximant of the cnexp exponential
 }
 
 VMODES = ("external", "clamp", "isolated")

@@ -388,3 +388,118 @@ def test_clamp_waveform(oracle):
     M.vclamp(t)
     ref = w.clamp_off + w.clamp_amp * np.sin(2 * np.pi * w.clamp_freq * t / 1000 + w.clamp_phase)
     assert np.allclose(M.v, ref, rtol=0, atol=1e-12)
+
+
+# -------------------------------------- section 5.2 variants (F1, F2) --
+def test_analytic_conductance_matches_central_difference(oracle):
+    """CONDUCTANCE variant: the closed-form di/dv equals a central difference
+    of the oracle's own current (h = 1e-4 mV, error O(h^2)) for every type."""
+    w = W.make_tiny(21, n_nodes=12, per_node=1, syn_per_node=3.0, vmode="external")
+    w.globals["analytic_conductance"] = 1
+    M = oracle.Model(w)
+    M.init()
+    rng = np.random.default_rng(4)
+    for s, sl in enumerate(w.slots):
+        if sl.kind == "syn":
+            for name in M.states[s]:
+                M.states[s][name][:] = rng.uniform(0, 3, sl.n)
+        for i in range(sl.n):
+            for v in (-75.0, -30.0, 15.0):
+                _, g = M.instance_current(s, i, v)
+                ip, _ = M.instance_current(s, i, v + 1e-4)
+                im, _ = M.instance_current(s, i, v - 1e-4)
+                cd = (ip - im) / 2e-4
+                assert abs(g - cd) <= 1e-7 * (abs(cd) + abs(g)) + 1e-15, (sl.kind, v)
+
+
+def test_analytic_conductance_leaves_rhs_and_states(oracle):
+    """Only d changes with the CONDUCTANCE variant: rhs and every STATE are
+    bit-identical, d agrees with the finite difference to O(dv)."""
+    w = W.make_tiny(22, per_node=2, nsteps=40)
+    A = oracle.Model(w)
+    A.init()
+    A.run(0, 40)
+    w.globals["analytic_conductance"] = 1
+    B = oracle.Model(w)
+    B.init()
+    B.run(0, 40)
+    assert np.array_equal(A.rhs, B.rhs)
+    for s in range(len(w.slots)):
+        for name in A.states[s]:
+            assert np.array_equal(A.states[s][name], B.states[s][name])
+    assert np.allclose(A.d, B.d, rtol=2e-4, atol=1e-12)
+
+
+def _pade(y):
+    return (1 - y / 2) / (1 + y / 2)
+
+
+def test_pade_cnexp_is_geometric_under_clamp(oracle):
+    """Pade variant: with v held the iterate is x_inf + (x0 - x_inf) P(dt/tau)^n,
+    P(y) = (1 - y/2)/(1 + y/2)."""
+    w = _single("hh", -20.0, 400)
+    w.globals["pade_cnexp"] = 1
+    M = oracle.Model(w)
+    M.init()
+    x0 = np.array([M.states[0][k][0] for k in "mhn"])
+    it = oracle.hh_inf_tau(-20.0, 6.3)
+    M.run(0, 400)
+    ref = it[:3] + (x0 - it[:3]) * _pade(0.025 / it[3:]) ** 400
+    got = np.array([M.states[0][k][0] for k in "mhn"])
+    assert np.all(np.abs(got - ref) <= 1e-14 + 1e-12 * np.abs(ref))
+
+
+def test_pade_cnexp_error_within_its_bound(oracle):
+    """One step: |P(y) - e^-y| <= y^3/12 (the leading error term of the (1,1)
+    approximant, an upper bound for 0 < y < 1), scaled by |x - x_inf|."""
+    for v in (-70.0, -40.0, 0.0, 30.0):
+        w = _single("hh", v, 1)
+        E = oracle.Model(w)
+        E.init()
+        w2 = _single("hh", v, 1)
+        w2.globals["pade_cnexp"] = 1
+        P = oracle.Model(w2)
+        P.init()
+        it = oracle.hh_inf_tau(v, 6.3)
+        E.run(0, 1)
+        P.run(0, 1)
+        for j, k in enumerate("mhn"):
+            y = 0.025 / it[3 + j]
+            x0 = oracle.hh_inf_tau(-65.0, 6.3)[j]
+            bound = y ** 3 / 12 * abs(x0 - it[j]) + 1e-15
+            assert abs(E.states[0][k][0] - P.states[0][k][0]) <= bound, (v, k)
+
+
+def test_pade_keeps_fixed_points_and_bounds(oracle):
+    w = W.make_tiny(23, kinds=("hh", "ih", "cahva"), n_nodes=30, shuffle=False, nsteps=300)
+    w.globals["pade_cnexp"] = 1
+    w.clamp_amp[:] = 70.0
+    M = oracle.Model(w)
+    M.init()
+    M.run(0, 300)
+    for st in M.states:
+        for name, a in st.items():
+            if name != "cai":
+                assert np.all((a >= 0) & (a <= 1))
+    v = -48.0
+    w = _single("hh", v, 30, v_init=v)
+    w.globals["pade_cnexp"] = 1
+    M = oracle.Model(w)
+    M.init(v)
+    before = {k: a.copy() for k, a in M.states[0].items()}
+    M.run(0, 30)
+    for k in before:
+        assert np.array_equal(before[k], M.states[0][k])
+
+
+def test_pade_synapse_decay(oracle):
+    w = _single("syn", -65.0, 1, params={"weight": np.array([2.0])})
+    w.globals["pade_cnexp"] = 1
+    w.globals["event_rate_hz"] = 1e9
+    M = oracle.Model(w)
+    M.init(-65.0)
+    M.events(0)
+    M.set_global("event_rate_hz", 0.0)
+    a0 = M.states[0]["B_nmda"][0]
+    M.run(1, 200)
+    assert abs(M.states[0]["B_nmda"][0] - a0 * _pade(0.025 / 43.0) ** 200) < 1e-14 * a0
