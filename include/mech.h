@@ -144,7 +144,14 @@ int mech_set_params(mech_ctx *ctx, int type_slot, const char *name, const double
 
 /* Set a global: celsius, ena, ek, eh, cao, cai0, tau_ca, ca_gamma, ca_depth,
  * e_syn, mg, tau_r_ampa, tau_d_ampa, tau_r_nmda, tau_d_nmda, event_rate_hz,
- * event_seed (an integer below 2^53), vthresh, fd_dv.                      */
+ * event_seed (an integer below 2^53), vthresh, fd_dv, and the two variants
+ * of section 5.2 (0 or 1, default 0):
+ *   analytic_conductance  g = di/dv in closed form (the CONDUCTANCE
+ *                         statement) instead of the finite difference;
+ *   pade_cnexp            every cnexp factor exp(-dt/tau) replaced by its
+ *                         (1,1) Pade approximant (1 - y/2)/(1 + y/2),
+ *                         y = dt/tau (requires y < 2 to keep gates in
+ *                         [0, 1]).                                          */
 int mech_set_global(mech_ctx *ctx, const char *name, double value);
 
 /* INITIAL (section 3): every gate at its steady state x_inf(v) at the bound

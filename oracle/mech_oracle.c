@@ -22,6 +22,9 @@
  *   ih    one gate, alpha = 0.005 exp(-(v+90)/20), beta = 0.005 exp((v+90)/20)
  *   cahva m^2 h, Nernst eca, shell calcium with relaxation to cai0
  *   syn   double-exponential AMPA + NMDA conductance with Mg block
+ *   kmarkov  three-state C1-C2-O potassium scheme, implicit Euler (sparse)
+ *   capump   Ca-HVA gates with a pool emptied by a saturable pump, implicit
+ *            Euler solved by Newton's method (derivimplicit)
  */
 #include "mech_oracle.h"
 
@@ -97,6 +100,72 @@ void orc_cahva_inf_tau(double v, double *o) {
     o[3] = 1.0 / (ah + bh);
 }
 
+/* ------------------------------------------------------------- kmarkov -- */
+/* Three-state potassium scheme C1 <-> C2 <-> O with the Hodgkin-Huxley n-gate
+ * rates a = q10 alpha_n, b = q10 beta_n:  C1 -> C2 at 2a, C2 -> C1 at b,
+ * C2 -> O at a, O -> C2 at 2b.  Its equilibrium is the binomial
+ * (1-n)^2, 2n(1-n), n^2 with n = n_inf, so O plays the role of n^2.
+ * dx/dt = A x; implicit Euler solves (I - dt A) x_new = x_old.            */
+void orc_kmarkov_matrix(double v, double celsius, double dt, double *M) {
+    double q = hh_q10(celsius);
+    double a = q * hh_an(v), b = q * hh_bn(v);
+    double A[9] = {-2.0 * a, b, 0.0,
+                   2.0 * a, -(a + b), 2.0 * b,
+                   0.0, a, -2.0 * b};
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+            M[3 * r + c] = (r == c ? 1.0 : 0.0) - dt * A[3 * r + c];
+}
+
+/* Gaussian elimination with partial pivoting on a 3x3 system (textbook). */
+static void solve3(double *M, double *x) {
+    for (int k = 0; k < 3; ++k) {
+        int p = k;
+        for (int r = k + 1; r < 3; ++r)
+            if (fabs(M[3 * r + k]) > fabs(M[3 * p + k])) p = r;
+        if (p != k) {
+            for (int c = 0; c < 3; ++c) {
+                double t = M[3 * k + c]; M[3 * k + c] = M[3 * p + c]; M[3 * p + c] = t;
+            }
+            double t = x[k]; x[k] = x[p]; x[p] = t;
+        }
+        for (int r = k + 1; r < 3; ++r) {
+            double f = M[3 * r + k] / M[3 * k + k];
+            for (int c = k; c < 3; ++c) M[3 * r + c] -= f * M[3 * k + c];
+            x[r] -= f * x[k];
+        }
+    }
+    for (int k = 2; k >= 0; --k) {
+        double sum = x[k];
+        for (int c = k + 1; c < 3; ++c) sum -= M[3 * k + c] * x[c];
+        x[k] = sum / M[3 * k + k];
+    }
+}
+
+void orc_kmarkov_step(double v, double celsius, double dt, double *x) {
+    double M[9];
+    orc_kmarkov_matrix(v, celsius, dt, M);
+    solve3(M, x);
+}
+
+/* -------------------------------------------------------------- capump -- */
+static double pump_rate(const orc_globals *gl, double c) {
+    return gl->pump_vmax * (c / (c + gl->pump_kp) - gl->cai0 / (gl->cai0 + gl->pump_kp));
+}
+
+double orc_capump_step(const orc_globals *gl, double ica, double dt, double *cai, int iters) {
+    double kappa = orc_ca_kappa(gl->ca_gamma, gl->ca_depth);
+    double c0 = *cai, c = c0, G = 0.0;
+    for (int it = 0; it < iters; ++it) {
+        double F = -kappa * ica - pump_rate(gl, c);
+        double dF = -gl->pump_vmax * gl->pump_kp / ((c + gl->pump_kp) * (c + gl->pump_kp));
+        G = c - c0 - dt * F;
+        c = c - G / (1.0 - dt * dF);
+    }
+    *cai = c;
+    return c - c0 - dt * (-kappa * ica - pump_rate(gl, c));
+}
+
 double orc_nernst_ca(double cai, double cao, double celsius) {
     double T = celsius + 273.15;
     return 1e3 * ORC_R * T / (2.0 * ORC_F) * log(cao / cai);
@@ -160,11 +229,14 @@ static double instance_i(const orc_globals *gl, const orc_slot *s, int64_t i, do
     }
     case ORC_IH:
         return s->par[0][i] * s->st[0][i] * (v - gl->eh);
-    case ORC_CAHVA: {
+    case ORC_CAHVA:
+    case ORC_CAPUMP: {
         double m = s->st[0][i], h = s->st[1][i];
         double eca = orc_nernst_ca(s->st[2][i], gl->cao, gl->celsius);
         return s->par[0][i] * m * m * h * (v - eca);
     }
+    case ORC_KMARKOV:
+        return s->par[0][i] * s->st[2][i] * (v - gl->ek);
     case ORC_SYN: {
         double ga = s->st[1][i] - s->st[0][i];
         double gn = s->st[3][i] - s->st[2][i];
@@ -189,10 +261,13 @@ static double instance_g(const orc_globals *gl, const orc_slot *s, int64_t i, do
     }
     case ORC_IH:
         return s->par[0][i] * s->st[0][i];
-    case ORC_CAHVA: {
+    case ORC_CAHVA:
+    case ORC_CAPUMP: {
         double m = s->st[0][i], h = s->st[1][i];
         return s->par[0][i] * m * m * h;
     }
+    case ORC_KMARKOV:
+        return s->par[0][i] * s->st[2][i];
     case ORC_SYN: {
         double ga = s->st[1][i] - s->st[0][i];
         double gn = s->st[3][i] - s->st[2][i];
@@ -232,10 +307,19 @@ void orc_init(const orc_globals *gl, orc_nodes *nd, orc_slot *slots, int nslots)
                 sl->st[0][i] = o[0];
                 break;
             case ORC_CAHVA:
+            case ORC_CAPUMP:
                 orc_cahva_inf_tau(v, o);
                 sl->st[0][i] = o[0]; sl->st[1][i] = o[1]; sl->st[2][i] = gl->cai0;
                 if (sl->ica) sl->ica[i] = 0.0;
                 break;
+            case ORC_KMARKOV: {
+                orc_hh_inf_tau(v, gl->celsius, o);
+                double n = o[2];
+                sl->st[0][i] = (1.0 - n) * (1.0 - n);
+                sl->st[1][i] = 2.0 * n * (1.0 - n);
+                sl->st[2][i] = n * n;
+                break;
+            }
             case ORC_SYN:
                 for (int j = 0; j < 4; ++j) sl->st[j][i] = 0.0;
                 break;
@@ -276,7 +360,7 @@ void orc_cur(const orc_globals *gl, orc_nodes *nd, orc_slot *slots, int nslots) 
             int32_t ni = sl->node[i];
             double I0, g;
             orc_instance_current(gl, sl, i, nd->v[ni], &I0, &g);
-            if (sl->kind == ORC_CAHVA && sl->ica) sl->ica[i] = I0;
+            if ((sl->kind == ORC_CAHVA || sl->kind == ORC_CAPUMP) && sl->ica) sl->ica[i] = I0;
             if (sl->kind == ORC_SYN) {
                 /* nA/um2 -> mA/cm2 and uS/um2 -> S/cm2: both a factor 100 */
                 double sc = 1e2 / nd->area[ni];
@@ -347,6 +431,19 @@ void orc_state(const orc_globals *gl, orc_nodes *nd, orc_slot *slots, int nslots
                  * cai_inf = cai0 - kappa*tau_ca*ica, time constant tau_ca   */
                 double cinf = gl->cai0 - kappa * gl->tau_ca * sl->ica[i];
                 sl->st[2][i] = cnexp(gl, sl->st[2][i], cinf, gl->tau_ca, dt);
+                break;
+            }
+            case ORC_CAPUMP: {
+                orc_cahva_inf_tau(v, o);
+                sl->st[0][i] = cnexp(gl, sl->st[0][i], o[0], o[2], dt);
+                sl->st[1][i] = cnexp(gl, sl->st[1][i], o[1], o[3], dt);
+                orc_capump_step(gl, sl->ica[i], dt, &sl->st[2][i], gl->newton_iters);
+                break;
+            }
+            case ORC_KMARKOV: {
+                double x[3] = {sl->st[0][i], sl->st[1][i], sl->st[2][i]};
+                orc_kmarkov_step(v, gl->celsius, dt, x);
+                sl->st[0][i] = x[0]; sl->st[1][i] = x[1]; sl->st[2][i] = x[2];
                 break;
             }
             case ORC_SYN:

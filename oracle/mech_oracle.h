@@ -42,13 +42,15 @@
 extern "C" {
 #endif
 
-enum { ORC_PAS = 0, ORC_HH = 1, ORC_IH = 2, ORC_CAHVA = 3, ORC_SYN = 4 };
+enum { ORC_PAS = 0, ORC_HH = 1, ORC_IH = 2, ORC_CAHVA = 3, ORC_SYN = 4, ORC_KMARKOV = 5, ORC_CAPUMP = 6 };
 enum { ORC_V_EXTERNAL = 0, ORC_V_CLAMP = 1, ORC_V_ISOLATED = 2 };
 
 /* One mechanism type ("slot") and its instances, in the caller's order.
  *   st : STATE arrays     hh: m,h,n   ih: m   cahva: m,h,cai   syn: Aa,Ba,An,Bn
+ *                         kmarkov: C1,C2,O   capump: m,h,cai
  *   par: RANGE parameters hh: gnabar,gkbar,gl,el   pas: g,e   ih: gbar
- *                         cahva: gbar   syn: weight (nS)
+ *                         cahva: gbar   syn: weight (nS)   kmarkov: gbar
+ *                         capump: gbar
  *   ica: Ca-HVA calcium current written by cur and read by state (mA/cm2)
  *   gid: synapse event-stream id (NULL: the instance index is used)        */
 typedef struct {
@@ -80,6 +82,11 @@ typedef struct {
      *   (1,1) Pade approximant (1 - x/2)/(1 + x/2).                          */
     int32_t analytic_conductance;
     int32_t pade_cnexp;
+    /* capump: Michaelis-Menten pump of maximal rate vmax (mM/ms) and
+     * half-activation kp (mM), balanced at cai0; newton_iters Newton steps
+     * solve its implicit Euler equation (section 5.2, derivimplicit).        */
+    double pump_vmax, pump_kp;
+    int32_t newton_iters;
 } orc_globals;
 
 typedef struct {
@@ -98,6 +105,16 @@ void orc_hh_inf_tau(double v, double celsius, double *out6);
 void orc_hh_rates(double v, double *out6);
 void orc_ih_inf_tau(double v, double *out2);                 /* m_inf, tau_m */
 void orc_cahva_inf_tau(double v, double *out4);   /* m_inf, h_inf, tau_m, tau_h */
+/* kmarkov: the 3x3 implicit Euler matrix M = I - dt A(v) (row-major) and
+ * one implicit Euler step x <- M^{-1} x by Gaussian elimination with
+ * partial pivoting (section 5.2, sparse method).                           */
+void orc_kmarkov_matrix(double v, double celsius, double dt, double *M9);
+void orc_kmarkov_step(double v, double celsius, double dt, double *x3);
+/* capump: one implicit Euler step of the pool, cai <- root of
+ * c - cai - dt F(c) = 0 with F(c) = -kappa ica - vmax (c/(c+kp) -
+ * cai0/(cai0+kp)), by `iters` Newton steps from c = cai; returns the
+ * residual of the last iterate.                                           */
+double orc_capump_step(const orc_globals *gl, double ica, double dt, double *cai, int iters);
 double orc_mg_block(double v, double mg);
 double orc_syn_peak_factor(double tau_r, double tau_d, double *t_peak);
 double orc_nernst_ca(double cai, double cao, double celsius);     /* mV      */

@@ -20,12 +20,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "mech_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
-KIND = {"pas": 0, "hh": 1, "ih": 2, "cahva": 3, "syn": 4}
+KIND = {"pas": 0, "hh": 1, "ih": 2, "cahva": 3, "syn": 4, "kmarkov": 5, "capump": 6}
 VMODE = {"external": 0, "clamp": 1, "isolated": 2}
 PARAMS = {"pas": ("g", "e"), "hh": ("gnabar", "gkbar", "gl", "el"), "ih": ("gbar",),
-          "cahva": ("gbar",), "syn": ("weight",)}
+          "cahva": ("gbar",), "syn": ("weight",), "kmarkov": ("gbar",), "capump": ("gbar",)}
 STATES = {"pas": (), "hh": ("m", "h", "n"), "ih": ("m",), "cahva": ("m", "h", "cai"),
-          "syn": ("A_ampa", "B_ampa", "A_nmda", "B_nmda")}
+          "syn": ("A_ampa", "B_ampa", "A_nmda", "B_nmda"), "kmarkov": ("C1", "C2", "O"),
+          "capump": ("m", "h", "cai")}
 GLOBAL_FIELDS = ("celsius", "ena", "ek", "eh", "cao", "cai0", "tau_ca", "ca_gamma", "ca_depth",
                  "e_syn", "mg", "tau_r_ampa", "tau_d_ampa", "tau_r_nmda", "tau_d_nmda",
                  "event_rate_hz", "vthresh", "fd_dv")
@@ -45,7 +46,8 @@ FLAG_FIELDS = ("analytic_conductance", "pade_cnexp")
 
 class _Globals(C.Structure):
     _fields_ = ([(f, C.c_double) for f in GLOBAL_FIELDS] + [("event_seed", C.c_uint64)] +
-                [(f, C.c_int32) for f in FLAG_FIELDS])
+                [(f, C.c_int32) for f in FLAG_FIELDS] +
+                [("pump_vmax", C.c_double), ("pump_kp", C.c_double), ("newton_iters", C.c_int32)])
 
 
 class _Nodes(C.Structure):
@@ -90,6 +92,10 @@ def lib():
         L.orc_event_hash.restype = C.c_uint64
         L.orc_event_threshold.argtypes = [C.c_double, C.c_double]
         L.orc_event_threshold.restype = C.c_uint64
+        L.orc_kmarkov_matrix.argtypes = [C.c_double, C.c_double, C.c_double, _dp]
+        L.orc_kmarkov_step.argtypes = [C.c_double, C.c_double, C.c_double, _dp]
+        L.orc_capump_step.argtypes = [C.POINTER(_Globals), C.c_double, C.c_double, _dp, C.c_int]
+        L.orc_capump_step.restype = C.c_double
         L.orc_instance_current.argtypes = [C.POINTER(_Globals), C.POINTER(_Slot), C.c_int64, C.c_double, _dp, _dp]
         sig = [C.POINTER(_Globals), C.POINTER(_Nodes), C.POINTER(_Slot), C.c_int]
         L.orc_init.argtypes = sig
@@ -159,6 +165,18 @@ def event_threshold(rate_hz: float, dt: float) -> int:
     return int(lib().orc_event_threshold(rate_hz, dt))
 
 
+def kmarkov_matrix(v: float, celsius: float, dt: float) -> np.ndarray:
+    M = np.zeros(9)
+    lib().orc_kmarkov_matrix(v, celsius, dt, _ptr(M))
+    return M.reshape(3, 3)
+
+
+def kmarkov_step(v: float, celsius: float, dt: float, x) -> np.ndarray:
+    x = np.array(x, dtype=np.float64)
+    lib().orc_kmarkov_step(v, celsius, dt, _ptr(x))
+    return x
+
+
 # ----------------------------------------------------------------- model --
 class Model:
     """Owns FP64 copies of one workload's arrays and runs the oracle on them.
@@ -217,6 +235,9 @@ class Model:
         g.event_seed = int(self.globals["event_seed"]) & ((1 << 64) - 1)
         for f in FLAG_FIELDS:
             setattr(g, f, int(self.globals.get(f, 0)))
+        g.pump_vmax = float(self.globals.get("pump_vmax", 1e-4))
+        g.pump_kp = float(self.globals.get("pump_kp", 1e-3))
+        g.newton_iters = int(self.globals.get("newton_iters", 4))
         return g
 
     def set_global(self, name, value):
@@ -255,6 +276,12 @@ class Model:
         r = lib().orc_run(*self._args(), k0, nsteps, self.dt, vm)
         if r != 0:
             raise ValueError("orc_run rejected its arguments")
+
+    def capump_step(self, ica: float, cai: float, iters: int):
+        """One implicit Euler step of the capump pool; returns (cai, residual)."""
+        c = C.c_double(cai)
+        r = lib().orc_capump_step(C.byref(self._g), ica, self.dt, C.byref(c), iters)
+        return c.value, r
 
     def instance_current(self, s: int, i: int, v: float):
         cur, cond = C.c_double(), C.c_double()

@@ -50,6 +50,8 @@ struct GlobDev {
     double omdecay[4];         // 1 - decay, from expm1
     double ca_decay, ca_omdecay;
     uint64_t seed, threshold;  // event draws: fire when H(seed, gid, k) < threshold
+    int analytic_g;            // conductance in closed form instead of the finite difference
+    int pade;                  // cnexp factor exp(-y) replaced by (1 - y/2)/(1 + y/2)
 };
 
 struct NodesDev {

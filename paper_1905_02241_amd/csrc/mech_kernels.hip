@@ -78,6 +78,17 @@ __device__ __forceinline__ double linexp_d(double a, double inv_k, double x, dou
     return linexp_d(a, inv_k, x, lim, em1);
 }
 
+// cnexp factor e^{-y} over one step, or its (1,1) Pade approximant
+// (1 - y/2)/(1 + y/2) (the optional replacement of the paper's section 5.2).
+__device__ __forceinline__ double cnexp_factor(double y, int pade) {
+    return pade ? fdiv(1.0 - 0.5 * y, 1.0 + 0.5 * y) : exp(-y);
+}
+// 1 - factor in FP32 without cancellation: the series / exp form above, or
+// y/(1 + y/2) for the Pade approximant.
+__device__ __forceinline__ float one_minus_factor_f(float y, int pade) {
+    return pade ? y * frcp(1.0f + 0.5f * y) : one_minus_exp_f(y);
+}
+
 // ----------------------------------------------------- rates and cnexp --
 // Hodgkin-Huxley gates at v; x <- x_inf + (x - x_inf) exp(-dt q10 (a + b)).
 // exp(-(v+35)/10) = e^{1/2} exp(-(v+40)/10) reuses alpha_m's expm1, and
@@ -94,10 +105,10 @@ __device__ __forceinline__ void hh_state(double v, const GlobDev &g, double &m, 
     const double bn = 0.125 * e80;
     const double sm = am + bm, sh = ah + bh, sn = an + bn;
     const double mi = fdiv(am, sm), hi = fdiv(ah, sh), nI = fdiv(an, sn);
-    const double c = -g.dt * g.q10;
-    m = mi + (m - mi) * exp(c * sm);
-    h = hi + (h - hi) * exp(c * sh);
-    n = nI + (n - nI) * exp(c * sn);
+    const double c = g.dt * g.q10;
+    m = mi + (m - mi) * cnexp_factor(c * sm, g.pade);
+    h = hi + (h - hi) * cnexp_factor(c * sh, g.pade);
+    n = nI + (n - nI) * cnexp_factor(c * sn, g.pade);
 }
 
 __device__ __forceinline__ void hh_state(double vd, const GlobDev &g, float &m, float &h, float &n) {
@@ -112,9 +123,9 @@ __device__ __forceinline__ void hh_state(double vd, const GlobDev &g, float &m, 
     const float bn = 0.125f * e80;
     const float sm = am + bm, sh = ah + bh, sn = an + bn;
     const float c = (float)(g.dt * g.q10);
-    m += (am * frcp(sm) - m) * one_minus_exp_f(c * sm);
-    h += (ah * frcp(sh) - h) * one_minus_exp_f(c * sh);
-    n += (an * frcp(sn) - n) * one_minus_exp_f(c * sn);
+    m += (am * frcp(sm) - m) * one_minus_factor_f(c * sm, g.pade);
+    h += (ah * frcp(sh) - h) * one_minus_factor_f(c * sh, g.pade);
+    n += (an * frcp(sn) - n) * one_minus_factor_f(c * sn, g.pade);
 }
 
 __device__ __forceinline__ void hh_inf(double v, double &m, double &h, double &n) {
@@ -134,12 +145,12 @@ __device__ __forceinline__ void ih_state(double v, const GlobDev &g, double &m) 
     const double e = exp((v + 90.0) * 0.05);
     const double a = fdiv(0.005, e), b = 0.005 * e, s = a + b;
     const double mi = fdiv(a, s);
-    m = mi + (m - mi) * exp(-g.dt * s);
+    m = mi + (m - mi) * cnexp_factor(g.dt * s, g.pade);
 }
 __device__ __forceinline__ void ih_state(double vd, const GlobDev &g, float &m) {
     const float e = fexp(((float)vd + 90.0f) * 0.05f);
     const float a = 0.005f * frcp(e), b = 0.005f * e, s = a + b;
-    m += (a * frcp(s) - m) * one_minus_exp_f((float)g.dt * s);
+    m += (a * frcp(s) - m) * one_minus_factor_f((float)g.dt * s, g.pade);
 }
 __device__ __forceinline__ double ih_inf(double v) {
     const double a = 0.005 * exp(-(v + 90.0) / 20.0), b = 0.005 * exp((v + 90.0) / 20.0);
@@ -156,8 +167,8 @@ __device__ __forceinline__ void ca_gates(double v, const GlobDev &g, double &m, 
     const double bh = fdiv(0.006, 1.0 + exp((v + 20.0) * (-0.1)));
     const double sm = am + bm, sh = ah + bh;
     const double mi = fdiv(am, sm), hi = fdiv(ah, sh);
-    m = mi + (m - mi) * exp(-g.dt * sm);
-    h = hi + (h - hi) * exp(-g.dt * sh);
+    m = mi + (m - mi) * cnexp_factor(g.dt * sm, g.pade);
+    h = hi + (h - hi) * cnexp_factor(g.dt * sh, g.pade);
 }
 __device__ __forceinline__ void ca_gates(double vd, const GlobDev &g, float &m, float &h) {
     const float v = (float)vd;
@@ -167,8 +178,8 @@ __device__ __forceinline__ void ca_gates(double vd, const GlobDev &g, float &m, 
     const float bh = 0.006f * frcp(1.0f + fexp((v + 20.0f) * (-0.1f)));
     const float sm = am + bm, sh = ah + bh;
     const float dt = (float)g.dt;
-    m += (am * frcp(sm) - m) * one_minus_exp_f(dt * sm);
-    h += (ah * frcp(sh) - h) * one_minus_exp_f(dt * sh);
+    m += (am * frcp(sm) - m) * one_minus_factor_f(dt * sm, g.pade);
+    h += (ah * frcp(sh) - h) * one_minus_factor_f(dt * sh, g.pade);
 }
 // Calcium pool: relaxes to cai_inf = cai0 - kappa tau_ca ica with time
 // constant tau_ca, ica held at the value of the last current update.
@@ -223,6 +234,10 @@ __device__ __forceinline__ void hh_cur(double v, S m, S h, S n, S gnabar, S gkba
     const double gk = (double)(gkbar * n * n * n * n);
     const double gll = (double)gl;
     i0 = gna * (v - g.ena) + gk * (v - g.ek) + gll * (v - el);
+    if (g.analytic_g) {
+        gg = gna + gk + gll;
+        return;
+    }
     const double vd = v + g.fd_dv;
     const double i1 = gna * (vd - g.ena) + gk * (vd - g.ek) + gll * (vd - el);
     gg = (i1 - i0) * g.inv_fd_dv;
@@ -233,6 +248,10 @@ __device__ __forceinline__ void lin_cur(double v, S gbar_x, double e, const Glob
                                         double &gg) {
     const double gc = (double)gbar_x;
     i0 = gc * (v - e);
+    if (g.analytic_g) {
+        gg = gc;
+        return;
+    }
     const double i1 = gc * (v + g.fd_dv - e);
     gg = (i1 - i0) * g.inv_fd_dv;
 }
@@ -244,6 +263,10 @@ __device__ __forceinline__ double ca_cur(double v, S m, S h, S cai, S gbar, cons
     const double eca = g.nernst * log(g.cao / (double)cai);
     const double gc = (double)(gbar * m * m * h);
     i0 = gc * (v - eca);
+    if (g.analytic_g) {
+        gg = gc;
+        return i0;
+    }
     const double i1 = gc * (v + g.fd_dv - eca);
     gg = (i1 - i0) * g.inv_fd_dv;
     return i0;
@@ -257,9 +280,14 @@ __device__ __forceinline__ void syn_cur(double v, const S *x, const GlobDev &g, 
     const double gn = (double)(x[3] - x[2]);
     const double ex = exp(-0.062 * v);
     const double b0 = fdiv(1.0, 1.0 + ex * g.mg_357);
+    i0 = 1e-3 * (ga + gn * b0) * (v - g.e_syn);
+    if (g.analytic_g) {
+        // di/dv = 1e-3 (ga + gn (B + (v - e) B')), B' = 0.062 B (1 - B)
+        gg = 1e-3 * (ga + gn * (b0 + (v - g.e_syn) * 0.062 * b0 * (1.0 - b0)));
+        return;
+    }
     const double b1 = fdiv(1.0, 1.0 + ex * g.mg_fd * g.mg_357);
     const double vd = v + g.fd_dv;
-    i0 = 1e-3 * (ga + gn * b0) * (v - g.e_syn);
     const double i1 = 1e-3 * (ga + gn * b1) * (vd - g.e_syn);
     gg = (i1 - i0) * g.inv_fd_dv;
 }
@@ -366,27 +394,53 @@ __device__ __forceinline__ void instance(const SlotDev &sl, int i, double v, con
 }
 
 // ---------------------------------------------------------- plain path --
+// Segmented inclusive sum over a wave of instances sorted by node: after the
+// log2(64) shuffle steps each lane holds the sum of its node's run up to
+// itself, so the run's last lane carries the node's total.  Returns true on
+// that lane.  Lanes with key < 0 (past the end) form no run.
+__device__ __forceinline__ bool segmented_sum(int key, double &x, double &y) {
+    const int lane = (int)(threadIdx.x & 63);
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const double xo = __shfl_up(x, d, 64);
+        const double yo = __shfl_up(y, d, 64);
+        const int ko = __shfl_up(key, d, 64);
+        if (lane >= d && ko == key) {
+            x += xo;
+            y += yo;
+        }
+    }
+    const int kn = __shfl_down(key, 1, 64);
+    return key >= 0 && (lane == 63 || kn != key);
+}
+
 template <class S, int KIND>
 __global__ __launch_bounds__(256) void k_plain_cur(PlainArgs a) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     int flag = 0;
+    int ni = -1;
+    double ci = 0.0, cg = 0.0;
     if (i < a.slot.n) {
-        const int ni = a.slot.ni[i];
+        ni = a.slot.ni[i];
         const double v = a.nd.v[ni];
-        double ci, cg;
         instance<S, KIND, kDoCur>(a.slot, i, v, a.g, a.k, ci, cg, flag);
         if (KIND == MECH_SYN) {
             const double sc = 1e2 / a.nd.area[ni];
             ci *= sc;
             cg *= sc;
         }
-        if (a.slot.identity) {
+    }
+    if (a.slot.identity) {
+        // one instance per node: a plain read-modify-write, ordered after the
+        // previous type's kernel on the stream
+        if (ni >= 0) {
             a.nd.rhs[ni] -= ci;
             a.nd.d[ni] += cg;
-        } else {
-            unsafeAtomicAdd(&a.nd.rhs[ni], -ci);
-            unsafeAtomicAdd(&a.nd.d[ni], cg);
         }
+    } else if (segmented_sum(ni, ci, cg)) {
+        // node-sorted instances: one FP64 atomic per node run in the wave
+        unsafeAtomicAdd(&a.nd.rhs[ni], -ci);
+        unsafeAtomicAdd(&a.nd.d[ni], cg);
     }
     if (flag) atomicOr(a.err, 1);
 }

@@ -53,6 +53,8 @@ struct Globals {
     double tau_r_ampa = 0.2, tau_d_ampa = 1.7, tau_r_nmda = 0.29, tau_d_nmda = 43.0;
     double event_rate_hz = 5.0, vthresh = -20.0, fd_dv = 1e-3;
     uint64_t event_seed = 0;
+    int analytic_conductance = 0;   // closed-form di/dv instead of the finite difference
+    int pade_cnexp = 0;             // (1,1) Pade approximant of the cnexp exponential
 };
 
 struct SlotHost {
@@ -182,13 +184,24 @@ GlobDev make_glob(const mech_ctx *c, double dt) {
     g.fa = peak(G.tau_r_ampa, G.tau_d_ampa);
     g.fn = peak(G.tau_r_nmda, G.tau_d_nmda);
     g.dt = dt;
+    // cnexp factor of a linear decay over dt: exp(-y), y = dt/tau, or its
+    // (1,1) Pade approximant (1 - y/2)/(1 + y/2); 1 - factor in a form with no
+    // cancellation for the FP32 updates
+    auto factor = [&](double tau, double *f, double *omf) {
+        const double y = dt / tau;
+        if (G.pade_cnexp) {
+            *f = (1.0 - y / 2.0) / (1.0 + y / 2.0);
+            *omf = y / (1.0 + y / 2.0);
+        } else {
+            *f = std::exp(-y);
+            *omf = -std::expm1(-y);
+        }
+    };
     const double taus[4] = {G.tau_r_ampa, G.tau_d_ampa, G.tau_r_nmda, G.tau_d_nmda};
-    for (int j = 0; j < 4; ++j) {
-        g.decay[j] = std::exp(-dt / taus[j]);
-        g.omdecay[j] = -std::expm1(-dt / taus[j]);
-    }
-    g.ca_decay = std::exp(-dt / G.tau_ca);
-    g.ca_omdecay = -std::expm1(-dt / G.tau_ca);
+    for (int j = 0; j < 4; ++j) factor(taus[j], &g.decay[j], &g.omdecay[j]);
+    factor(G.tau_ca, &g.ca_decay, &g.ca_omdecay);
+    g.analytic_g = G.analytic_conductance ? 1 : 0;
+    g.pade = G.pade_cnexp ? 1 : 0;
     g.seed = G.event_seed;
     // fire with probability p = rate*dt: draws below floor(p * 2^64)
     const double p = G.event_rate_hz * dt * 1e-3;
@@ -634,6 +647,12 @@ int mech_set_global(mech_ctx *c, const char *name, double value) {
         if (!(value >= 0.0) || value >= 9007199254740992.0 || value != std::floor(value))
             return fail(c, MECH_ERR_INVAL, "event_seed must be an integer in [0, 2^53)");
         G.event_seed = (uint64_t)value;
+        clear_graphs(c);
+        return MECH_OK;
+    }
+    if (!strcmp(name, "analytic_conductance") || !strcmp(name, "pade_cnexp")) {
+        if (value != 0.0 && value != 1.0) return fail(c, MECH_ERR_INVAL, "%s must be 0 or 1", name);
+        (name[0] == 'a' ? G.analytic_conductance : G.pade_cnexp) = value != 0.0;
         clear_graphs(c);
         return MECH_OK;
     }

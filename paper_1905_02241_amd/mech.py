@@ -24,7 +24,7 @@ VMODE = {"external": 0, "clamp": 1, "isolated": 2}
 PATH = {"plain": 0, "batched": 1}
 GLOBAL_NAMES = ("celsius", "ena", "ek", "eh", "cao", "cai0", "tau_ca", "ca_gamma", "ca_depth", "e_syn",
                 "mg", "tau_r_ampa", "tau_d_ampa", "tau_r_nmda", "tau_d_nmda", "event_rate_hz", "event_seed",
-                "vthresh", "fd_dv")
+                "vthresh", "fd_dv", "analytic_conductance", "pade_cnexp")
 
 # Exported symbols of include/mech.h (checked by the CPU tests).
 SYMBOLS = ("mech_required_bytes", "mech_alloc", "mech_bind_nodes", "mech_bind_clamp", "mech_set_params",

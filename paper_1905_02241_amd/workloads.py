@@ -20,7 +20,7 @@ from typing import Dict, List, Optional
 
 import numpy as np
 
-KINDS = ("pas", "hh", "ih", "cahva", "syn")
+KINDS = ("pas", "hh", "ih", "cahva", "syn", "kmarkov", "capump")
 KIND_ID = {k: i for i, k in enumerate(KINDS)}
 
 # Variable names of every mechanism type (interface only).
@@ -30,6 +30,8 @@ PARAM_NAMES = {
     "ih": ("gbar",),
     "cahva": ("gbar",),
     "syn": ("weight",),
+    "kmarkov": ("gbar",),
+    "capump": ("gbar",),
 }
 STATE_NAMES = {
     "pas": (),
@@ -37,6 +39,8 @@ STATE_NAMES = {
     "ih": ("m",),
     "cahva": ("m", "h", "cai"),
     "syn": ("A_ampa", "B_ampa", "A_nmda", "B_nmda"),
+    "kmarkov": ("C1", "C2", "O"),
+    "capump": ("m", "h", "cai"),
 }
 PARAM_DEFAULTS = {
     "pas": {"g": 1e-3, "e": -70.0},
@@ -44,6 +48,8 @@ PARAM_DEFAULTS = {
     "ih": {"gbar": 1e-4},
     "cahva": {"gbar": 5e-5},
     "syn": {"weight": 1.0},
+    "kmarkov": {"gbar": 0.01},
+    "capump": {"gbar": 5e-5},
 }
 
 DEFAULT_GLOBALS = {
@@ -68,6 +74,9 @@ DEFAULT_GLOBALS = {
     "event_seed": 0,
     "analytic_conductance": 0,   # section 5.2: closed-form di/dv instead of the finite difference
     "pade_cnexp": 0,             # section 5.2: (1,1) Pade approximant of the cnexp exponential
+    "pump_vmax": 1e-4,           # capump: maximal pump rate (mM/ms)
+    "pump_kp": 1e-3,             # capump: pump half-activation (mM)
+    "newton_iters": 4,           # capump: Newton steps per implicit Euler step
 }
 
 VMODES = ("external", "clamp", "isolated")

@@ -320,3 +320,34 @@ def test_config5_fp64_sampled_spikes():
     got, M, nodes = _sampled(5, 2000, "fp64", "batched", 1500)
     assert np.array_equal(got["spikes"][nodes], M.spikes)
     log(f"c5 spikes on sample: {int(M.spikes.sum())}")
+
+
+# ------------------------------------------ section 5.2 variants (F1, F2) --
+@pytest.mark.parametrize("variant", ["analytic_conductance", "pade_cnexp", "both"])
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("prec", PRECS)
+def test_variants_parity(variant, path, prec):
+    """Closed-form conductance and Pade cnexp, each against the oracle's own
+    variant, on all five types in clamp mode."""
+    w = W.make_tiny(31, per_node=2, nsteps=60)
+    for k in (("analytic_conductance", "pade_cnexp") if variant == "both" else (variant,)):
+        w.globals[k] = 1
+    got, m = run_gpu(w, 60, path, prec)
+    M = run_oracle(w, 60)
+    compare_states(got, M, prec, label=variant)
+    compare_nodes(got, M, prec, label=variant)
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_variants_isolated_fp64(path):
+    w = W.make_tiny(32, kinds=("pas", "hh", "cahva", "syn"), n_nodes=40, syn_per_node=6.0,
+                    vmode="isolated", event_rate_hz=300.0, nsteps=400)
+    w.area[:] = np.linspace(100.0, 400.0, w.n_nodes)
+    w.slots[-1].params["weight"][:] *= 6.0
+    w.globals["analytic_conductance"] = 1
+    w.globals["pade_cnexp"] = 1
+    got, m = run_gpu(w, 400, path, "fp64")
+    M = run_oracle(w, 400)
+    assert np.array_equal(got["spikes"], M.spikes)
+    compare_states(got, M, "fp64", label="variants isolated")
+    compare_nodes(got, M, "fp64", label="variants isolated")

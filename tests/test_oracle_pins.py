@@ -503,3 +503,100 @@ def test_pade_synapse_decay(oracle):
     a0 = M.states[0]["B_nmda"][0]
     M.run(1, 200)
     assert abs(M.states[0]["B_nmda"][0] - a0 * _pade(0.025 / 43.0) ** 200) < 1e-14 * a0
+
+
+# ------------------------------------- implicit solves (F3): kmarkov, capump --
+def test_kmarkov_matrix_conserves_probability(oracle):
+    """I - dt A with a generator A (columns summing to zero): every column of
+    the implicit Euler matrix sums to one, so C1 + C2 + O is conserved."""
+    for v in (-90.0, -55.0, -20.0, 30.0):
+        M = oracle.kmarkov_matrix(v, 6.3, 0.025)
+        assert np.allclose(M.sum(axis=0), 1.0, rtol=0, atol=1e-15)
+        assert np.all(np.diag(M) >= 1.0) and np.all(M - np.diag(np.diag(M)) <= 0)
+
+
+def test_kmarkov_step_equals_library_solve(oracle):
+    rng = np.random.default_rng(8)
+    for v in rng.uniform(-100, 50, 20):
+        x = rng.dirichlet(np.ones(3))
+        ref = np.linalg.solve(oracle.kmarkov_matrix(v, 6.3, 0.025), x)
+        got = oracle.kmarkov_step(v, 6.3, 0.025, x)
+        assert np.allclose(got, ref, rtol=1e-14, atol=1e-16)
+        assert abs(got.sum() - 1.0) < 4e-16
+
+
+def test_kmarkov_equilibrium_is_binomial_fixed_point(oracle):
+    for v in (-80.0, -40.0, 10.0):
+        n = oracle.hh_inf_tau(v, 6.3)[2]
+        x = np.array([(1 - n) ** 2, 2 * n * (1 - n), n * n])
+        y = oracle.kmarkov_step(v, 6.3, 0.025, x)
+        assert np.allclose(y, x, rtol=0, atol=2e-16)
+
+
+def test_kmarkov_converges_to_two_gate_solution(oracle):
+    """The scheme C1 <-(2a,b)-> C2 <-(a,2b)-> O is two independent n-gates:
+    from a binomial start the exact O(t) is n(t)^2 with n(t) the HH gate.
+    Implicit Euler approaches it at first order in dt."""
+    v0, v1, T = -65.0, -10.0, 2.0
+    n0 = oracle.hh_inf_tau(v0, 6.3)[2]
+    ninf, tau = oracle.hh_inf_tau(v1, 6.3)[2], oracle.hh_inf_tau(v1, 6.3)[5]
+    exact = (ninf + (n0 - ninf) * math.exp(-T / tau)) ** 2
+    errs = []
+    for dt in (0.02, 0.01, 0.005):
+        x = np.array([(1 - n0) ** 2, 2 * n0 * (1 - n0), n0 * n0])
+        for _ in range(int(round(T / dt))):
+            x = oracle.kmarkov_step(v1, 6.3, dt, x)
+        errs.append(abs(x[2] - exact))
+    assert errs[0] < 2e-3
+    assert 1.7 < errs[0] / errs[1] < 2.3 and 1.7 < errs[1] / errs[2] < 2.3
+
+
+def test_capump_newton_solves_implicit_equation(oracle):
+    """derivimplicit: four Newton steps reach the root of the implicit Euler
+    equation; scipy's bracketing root finder on the same equation agrees."""
+    from scipy.optimize import brentq
+    w = _single("capump", -65.0, 1)
+    M = oracle.Model(w)
+    kappa = oracle.ca_kappa(0.05, 0.1)
+    vmax, kp, c0r = 1e-4, 1e-3, 5e-5
+    F = lambda c, ica: -kappa * ica - vmax * (c / (c + kp) - c0r / (c0r + kp))
+    for ica, c in ((-2e-3, 5e-5), (-1e-2, 3e-3), (0.0, 2e-3), (-5e-4, 1e-6)):
+        got, res = M.capump_step(ica, c, 4)
+        assert abs(res) <= 1e-18 + 1e-15 * got
+        ref = brentq(lambda x: x - c - 0.025 * F(x, ica), 1e-12, 1.0, xtol=1e-22, rtol=9e-16)
+        assert abs(got - ref) <= 4e-15 * ref
+
+
+def test_capump_reduces_to_linear_implicit_euler(oracle):
+    """vmax = 0: F is constant, so implicit Euler is c + dt(-kappa ica)."""
+    w = _single("capump", -65.0, 1)
+    w.globals["pump_vmax"] = 0.0
+    M = oracle.Model(w)
+    kappa = oracle.ca_kappa(0.05, 0.1)
+    got, _ = M.capump_step(-3e-3, 1e-4, 4)
+    assert abs(got - (1e-4 + 0.025 * kappa * 3e-3)) < 1e-18
+
+
+def test_capump_rest_is_fixed_point_and_relaxation_monotone(oracle):
+    w = _single("capump", -65.0, 1)
+    M = oracle.Model(w)
+    got, _ = M.capump_step(0.0, 5e-5, 4)
+    assert got == 5e-5
+    c = 2e-3
+    prev = c
+    for _ in range(200):
+        c, _ = M.capump_step(0.0, c, 4)
+        assert 5e-5 < c < prev
+        prev = c
+
+
+def test_new_kinds_vanish_at_reversal(oracle):
+    w = _single("kmarkov", 0.0, 1)
+    M = oracle.Model(w)
+    M.init()
+    assert M.instance_current(0, 0, -77.0)[0] == 0.0
+    w = _single("capump", 0.0, 1)
+    M = oracle.Model(w)
+    M.init()
+    eca = oracle.nernst_ca(5e-5, 2.0, 6.3)
+    assert M.instance_current(0, 0, eca)[0] == 0.0
