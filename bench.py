@@ -152,6 +152,53 @@ def cpu_baseline(w, target_s: float, nodes: int):
                       f"single-threaded FP64 C, {dt:.1f} s"}
 
 
+def precision_report(w, steps: int, sample: int, torch, mech):
+    """Per-state error of the FP64 and FP32-mixed batched paths against the
+    oracle on a node sample after `steps` steps (the precision contract)."""
+    import numpy as np
+    from oracle import oracle as O
+    from paper_1905_02241_amd import workloads as W
+    rng = np.random.default_rng(11)
+    nodes = np.sort(rng.choice(w.n_nodes, size=min(sample, w.n_nodes), replace=False))
+    sub, keep = W.subset(w, nodes)
+    M = O.Model(sub)
+    M.init()
+    M.run(0, steps)
+    out = {"steps": steps, "sample_nodes": int(nodes.shape[0]), "vmode": w.vmode}
+    for prec in ("fp64", "fp32"):
+        m = mech.from_workload(w, prec)
+        cached = None
+        try:
+            from paper_1905_02241_amd import tuning
+            cached = tuning.lookup(w, prec)
+        except Exception:
+            cached = None
+        if cached:
+            m.set_launch(*cached)
+        m.step(steps, 0, w.dt, w.vmode, "batched")
+        m.sync()
+        st = mech.states_of(m)
+        rep = {}
+        for s, sl in enumerate(sub.slots):
+            for name, ref in M.states[s].items():
+                g = st[s][name][keep[s]]
+                if ref.size == 0:
+                    continue
+                err = np.abs(g - ref)
+                rel = err / np.maximum(np.abs(ref), 1e-300)
+                rep[f"{sl.kind}.{name}"] = {"max_abs": float(err.max()), "max_rel": float(rel.max())}
+        v = m.v.cpu().numpy()[nodes]
+        rep["v"] = {"max_abs": float(np.max(np.abs(v - M.v)))}
+        if w.vmode == "isolated":
+            sp = m.spike_counts()[nodes]
+            rep["spikes"] = {"match_rate": float(np.mean(sp == M.spikes)), "oracle_total": int(M.spikes.sum()),
+                             "gpu_total": int(sp.sum())}
+        out[prec] = rep
+        m.close()
+        log(f"precision {prec}: " + ", ".join(f"{k} {v.get('max_abs', 0):.3g}" for k, v in rep.items()))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -167,6 +214,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-nodes", type=int, default=20000)
+    ap.add_argument("--precision-report", type=int, default=0, metavar="NODES",
+                    help="instead of timing: per-state error of FP64 and FP32-mixed vs the oracle on a node sample")
     ap.add_argument("--launch", default=None,
                     help="fixed batched launch shape 'block,tile_instances,tile_nodes,blocks_per_cu' (no autotune)")
     args = ap.parse_args()
@@ -187,6 +236,11 @@ def main():
     t0 = time.perf_counter()
     w = W.make_config(args.config, scale=args.scale)
     log(f"workload {w.name}: {w.n_nodes} nodes, {w.instance_counts()}, built in {time.perf_counter() - t0:.1f}s")
+
+    if args.precision_report:
+        rep = precision_report(w, args.steps, args.precision_report, torch, mech)
+        print(json.dumps({"precision_report": rep, "workload": w.name}), flush=True)
+        return
 
     res = {}
     for v in args.variants.split(","):

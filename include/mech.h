@@ -32,6 +32,15 @@
  *               to both rise (A) and decay (B) states of each receptor
  *                                                           params weight (nS)
  *                                                           states A_ampa, B_ampa, A_nmda, B_nmda
+ *   MECH_KMARKOV density, three-state potassium scheme C1 <-> C2 <-> O with
+ *               the Hodgkin-Huxley n rates (2a, b, a, 2b), i = gbar O (v - ek),
+ *               advanced by implicit Euler: one 3x3 linear solve per instance
+ *               (the sparse method of section 5.2)      params gbar; states C1, C2, O
+ *   MECH_CAPUMP density, Ca-HVA gates with a calcium pool emptied by a
+ *               saturable pump, vmax (c/(c+kp) - cai0/(cai0+kp)); the pool's
+ *               implicit Euler equation is solved by Newton's method with the
+ *               analytic derivative (derivimplicit, section 5.2)
+ *                                                           params gbar; states m, h, cai
  *
  * Units: mV, ms, mA/cm2 and S/cm2 for density mechanisms, nA and uS for the
  * synapse (scaled by 100/area into the node vectors), um2, uF/cm2, mM, degC,
@@ -82,7 +91,7 @@ enum {
     MECH_ERR_NONFINITE = -6    /* a kernel produced a non-finite STATE          */
 };
 
-enum { MECH_PAS = 0, MECH_HH = 1, MECH_IH = 2, MECH_CAHVA = 3, MECH_SYN = 4 };
+enum { MECH_PAS = 0, MECH_HH = 1, MECH_IH = 2, MECH_CAHVA = 3, MECH_SYN = 4, MECH_KMARKOV = 5, MECH_CAPUMP = 6 };
 enum { MECH_FP64 = 0, MECH_FP32_MIXED = 1 };
 /* voltage provision between the current and the state update of a step
  * (section 8, Table 3 "Other"):
@@ -139,7 +148,7 @@ int mech_bind_clamp(mech_ctx *ctx, const double *off, const double *amp, const d
 /* Set the RANGE parameter `name` of type slot `type_slot` from host memory:
  * n == 1 broadcasts one value, n == count gives one value per instance in the
  * caller's order.  Names: pas g,e; hh gnabar,gkbar,gl,el; ih gbar;
- * cahva gbar; syn weight.                                                  */
+ * cahva gbar; syn weight; kmarkov gbar; capump gbar.                       */
 int mech_set_params(mech_ctx *ctx, int type_slot, const char *name, const double *host_vals, int64_t n);
 
 /* Set a global: celsius, ena, ek, eh, cao, cai0, tau_ca, ca_gamma, ca_depth,
@@ -151,7 +160,9 @@ int mech_set_params(mech_ctx *ctx, int type_slot, const char *name, const double
  *   pade_cnexp            every cnexp factor exp(-dt/tau) replaced by its
  *                         (1,1) Pade approximant (1 - y/2)/(1 + y/2),
  *                         y = dt/tau (requires y < 2 to keep gates in
- *                         [0, 1]).                                          */
+ *                         [0, 1]);
+ * and the pump of MECH_CAPUMP: pump_vmax (mM/ms), pump_kp (mM),
+ * newton_iters (1..16 Newton steps per implicit Euler step, default 4).    */
 int mech_set_global(mech_ctx *ctx, const char *name, double value);
 
 /* INITIAL (section 3): every gate at its steady state x_inf(v) at the bound
@@ -194,7 +205,7 @@ int mech_get_launch(const mech_ctx *ctx, int *block, int *tile_instances, int *t
  * after, so the call has no visible effect besides the chosen shape.      */
 int mech_autotune(mech_ctx *ctx, double dt, int vmode, int nsteps, int reps, double *best_ms_per_step);
 
-/* Copy STATE `name` (or "ica" for Ca-HVA) of type slot `type_slot` to /
+/* Copy STATE `name` (or "ica" for Ca-HVA and capump) of type slot `type_slot` to /
  * from host doubles in the caller's instance order; n must equal count.   */
 int mech_get_state(mech_ctx *ctx, int type_slot, const char *name, double *host_out, int64_t n);
 int mech_set_state(mech_ctx *ctx, int type_slot, const char *name, const double *host_in, int64_t n);

@@ -52,6 +52,9 @@ struct GlobDev {
     uint64_t seed, threshold;  // event draws: fire when H(seed, gid, k) < threshold
     int analytic_g;            // conductance in closed form instead of the finite difference
     int pade;                  // cnexp factor exp(-y) replaced by (1 - y/2)/(1 + y/2)
+    double kappa;              // calcium influx per unit current, mM/ms per mA/cm2
+    double pump_vmax, pump_kp, pump_rest;   // pump_rest = vmax cai0/(cai0 + kp)
+    int newton_iters;
 };
 
 struct NodesDev {

@@ -200,6 +200,64 @@ __device__ __forceinline__ void ca_inf(double v, double &m, double &h) {
     h = ah / (ah + bh);
 }
 
+// kmarkov: C1 <-(2a, b)-> C2 <-(a, 2b)-> O with a = q10 alpha_n, b = q10
+// beta_n; implicit Euler (I - dt A) x_new = x_old is tridiagonal and
+// diagonally dominant by columns, so the Thomas elimination needs no pivot.
+template <class T>
+__device__ __forceinline__ void kmarkov_solve(T a, T b, T dt, T &c1, T &c2, T &o) {
+    const T d0 = T(1) + T(2) * a * dt, u0 = -b * dt;
+    const T l1 = T(-2) * a * dt, d1 = T(1) + (a + b) * dt, u1 = T(-2) * b * dt;
+    const T l2 = -a * dt, d2 = T(1) + T(2) * b * dt;
+    const T r0 = T(1) / d0;
+    const T c0p = u0 * r0, x0p = c1 * r0;
+    const T d1p = d1 - l1 * c0p;
+    const T r1 = T(1) / d1p;
+    const T c1p = u1 * r1, x1p = (c2 - l1 * x0p) * r1;
+    const T d2p = d2 - l2 * c1p;
+    o = (o - l2 * x1p) / d2p;
+    c2 = x1p - c1p * o;
+    c1 = x0p - c0p * c2;
+}
+__device__ __forceinline__ void kmarkov_state(double v, const GlobDev &g, double &c1, double &c2, double &o) {
+    const double an = linexp_d(0.01, 0.1, v + 55.0, 0.1);
+    const double bn = 0.125 * exp((v + 65.0) * (-1.0 / 80.0));
+    kmarkov_solve<double>(g.q10 * an, g.q10 * bn, g.dt, c1, c2, o);
+}
+__device__ __forceinline__ void kmarkov_state(double vd, const GlobDev &g, float &c1, float &c2, float &o) {
+    const float v = (float)vd;
+    const float an = linexp_f(0.01f, 10.0f, v + 55.0f);
+    const float bn = 0.125f * fexp((v + 65.0f) * (-1.0f / 80.0f));
+    const float q = (float)g.q10;
+    kmarkov_solve<float>(q * an, q * bn, (float)g.dt, c1, c2, o);
+}
+
+// capump pool: implicit Euler c - c_old - dt F(c) = 0, F(c) = -kappa ica -
+// vmax (c/(c+kp) - cai0/(cai0+kp)), by a fixed number of Newton steps on the
+// analytic derivative F'(c) = -vmax kp/(c+kp)^2, starting from c_old.
+__device__ __forceinline__ void capump_pool(const GlobDev &g, double ica, double &cai) {
+    const double c0 = cai, infl = -g.kappa * ica;
+    double c = c0;
+    for (int it = 0; it < g.newton_iters; ++it) {
+        const double r = fdiv(1.0, c + g.pump_kp);
+        const double F = infl - (g.pump_vmax * (c * r) - g.pump_rest);
+        const double dF = -g.pump_vmax * g.pump_kp * (r * r);
+        c -= fdiv(c - c0 - g.dt * F, 1.0 - g.dt * dF);
+    }
+    cai = c;
+}
+__device__ __forceinline__ void capump_pool(const GlobDev &g, float ica, float &cai) {
+    const float c0 = cai, infl = -(float)g.kappa * ica, vmax = (float)g.pump_vmax, kp = (float)g.pump_kp;
+    const float rest = (float)g.pump_rest, dt = (float)g.dt;
+    float c = c0;
+    for (int it = 0; it < g.newton_iters; ++it) {
+        const float r = 1.0f / (c + kp);
+        const float F = infl - (vmax * (c * r) - rest);
+        const float dF = -vmax * kp * (r * r);
+        c -= (c - c0 - dt * F) / (1.0f - dt * dF);
+    }
+    cai = c;
+}
+
 // Synapse decay: A <- A e^{-dt/tau}; in FP32 A <- A - A (1 - e^{-dt/tau}),
 // which keeps the rounding of the factor from being amplified by tau/dt.
 __device__ __forceinline__ void syn_decay(double *x, const GlobDev &g) {
@@ -370,6 +428,38 @@ __device__ __forceinline__ void instance(const SlotDev &sl, int i, double v, con
                 st<NT>(CAI + i, cai);
             }
         }
+    } else if constexpr (KIND == MECH_KMARKOV) {
+        S *X0 = (S *)sl.st[0], *X1 = (S *)sl.st[1], *X2 = (S *)sl.st[2];
+        S c1 = ld<NT>(X0 + i), c2 = ld<NT>(X1 + i), o = ld<NT>(X2 + i);
+        if (PH & kDoState) {
+            kmarkov_state(v, g, c1, c2, o);
+            flag |= bad(c1) | bad(c2) | bad(o);
+            st<NT>(X0 + i, c1); st<NT>(X1 + i, c2); st<NT>(X2 + i, o);
+        }
+        if (PH & kDoCur) {
+            const S gbar = ld<NT>((const S *)sl.par[0] + i);
+            lin_cur<S>(v, (S)(gbar * o), g.ek, g, ci, cg);
+        }
+    } else if constexpr (KIND == MECH_CAPUMP) {
+        S *M = (S *)sl.st[0], *H = (S *)sl.st[1], *CAI = (S *)sl.st[2], *ICA = (S *)sl.ica;
+        S m = ld<NT>(M + i), h = ld<NT>(H + i), cai = ld<NT>(CAI + i);
+        if (PH & kDoState) {
+            ca_gates(v, g, m, h);
+            if (!FOLD) capump_pool(g, ld<NT>(ICA + i), cai);
+            flag |= bad(m) | bad(h) | bad(cai);
+            st<NT>(M + i, m); st<NT>(H + i, h);
+            if (!FOLD) st<NT>(CAI + i, cai);
+        }
+        if (PH & kDoCur) {
+            const S gbar = ld<NT>((const S *)sl.par[0] + i);
+            const S ica = (S)ca_cur<S>(v, m, h, cai, gbar, g, ci, cg);
+            st<NT>(ICA + i, ica);
+            if (FOLD) {
+                capump_pool(g, ica, cai);
+                flag |= bad(cai);
+                st<NT>(CAI + i, cai);
+            }
+        }
     } else if constexpr (KIND == MECH_SYN) {
         S x[4];
 #pragma unroll
@@ -471,11 +561,17 @@ __global__ __launch_bounds__(256) void k_init(PlainArgs a) {
         st[0][i] = (S)m; st[1][i] = (S)h; st[2][i] = (S)n;
     } else if constexpr (KIND == MECH_IH) {
         st[0][i] = (S)ih_inf(v);
-    } else if constexpr (KIND == MECH_CAHVA) {
+    } else if constexpr (KIND == MECH_CAHVA || KIND == MECH_CAPUMP) {
         double m, h;
         ca_inf(v, m, h);
         st[0][i] = (S)m; st[1][i] = (S)h; st[2][i] = (S)a.g.cai0;
         ((S *)a.slot.ica)[i] = (S)0;
+    } else if constexpr (KIND == MECH_KMARKOV) {
+        double m, h, n;
+        hh_inf(v, m, h, n);
+        st[0][i] = (S)((1.0 - n) * (1.0 - n));
+        st[1][i] = (S)(2.0 * n * (1.0 - n));
+        st[2][i] = (S)(n * n);
     } else if constexpr (KIND == MECH_SYN) {
         for (int j = 0; j < 4; ++j) st[j][i] = (S)0;
     }
@@ -583,6 +679,8 @@ __global__ __launch_bounds__(1024) void k_fused(FusedArgs a, int tn) {
             case MECH_IH: tile_slot<S, MECH_IH, PH, NT>(sl, lo, hi, nlo, vl, sc, ar, ad, a.g, k, flag); break;
             case MECH_CAHVA: tile_slot<S, MECH_CAHVA, PH, NT>(sl, lo, hi, nlo, vl, sc, ar, ad, a.g, k, flag); break;
             case MECH_SYN: tile_slot<S, MECH_SYN, PH, NT>(sl, lo, hi, nlo, vl, sc, ar, ad, a.g, k, flag); break;
+            case MECH_KMARKOV: tile_slot<S, MECH_KMARKOV, PH, NT>(sl, lo, hi, nlo, vl, sc, ar, ad, a.g, k, flag); break;
+            case MECH_CAPUMP: tile_slot<S, MECH_CAPUMP, PH, NT>(sl, lo, hi, nlo, vl, sc, ar, ad, a.g, k, flag); break;
             default: break;
             }
         }
@@ -690,6 +788,8 @@ static hipError_t init_t(const PlainArgs &a, hipStream_t s) {
     case MECH_IH: k_init<S, MECH_IH><<<gr, 256, 0, s>>>(a); break;
     case MECH_CAHVA: k_init<S, MECH_CAHVA><<<gr, 256, 0, s>>>(a); break;
     case MECH_SYN: k_init<S, MECH_SYN><<<gr, 256, 0, s>>>(a); break;
+    case MECH_KMARKOV: k_init<S, MECH_KMARKOV><<<gr, 256, 0, s>>>(a); break;
+    case MECH_CAPUMP: k_init<S, MECH_CAPUMP><<<gr, 256, 0, s>>>(a); break;
     default: break;
     }
     return hipGetLastError();
@@ -708,6 +808,8 @@ static hipError_t cur_t(const PlainArgs &a, hipStream_t s) {
     case MECH_IH: k_plain_cur<S, MECH_IH><<<gr, 256, 0, s>>>(a); break;
     case MECH_CAHVA: k_plain_cur<S, MECH_CAHVA><<<gr, 256, 0, s>>>(a); break;
     case MECH_SYN: k_plain_cur<S, MECH_SYN><<<gr, 256, 0, s>>>(a); break;
+    case MECH_KMARKOV: k_plain_cur<S, MECH_KMARKOV><<<gr, 256, 0, s>>>(a); break;
+    case MECH_CAPUMP: k_plain_cur<S, MECH_CAPUMP><<<gr, 256, 0, s>>>(a); break;
     default: break;
     }
     return hipGetLastError();
@@ -725,6 +827,8 @@ static hipError_t state_t(const PlainArgs &a, hipStream_t s) {
     case MECH_IH: k_plain_state<S, MECH_IH><<<gr, 256, 0, s>>>(a); break;
     case MECH_CAHVA: k_plain_state<S, MECH_CAHVA><<<gr, 256, 0, s>>>(a); break;
     case MECH_SYN: k_plain_state<S, MECH_SYN><<<gr, 256, 0, s>>>(a); break;
+    case MECH_KMARKOV: k_plain_state<S, MECH_KMARKOV><<<gr, 256, 0, s>>>(a); break;
+    case MECH_CAPUMP: k_plain_state<S, MECH_CAPUMP><<<gr, 256, 0, s>>>(a); break;
     default: break;  // pas has no STATE
     }
     return hipGetLastError();

@@ -37,13 +37,15 @@ struct KindDesc {
     double defaults[kMaxParams];
 };
 
-const KindDesc kKinds[5] = {
+const KindDesc kKinds[7] = {
     {"pas", false, 0, {}, 2, {{"g", false}, {"e", true}}, {1e-3, -70.0}},
     {"hh", false, 3, {"m", "h", "n"}, 4,
      {{"gnabar", false}, {"gkbar", false}, {"gl", false}, {"el", true}}, {0.12, 0.036, 0.0003, -54.3}},
     {"ih", false, 1, {"m"}, 1, {{"gbar", false}}, {1e-4}},
     {"cahva", false, 3, {"m", "h", "cai"}, 1, {{"gbar", false}}, {5e-5}},
     {"syn", true, 4, {"A_ampa", "B_ampa", "A_nmda", "B_nmda"}, 1, {{"weight", true}}, {1.0}},
+    {"kmarkov", false, 3, {"C1", "C2", "O"}, 1, {{"gbar", false}}, {0.01}},
+    {"capump", false, 3, {"m", "h", "cai"}, 1, {{"gbar", false}}, {5e-5}},
 };
 
 struct Globals {
@@ -55,6 +57,8 @@ struct Globals {
     uint64_t event_seed = 0;
     int analytic_conductance = 0;   // closed-form di/dv instead of the finite difference
     int pade_cnexp = 0;             // (1,1) Pade approximant of the cnexp exponential
+    double pump_vmax = 1e-4, pump_kp = 1e-3;
+    int newton_iters = 4;
 };
 
 struct SlotHost {
@@ -94,7 +98,7 @@ void compute_layout(int64_t n_nodes, std::vector<SlotHost> &slots, int prec, Lay
             s.off_par[j] = off;
             off = align_up(off + (K.param[j].is_double ? 8 : ss) * (size_t)s.np);
         }
-        s.has_ica = s.kind == MECH_CAHVA;
+        s.has_ica = s.kind == MECH_CAHVA || s.kind == MECH_CAPUMP;
         if (s.has_ica) { s.off_ica = off; off = align_up(off + ss * (size_t)s.np); }
     }
     L.inst_end = off;
@@ -202,6 +206,11 @@ GlobDev make_glob(const mech_ctx *c, double dt) {
     factor(G.tau_ca, &g.ca_decay, &g.ca_omdecay);
     g.analytic_g = G.analytic_conductance ? 1 : 0;
     g.pade = G.pade_cnexp ? 1 : 0;
+    g.kappa = kappa;
+    g.pump_vmax = G.pump_vmax;
+    g.pump_kp = G.pump_kp;
+    g.pump_rest = G.pump_vmax * (G.cai0 / (G.cai0 + G.pump_kp));
+    g.newton_iters = G.newton_iters;
     g.seed = G.event_seed;
     // fire with probability p = rate*dt: draws below floor(p * 2^64)
     const double p = G.event_rate_hz * dt * 1e-3;
@@ -471,7 +480,7 @@ static int validate_types(int64_t n_nodes, const mech_type_desc *types, int n_ty
     if (n_types > 0 && !types) return fail(nullptr, MECH_ERR_INVAL, "null types");
     if (prec != MECH_FP64 && prec != MECH_FP32_MIXED) return fail(nullptr, MECH_ERR_INVAL, "bad precision %d", prec);
     for (int s = 0; s < n_types; ++s) {
-        if (types[s].kind < MECH_PAS || types[s].kind > MECH_SYN)
+        if (types[s].kind < MECH_PAS || types[s].kind > MECH_CAPUMP)
             return fail(nullptr, MECH_ERR_INVAL, "type %d: bad kind %d", s, types[s].kind);
         if (types[s].count < 0 || types[s].count >= (int64_t(1) << 31))
             return fail(nullptr, MECH_ERR_INVAL, "type %d: bad count", s);
@@ -642,7 +651,14 @@ int mech_set_global(mech_ctx *c, const char *name, double value) {
         {"cai0", &G.cai0}, {"tau_ca", &G.tau_ca}, {"ca_gamma", &G.ca_gamma}, {"ca_depth", &G.ca_depth},
         {"e_syn", &G.e_syn}, {"mg", &G.mg}, {"tau_r_ampa", &G.tau_r_ampa}, {"tau_d_ampa", &G.tau_d_ampa},
         {"tau_r_nmda", &G.tau_r_nmda}, {"tau_d_nmda", &G.tau_d_nmda}, {"event_rate_hz", &G.event_rate_hz},
-        {"vthresh", &G.vthresh}, {"fd_dv", &G.fd_dv}};
+        {"vthresh", &G.vthresh}, {"fd_dv", &G.fd_dv}, {"pump_vmax", &G.pump_vmax}, {"pump_kp", &G.pump_kp}};
+    if (!strcmp(name, "newton_iters")) {
+        if (!(value >= 1.0 && value <= 16.0) || value != std::floor(value))
+            return fail(c, MECH_ERR_INVAL, "newton_iters must be an integer in [1, 16]");
+        G.newton_iters = (int)value;
+        clear_graphs(c);
+        return MECH_OK;
+    }
     if (!strcmp(name, "event_seed")) {
         if (!(value >= 0.0) || value >= 9007199254740992.0 || value != std::floor(value))
             return fail(c, MECH_ERR_INVAL, "event_seed must be an integer in [0, 2^53)");

@@ -351,3 +351,32 @@ def test_variants_isolated_fp64(path):
     assert np.array_equal(got["spikes"], M.spikes)
     compare_states(got, M, "fp64", label="variants isolated")
     compare_nodes(got, M, "fp64", label="variants isolated")
+
+
+# ------------------------------------------ implicit solves (F3) on the GPU --
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("prec", PRECS)
+def test_implicit_kinds_clamp(path, prec):
+    """kmarkov (3x3 implicit Euler) and capump (Newton-solved pool) next to
+    the other types, shuffled many-to-one index, clamp."""
+    w = W.make_tiny(41, kinds=("pas", "kmarkov", "capump", "syn"), per_node=2, nsteps=80)
+    w.clamp_amp[:] = 55.0
+    got, m = run_gpu(w, 80, path, prec)
+    M = run_oracle(w, 80)
+    ws = compare_states(got, M, prec, label="implicit")
+    compare_nodes(got, M, prec, label="implicit")
+    log(f"implicit {path} {prec}: worst state ratio {max(v[0] for v in ws.values()):.3g}")
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_implicit_kinds_isolated_fp64(path):
+    w = W.make_tiny(42, kinds=("pas", "hh", "kmarkov", "capump", "syn"), n_nodes=40, syn_per_node=6.0,
+                    vmode="isolated", event_rate_hz=300.0, nsteps=500)
+    w.area[:] = np.linspace(100.0, 400.0, w.n_nodes)
+    w.slots[-1].params["weight"][:] *= 6.0
+    w.globals["newton_iters"] = 3
+    got, m = run_gpu(w, 500, path, "fp64")
+    M = run_oracle(w, 500)
+    assert np.array_equal(got["spikes"], M.spikes)
+    compare_states(got, M, "fp64", label="implicit isolated")
+    compare_nodes(got, M, "fp64", label="implicit isolated")
