@@ -30,6 +30,7 @@
 
 #include <math.h>
 #include <stddef.h>
+#include <stdlib.h>
 
 #define ORC_PI 3.14159265358979323846
 #define ORC_R 8.314462618   /* J/(mol K) */
@@ -391,6 +392,52 @@ void orc_visolated(const orc_globals *gl, orc_nodes *nd, double dt) {
     }
 }
 
+/* Hines (1984) elimination on the tree matrix: node n's row holds
+ * D_n = 1e-3 cm/dt + d_n + sum of its couplings, -k_{n,p} towards its parent
+ * p and -k_{n,c} towards each child c.  Eliminating children into parents
+ * from the highest index down leaves a triangular system solved from the
+ * roots up.  parent[n] < n makes that order valid.                         */
+void orc_vcable(const orc_globals *gl, orc_nodes *nd, double dt) {
+    int64_t N = nd->n_nodes;
+    double *D = (double *)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
+    double *R = (double *)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
+    for (int64_t n = 0; n < N; ++n) {
+        D[n] = 1e-3 * nd->cm[n] / dt + nd->d[n];
+        R[n] = nd->rhs[n];
+    }
+    for (int64_t n = 0; n < N; ++n) {
+        int32_t p = nd->parent[n];
+        if (p < 0) continue;
+        double kn = 1e2 * nd->g_axial[n] / nd->area[n];   /* row n, towards p */
+        double kp = 1e2 * nd->g_axial[n] / nd->area[p];   /* row p, towards n */
+        D[n] += kn;
+        D[p] += kp;
+        R[n] += kn * (nd->v[p] - nd->v[n]);
+        R[p] += kp * (nd->v[n] - nd->v[p]);
+    }
+    for (int64_t n = N - 1; n >= 0; --n) {
+        int32_t p = nd->parent[n];
+        if (p < 0) continue;
+        double kn = 1e2 * nd->g_axial[n] / nd->area[n];
+        double kp = 1e2 * nd->g_axial[n] / nd->area[p];
+        double f = -kp / D[n];           /* row p's entry in column n over D_n */
+        D[p] -= f * -kn;
+        R[p] -= f * R[n];
+    }
+    for (int64_t n = 0; n < N; ++n) {
+        int32_t p = nd->parent[n];
+        double dv = p < 0 ? R[n] / D[n] : (R[n] - (-(1e2 * nd->g_axial[n] / nd->area[n])) * R[p]) / D[n];
+        R[n] = dv;   /* R now holds dv, parents before children */
+    }
+    for (int64_t n = 0; n < N; ++n) {
+        double v0 = nd->v[n], v1 = v0 + R[n];
+        if (nd->spikes && v0 < gl->vthresh && v1 >= gl->vthresh) nd->spikes[n] += 1;
+        nd->v[n] = v1;
+    }
+    free(D);
+    free(R);
+}
+
 /* cnexp: x' = (x_inf - x)/tau with x_inf and tau frozen over the step has the
  * exact solution x(t+dt) = x_inf + (x - x_inf) exp(-dt/tau) (section 5.2).
  * With pade_cnexp the factor exp(-y) is the (1,1) Pade approximant
@@ -468,6 +515,7 @@ int orc_run(const orc_globals *gl, orc_nodes *nd, orc_slot *slots, int nslots,
         orc_cur(gl, nd, slots, nslots);
         if (vmode == ORC_V_CLAMP) orc_vclamp(nd, (double)(k + 1) * dt);
         else if (vmode == ORC_V_ISOLATED) orc_visolated(gl, nd, dt);
+        else if (vmode == ORC_V_CABLE) orc_vcable(gl, nd, dt);
         orc_state(gl, nd, slots, nslots, dt);
     }
     return 0;

@@ -43,7 +43,7 @@ extern "C" {
 #endif
 
 enum { ORC_PAS = 0, ORC_HH = 1, ORC_IH = 2, ORC_CAHVA = 3, ORC_SYN = 4, ORC_KMARKOV = 5, ORC_CAPUMP = 6 };
-enum { ORC_V_EXTERNAL = 0, ORC_V_CLAMP = 1, ORC_V_ISOLATED = 2 };
+enum { ORC_V_EXTERNAL = 0, ORC_V_CLAMP = 1, ORC_V_ISOLATED = 2, ORC_V_CABLE = 3 };
 
 /* One mechanism type ("slot") and its instances, in the caller's order.
  *   st : STATE arrays     hh: m,h,n   ih: m   cahva: m,h,cai   syn: Aa,Ba,An,Bn
@@ -95,7 +95,13 @@ typedef struct {
     const double *area;             /* um2, NULL if no point process        */
     const double *cm;               /* uF/cm2, ISOLATED mode only            */
     const double *clamp_off, *clamp_amp, *clamp_freq, *clamp_phase;
-    int32_t *spikes;                /* ISOLATED mode only                    */
+    int32_t *spikes;                /* ISOLATED and CABLE modes              */
+    /* CABLE mode (section 8, Table 3 "Other": the tree solve between the
+     * current and the state update): parent[n] < n is node n's parent in its
+     * cell (-1 for a root), g_axial[n] the conductance (uS) of the segment
+     * between node n and its parent.                                        */
+    const int32_t *parent;
+    const double *g_axial;
 } orc_nodes;
 
 /* ---- single-point functions (used by the pins) ----------------------- */
@@ -131,6 +137,12 @@ void orc_events(const orc_globals *gl, orc_slot *slots, int nslots, int64_t k, d
 void orc_cur(const orc_globals *gl, orc_nodes *nd, orc_slot *slots, int nslots);
 void orc_vclamp(orc_nodes *nd, double t);
 void orc_visolated(const orc_globals *gl, orc_nodes *nd, double dt);
+/* Backward Euler of the cable equation linearised in v:
+ * (1e-3 cm/dt + d_n) dv_n + sum_j k_nj (dv_n - dv_j) = rhs_n + sum_j k_nj (v_j - v_n)
+ * with k_nj = 100 g_nj / area_n (S/cm2) over the tree neighbours j of n,
+ * solved by Hines' elimination (leaves to root, then root to leaves), then
+ * v += dv and spike counting as in ISOLATED mode.                         */
+void orc_vcable(const orc_globals *gl, orc_nodes *nd, double dt);
 void orc_state(const orc_globals *gl, orc_nodes *nd, orc_slot *slots, int nslots, double dt);
 /* runs steps k0 .. k0+nsteps-1; in CLAMP mode v is first set to the clamp
  * value at t_{k0}.  Returns 0, or -1 on a bad argument.                   */

@@ -21,7 +21,7 @@ SRC = os.path.join(HERE, "mech_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 KIND = {"pas": 0, "hh": 1, "ih": 2, "cahva": 3, "syn": 4, "kmarkov": 5, "capump": 6}
-VMODE = {"external": 0, "clamp": 1, "isolated": 2}
+VMODE = {"external": 0, "clamp": 1, "isolated": 2, "cable": 3}
 PARAMS = {"pas": ("g", "e"), "hh": ("gnabar", "gkbar", "gl", "el"), "ih": ("gbar",),
           "cahva": ("gbar",), "syn": ("weight",), "kmarkov": ("gbar",), "capump": ("gbar",)}
 STATES = {"pas": (), "hh": ("m", "h", "n"), "ih": ("m",), "cahva": ("m", "h", "cai"),
@@ -53,7 +53,7 @@ class _Globals(C.Structure):
 class _Nodes(C.Structure):
     _fields_ = [("n_nodes", C.c_int64), ("v", _dp), ("rhs", _dp), ("d", _dp), ("area", _dp), ("cm", _dp),
                 ("clamp_off", _dp), ("clamp_amp", _dp), ("clamp_freq", _dp), ("clamp_phase", _dp),
-                ("spikes", _ip)]
+                ("spikes", _ip), ("parent", _ip), ("g_axial", _dp)]
 
 
 def build(force: bool = False) -> str:
@@ -103,6 +103,7 @@ def lib():
         L.orc_events.argtypes = [C.POINTER(_Globals), C.POINTER(_Slot), C.c_int, C.c_int64, C.c_double]
         L.orc_vclamp.argtypes = [C.POINTER(_Nodes), C.c_double]
         L.orc_visolated.argtypes = [C.POINTER(_Globals), C.POINTER(_Nodes), C.c_double]
+        L.orc_vcable.argtypes = [C.POINTER(_Globals), C.POINTER(_Nodes), C.c_double]
         L.orc_state.argtypes = sig + [C.c_double]
         L.orc_run.argtypes = sig + [C.c_int64, C.c_int64, C.c_double, C.c_int]
         L.orc_run.restype = C.c_int
@@ -224,8 +225,14 @@ class Model:
                 sl.par[j] = _ptr(a)
             sl.ica = _ptr(ica)
         self.nslots = len(w.slots)
+        par = getattr(w, "parent", None)
+        self.parent = None if par is None else np.ascontiguousarray(par, dtype=np.int32)
+        self.g_axial = f64(getattr(w, "g_axial", None))
+        if self.parent is not None and self.parent.size and np.any(self.parent >= np.arange(n)):
+            raise ValueError("parent[n] must be < n (Hines order)")
         self._nodes = _Nodes(n, _ptr(self.v), _ptr(self.rhs), _ptr(self.d), _ptr(self.area), _ptr(self.cm),
-                             *[_ptr(a) for a in self.clamp], _ptr(self.spikes, _ip))
+                             *[_ptr(a) for a in self.clamp], _ptr(self.spikes, _ip),
+                             _ptr(self.parent, _ip), _ptr(self.g_axial))
         self._g = self._make_globals()
 
     def _make_globals(self):
@@ -267,12 +274,17 @@ class Model:
     def visolated(self):
         lib().orc_visolated(C.byref(self._g), C.byref(self._nodes), self.dt)
 
+    def vcable(self):
+        lib().orc_vcable(C.byref(self._g), C.byref(self._nodes), self.dt)
+
     def run(self, k0: int, nsteps: int, vmode=None):
         vm = VMODE[vmode or self.vmode]
         if vm == 1 and any(a is None for a in self.clamp):
             raise ValueError("clamp mode needs clamp arrays")
-        if vm == 2 and self.cm is None:
-            raise ValueError("isolated mode needs cm")
+        if vm in (2, 3) and self.cm is None:
+            raise ValueError("isolated and cable modes need cm")
+        if vm == 3 and (self.parent is None or self.g_axial is None or self.area is None):
+            raise ValueError("cable mode needs parent, g_axial and area")
         r = lib().orc_run(*self._args(), k0, nsteps, self.dt, vm)
         if r != 0:
             raise ValueError("orc_run rejected its arguments")

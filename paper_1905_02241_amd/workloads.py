@@ -79,7 +79,7 @@ DEFAULT_GLOBALS = {
     "newton_iters": 4,           # capump: Newton steps per implicit Euler step
 }
 
-VMODES = ("external", "clamp", "isolated")
+VMODES = ("external", "clamp", "isolated", "cable")
 SEED_BASE = 20190506
 
 
@@ -111,6 +111,8 @@ class Workload:
     clamp_freq: Optional[np.ndarray] = None
     clamp_phase: Optional[np.ndarray] = None
     globals: Dict[str, float] = dataclasses.field(default_factory=lambda: dict(DEFAULT_GLOBALS))
+    parent: Optional[np.ndarray] = None    # int32 [n_nodes], cable mode: parent node (-1 root), Hines order
+    g_axial: Optional[np.ndarray] = None   # float64 [n_nodes], cable mode: uS to the parent
 
     @property
     def n_instances(self) -> int:
@@ -198,23 +200,93 @@ def make_c3(seed: int = SEED_BASE + 2, n_nodes: int = 500_000, nsteps: int = 400
                     clamp_off=off, clamp_amp=amp, clamp_freq=freq, clamp_phase=phase, globals=_globals(2))
 
 
+def random_cell(rng: np.random.Generator, n: int, first: int, mean_section: float = 8.0,
+                ra: float = 100.0):
+    """One cell of n compartments in Hines order (parent index < own index),
+    numbered from `first`: a soma (diameter 20 um, length 20 um) and
+    unbranched sections of 1 + Poisson(mean_section - 1) compartments, each
+    attached to a uniformly chosen existing compartment.  Per section a
+    diameter U[0.5, 3] um, per compartment a length U[10, 30] um; area
+    pi d l (um2) and the axial conductance to the parent 1e2 pi (d/2)^2 /
+    (ra l) uS (ra in ohm cm, l in um), computed on the child's geometry."""
+    parent = np.empty(n, dtype=np.int32)
+    diam = np.empty(n)
+    length = np.empty(n)
+    parent[0], diam[0], length[0] = -1, 20.0, 20.0
+    k = 1
+    while k < n:
+        m = min(n - k, 1 + int(rng.poisson(mean_section - 1.0)))
+        at = int(rng.integers(0, k))
+        d = rng.uniform(0.5, 3.0)
+        for j in range(m):
+            parent[k + j] = first + (at if j == 0 else k + j - 1)
+        diam[k:k + m] = d
+        length[k:k + m] = rng.uniform(10.0, 30.0, m)
+        k += m
+    area = np.pi * diam * length
+    g = 1e2 * np.pi * (diam / 2.0) ** 2 / (ra * length)
+    g[0] = 0.0
+    return parent, area, g
+
+
 def make_c4(seed: int = SEED_BASE + 3, n_cells: int = 64, nsteps: int = 4000,
             lo: int = 200, hi: int = 20_000) -> Workload:
     """64 cells of log-uniform 200..20000 compartments, nodes contiguous per
-    cell; pas + hh everywhere, Ih and Ca-HVA on a seeded 30 %, synapses at
-    Poisson(3) per compartment; sinusoidal clamp."""
+    cell in Hines order (random branched morphologies, see random_cell);
+    pas + hh everywhere, Ih and Ca-HVA on a seeded 30 %, synapses at
+    Poisson(3) per compartment; sinusoidal clamp by default, or 'cable' mode
+    with the cells' tree coupling."""
     rng = np.random.default_rng(seed)
     sizes = np.rint(np.exp(rng.uniform(np.log(lo), np.log(hi), n_cells))).astype(np.int64)
     n_nodes = int(sizes.sum())
     off, amp, freq, phase = _sinusoid_clamp(rng, n_nodes)
-    area = rng.uniform(100.0, 1000.0, n_nodes)
     nodes = np.arange(n_nodes)
     sub = np.sort(rng.choice(n_nodes, size=int(round(0.3 * n_nodes)), replace=False))
     syn = _syn_slot(rng, n_nodes, 3.0, shuffle=False)
+    trng = np.random.default_rng(seed + 1000)
+    parts, first = [], 0
+    for sz in sizes:
+        parts.append(random_cell(trng, int(sz), first))
+        first += int(sz)
+    parent = np.concatenate([p[0] for p in parts])
+    area = np.concatenate([p[1] for p in parts])
+    g_axial = np.concatenate([p[2] for p in parts])
     w = Workload("cells64-mixed", n_nodes,
                  [_slot("pas", nodes), _slot("hh", nodes), _slot("ih", sub), _slot("cahva", sub), syn],
-                 "clamp", 0.025, nsteps, area=area,
-                 clamp_off=off, clamp_amp=amp, clamp_freq=freq, clamp_phase=phase, globals=_globals(3))
+                 "clamp", 0.025, nsteps, area=area, cm=np.ones(n_nodes),
+                 clamp_off=off, clamp_amp=amp, clamp_freq=freq, clamp_phase=phase, globals=_globals(3),
+                 parent=parent, g_axial=g_axial)
+    w.cell_sizes = sizes  # type: ignore[attr-defined]
+    return w
+
+
+def make_cells(seed: int, n_cells: int, lo: int, hi: int, kinds=("pas", "hh", "syn"), syn_per_node: float = 2.0,
+               event_rate_hz: float = 300.0, nsteps: int = 200, mean_section: float = 8.0) -> Workload:
+    """Small branched cells for cable-mode parity tests."""
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(lo, hi + 1, n_cells)
+    parts, first = [], 0
+    for sz in sizes:
+        parts.append(random_cell(rng, int(sz), first, mean_section))
+        first += int(sz)
+    n_nodes = first
+    parent = np.concatenate([p[0] for p in parts])
+    area = np.concatenate([p[1] for p in parts])
+    g_axial = np.concatenate([p[2] for p in parts])
+    nodes = np.arange(n_nodes)
+    slots = []
+    for k in kinds:
+        if k == "syn":
+            s = _syn_slot(rng, n_nodes, syn_per_node, shuffle=True)
+            s.params["weight"][:] *= 4.0
+            slots.append(s)
+        else:
+            slots.append(_slot(k, nodes))
+    g = _globals(200)
+    g["event_seed"] = 0xCAB1E + seed
+    g["event_rate_hz"] = event_rate_hz
+    w = Workload(f"cells-{seed}", n_nodes, slots, "cable", 0.025, nsteps, area=area, cm=np.ones(n_nodes),
+                 globals=g, parent=parent, g_axial=g_axial)
     w.cell_sizes = sizes  # type: ignore[attr-defined]
     return w
 
@@ -318,4 +390,20 @@ def subset(w: Workload, node_ids: np.ndarray):
     sub = Workload(w.name + "-sample", int(node_ids.shape[0]), slots, w.vmode, w.dt, w.nsteps, w.v_init,
                    pick(w.area), pick(w.cm), pick(w.clamp_off), pick(w.clamp_amp), pick(w.clamp_freq),
                    pick(w.clamp_phase), dict(w.globals))
+    if w.parent is not None:
+        # a node sample keeps its tree only if it holds whole cells; otherwise
+        # the nodes are cut loose (valid under a clamp or in isolated mode)
+        p = w.parent[node_ids]
+        inside = (p >= 0) & (remap[np.maximum(p, 0)] >= 0)
+        sub.parent = np.where(inside, remap[np.maximum(p, 0)], -1).astype(np.int32)
+        sub.g_axial = np.where(inside, w.g_axial[node_ids], 0.0)
+    return sub, keep
+
+
+def cells_subset(w: Workload, cells) -> tuple:
+    """Restrict a cell workload to whole cells (cable mode stays valid)."""
+    starts = np.concatenate([[0], np.cumsum(w.cell_sizes)])
+    nodes = np.concatenate([np.arange(starts[c], starts[c + 1]) for c in sorted(cells)])
+    sub, keep = subset(w, nodes)
+    sub.cell_sizes = np.asarray([w.cell_sizes[c] for c in sorted(cells)])  # type: ignore[attr-defined]
     return sub, keep

@@ -600,3 +600,89 @@ def test_new_kinds_vanish_at_reversal(oracle):
     M.init()
     eca = oracle.nernst_ca(5e-5, 2.0, 6.3)
     assert M.instance_current(0, 0, eca)[0] == 0.0
+
+
+# -------------------------------------------- cable mode: Hines solve (F4) --
+def _cable_matrix(M, dt):
+    """Dense matrix and right-hand side of the linearised backward Euler step,
+    assembled independently of the tree elimination."""
+    n = M.n_nodes
+    A = np.diag(1e-3 * M.cm / dt + M.d)
+    r = M.rhs.copy()
+    for i in range(n):
+        p = M.parent[i]
+        if p < 0:
+            continue
+        ki, kp = 1e2 * M.g_axial[i] / M.area[i], 1e2 * M.g_axial[i] / M.area[p]
+        A[i, i] += ki
+        A[p, p] += kp
+        A[i, p] -= ki
+        A[p, i] -= kp
+        r[i] += ki * (M.v[p] - M.v[i])
+        r[p] += kp * (M.v[i] - M.v[p])
+    return A, r
+
+
+def test_hines_solve_equals_dense_library_solve(oracle):
+    w = W.make_cells(3, n_cells=3, lo=20, hi=60, nsteps=1)
+    M = oracle.Model(w)
+    M.init()
+    rng = np.random.default_rng(5)
+    M.v[:] = rng.uniform(-80, 20, w.n_nodes)
+    M.events(0)
+    M.cur()
+    A, r = _cable_matrix(M, w.dt)
+    ref = M.v + np.linalg.solve(A, r)
+    M.vcable()
+    assert np.allclose(M.v, ref, rtol=1e-13, atol=1e-11)
+
+
+def test_cable_without_coupling_is_isolated(oracle):
+    w = W.make_cells(4, n_cells=2, lo=30, hi=40, nsteps=200)
+    w.g_axial[:] = 0.0
+    A = oracle.Model(w)
+    A.init()
+    A.run(0, 200, "cable")
+    B = oracle.Model(w)
+    B.init()
+    B.run(0, 200, "isolated")
+    assert np.array_equal(A.v, B.v)
+    assert np.array_equal(A.spikes, B.spikes)
+
+
+def test_cable_conserves_charge_without_membrane_current(oracle):
+    """With no mechanism (rhs = d = 0) the axial currents only move charge:
+    sum_n area_n cm_n dv_n = 0, and a uniform potential stays uniform."""
+    w = W.make_cells(5, n_cells=2, lo=40, hi=80, kinds=(), nsteps=1)
+    M = oracle.Model(w)
+    rng = np.random.default_rng(6)
+    M.v[:] = rng.uniform(-90, 30, w.n_nodes)
+    q0 = np.sum(w.area * M.v)
+    for _ in range(50):
+        M.rhs[:] = 0.0
+        M.d[:] = 0.0
+        M.vcable()
+    assert abs(np.sum(w.area * M.v) - q0) <= 1e-9 * np.sum(w.area)
+    M.v[:] = -42.0
+    M.rhs[:] = 0.0
+    M.d[:] = 0.0
+    M.vcable()
+    assert np.all(M.v == -42.0)
+
+
+def test_cable_spreads_current_along_the_tree(oracle):
+    """Two compartments: the closed-form 2x2 solve."""
+    w = W.Workload("two", 2, [], "cable", 0.025, 1, area=np.array([100.0, 50.0]), cm=np.array([1.0, 1.0]),
+                   parent=np.array([-1, 0], dtype=np.int32), g_axial=np.array([0.0, 0.02]))
+    M = oracle.Model(w)
+    M.v[:] = [-65.0, -20.0]
+    M.rhs[:] = [0.3, -0.1]
+    M.d[:] = [0.01, 0.002]
+    c = 1e-3 / 0.025
+    k0, k1 = 1e2 * 0.02 / 100.0, 1e2 * 0.02 / 50.0
+    a = np.array([[c + 0.01 + k0, -k0], [-k1, c + 0.002 + k1]])
+    r = np.array([0.3 + k0 * 45.0, -0.1 - k1 * 45.0])
+    det = a[0, 0] * a[1, 1] - a[0, 1] * a[1, 0]
+    dv = np.array([(r[0] * a[1, 1] - a[0, 1] * r[1]) / det, (a[0, 0] * r[1] - a[1, 0] * r[0]) / det])
+    M.vcable()
+    assert np.allclose(M.v, np.array([-65.0, -20.0]) + dv, rtol=0, atol=1e-12)
