@@ -100,8 +100,13 @@ enum { MECH_FP64 = 0, MECH_FP32_MIXED = 1 };
  *             t in ms, freq in Hz;
  *   ISOLATED  every node is an isolated compartment advanced by backward
  *             Euler, v += rhs/(1e-3 cm/dt + d), and an upward crossing of
- *             vthresh increments the node's spike count.                    */
-enum { MECH_V_EXTERNAL = 0, MECH_V_CLAMP = 1, MECH_V_ISOLATED = 2 };
+ *             vthresh increments the node's spike count;
+ *   CABLE     the nodes form trees (cells, mech_bind_cable) coupled by axial
+ *             conductances: backward Euler of the cable equation linearised
+ *             with rhs and d, (1e-3 cm/dt + d_n) dv_n + sum_j k_nj (dv_n -
+ *             dv_j) = rhs_n + sum_j k_nj (v_j - v_n), k_nj = 100 g_nj/area_n,
+ *             solved by Hines elimination; spikes as in ISOLATED.            */
+enum { MECH_V_EXTERNAL = 0, MECH_V_CLAMP = 1, MECH_V_ISOLATED = 2, MECH_V_CABLE = 3 };
 /* PLAIN: per step, one launch per mechanism type for the current update,
  *        one for the voltage, one per type for the state update, issued
  *        eagerly (the paper's per-mechanism kernel structure);
@@ -140,6 +145,21 @@ int mech_alloc(mech_ctx **out, int64_t n_nodes, const mech_type_desc *types, int
  * for MECH_V_ISOLATED (may be NULL otherwise).                             */
 int mech_bind_nodes(mech_ctx *ctx, double *v, double *rhs, double *d, const double *area,
                     const double *cm);
+
+/* Bytes of the device buffer the cell trees of MECH_V_CABLE need, from the
+ * host parent array (int32, n_nodes entries).                              */
+int mech_cable_required_bytes(int64_t n_nodes, const int32_t *parent, size_t *out_bytes);
+
+/* Bind the cell trees for MECH_V_CABLE.  parent (host, int32[n_nodes]):
+ * the parent of each node, -1 for a cell's root, with parent[n] < n (Hines
+ * order) and every cell a contiguous node range that starts at its root
+ * (MECH_ERR_INVAL otherwise).  g_axial (device, double[n_nodes], caller
+ * owned): the axial conductance in uS between node n and its parent.  The
+ * library builds per-cell elimination schedules into dev_buf (dev_bytes >=
+ * mech_cable_required_bytes, 256-byte aligned, caller owned, MECH_ERR_NOMEM
+ * if short).  Needs area and cm bound (mech_bind_nodes).                  */
+int mech_bind_cable(mech_ctx *ctx, const int32_t *parent, const double *g_axial, void *dev_buf,
+                    size_t dev_bytes);
 
 /* Bind the clamp waveform (device, double, n_nodes each) for MECH_V_CLAMP. */
 int mech_bind_clamp(mech_ctx *ctx, const double *off, const double *amp, const double *freq_hz,

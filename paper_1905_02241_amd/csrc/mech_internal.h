@@ -65,6 +65,28 @@ struct NodesDev {
     int n_nodes;
 };
 
+// Cell trees of the cable mode: per cell a contiguous node range, the
+// children of every node (CSR), the non-leaf nodes grouped by elimination
+// level and all nodes grouped by depth.
+struct CableDev {
+    const double *g_axial;     // uS to the parent
+    const int *parent;
+    const int *cell_first;     // [n_cells + 1]
+    const int *child_ptr;      // [n_nodes + 1]
+    const int *child_idx;
+    const int *elim_nodes;     // non-leaf nodes, per cell by level
+    const int *elim_ptr;       // level boundaries into elim_nodes
+    const int *cell_elim;      // [n_cells + 1] into elim_ptr
+    const int *back_nodes;     // all nodes, per cell by depth
+    const int *back_ptr;       // depth boundaries into back_nodes
+    const int *cell_back;      // [n_cells + 1] into back_ptr
+    double *D, *R;             // per-node scratch of the solve (cells too large for LDS)
+    int n_cells;
+    const int *small_cells;    // cells solved with D and R in LDS
+    const int *large_cells;    // cells solved in global scratch
+    int n_small, n_large, small_max_nodes;
+};
+
 struct FusedArgs {
     SlotDev slot[kMaxSlots];
     int n_slots;
@@ -101,6 +123,7 @@ hipError_t launch_init(bool fp32, const PlainArgs &a, hipStream_t s);
 hipError_t launch_plain_cur(bool fp32, const PlainArgs &a, hipStream_t s);
 hipError_t launch_plain_state(bool fp32, const PlainArgs &a, hipStream_t s);
 hipError_t launch_stream(int op, int unroll, void *dst, const void *src, size_t n16, int grid, hipStream_t s);
+hipError_t launch_cable(const CableDev &c, const NodesDev &nd, const GlobDev &g, hipStream_t s);
 hipError_t launch_fused(bool fp32, int phases, int vmode, const FusedArgs &a, int grid, int block,
                         size_t lds_bytes, hipStream_t s);
 

@@ -615,6 +615,90 @@ __global__ void k_visolated(NodesDev nd, GlobDev g) {
     if (n < nd.n_nodes) nd.v[n] = isolated_v(nd, g, n, nd.v[n], nd.rhs[n], nd.d[n]);
 }
 
+// ---------------------------------------------------------- cable solve --
+// Backward Euler of the cable equation on each cell's tree (Hines 1984), one
+// workgroup per cell.  Row n of the system: D_n dv_n - k_{n,p} dv_p -
+// sum_c k_{n,c} dv_c = R_n with D_n = 1e-3 cm/dt + d_n + k_{n,p} + sum_c
+// k_{n,c}, k_{n,j} = 100 g/area_n.  Elimination runs level by level from the
+// leaves: a node gathers its children's finished rows (no atomics), and a
+// barrier separates levels; back-substitution runs depth by depth from the
+// root.  In the LDS variant the cell's D and R (16 B per node) stay in LDS,
+// so each of the level steps costs a barrier and LDS traffic rather than L2
+// round trips; cells too large for LDS use the global scratch arrays.
+template <bool LDS>
+__global__ __launch_bounds__(256) void k_cable(CableDev c, NodesDev nd, GlobDev g, const int *cells) {
+    extern __shared__ double lds[];
+    const int cell = cells[blockIdx.x];
+    const int n0 = c.cell_first[cell], n1 = c.cell_first[cell + 1];
+    // node n's row sits at index n - base of Dp / Rp
+    double *Dp = LDS ? lds : c.D;
+    double *Rp = LDS ? lds + (n1 - n0) : c.R;
+    const int base = LDS ? n0 : 0;
+    for (int n = n0 + (int)threadIdx.x; n < n1; n += (int)blockDim.x) {
+        const double vn = nd.v[n];
+        double D = 1e-3 * nd.cm[n] / g.dt + nd.d[n];
+        double R = nd.rhs[n];
+        const int p = c.parent[n];
+        if (p >= 0) {
+            const double kn = 1e2 * c.g_axial[n] / nd.area[n];
+            D += kn;
+            R += kn * (nd.v[p] - vn);
+        }
+        const double an = nd.area[n];
+        for (int q = c.child_ptr[n]; q < c.child_ptr[n + 1]; ++q) {
+            const int ch = c.child_idx[q];
+            const double kp = 1e2 * c.g_axial[ch] / an;
+            D += kp;
+            R += kp * (nd.v[ch] - vn);
+        }
+        Dp[n - base] = D;
+        Rp[n - base] = R;
+    }
+    __syncthreads();
+    // leaves to root: children (lower levels) are final when a level starts
+    for (int L = c.cell_elim[cell]; L < c.cell_elim[cell + 1]; ++L) {
+        for (int q = c.elim_ptr[L] + (int)threadIdx.x; q < c.elim_ptr[L + 1]; q += (int)blockDim.x) {
+            const int n = c.elim_nodes[q];
+            const double an = nd.area[n];
+            double D = Dp[n - base], R = Rp[n - base];
+            for (int j = c.child_ptr[n + 1] - 1; j >= c.child_ptr[n]; --j) {
+                const int ch = c.child_idx[j];
+                const double ga = c.g_axial[ch];
+                const double kp = 1e2 * ga / an, kn = 1e2 * ga / nd.area[ch];
+                const double f = kp / Dp[ch - base];
+                D -= f * kn;
+                R += f * Rp[ch - base];
+            }
+            Dp[n - base] = D;
+            Rp[n - base] = R;
+        }
+        __syncthreads();
+    }
+    // root to leaves: dv overwrites R
+    for (int L = c.cell_back[cell]; L < c.cell_back[cell + 1]; ++L) {
+        for (int q = c.back_ptr[L] + (int)threadIdx.x; q < c.back_ptr[L + 1]; q += (int)blockDim.x) {
+            const int n = c.back_nodes[q];
+            const int p = c.parent[n];
+            double r = Rp[n - base];
+            if (p >= 0) r += 1e2 * c.g_axial[n] / nd.area[n] * Rp[p - base];
+            Rp[n - base] = r / Dp[n - base];
+        }
+        __syncthreads();
+    }
+    for (int n = n0 + (int)threadIdx.x; n < n1; n += (int)blockDim.x) {
+        const double v0 = nd.v[n], v1 = v0 + Rp[n - base];
+        if (v0 < g.vthresh && v1 >= g.vthresh) nd.spikes[n] += 1;
+        nd.v[n] = v1;
+    }
+}
+
+hipError_t launch_cable(const CableDev &c, const NodesDev &nd, const GlobDev &g, hipStream_t s) {
+    if (c.n_small > 0)
+        k_cable<true><<<c.n_small, 256, 16 * (size_t)c.small_max_nodes, s>>>(c, nd, g, c.small_cells);
+    if (c.n_large > 0) k_cable<false><<<c.n_large, 256, 0, s>>>(c, nd, g, c.large_cells);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------- fused path --
 // LDS per tile node: v, 100/area, rhs and d accumulators (4 doubles).
 template <class S, int KIND, int PH, bool NT>

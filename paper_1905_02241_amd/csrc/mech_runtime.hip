@@ -73,6 +73,99 @@ struct SlotHost {
     bool has_gid = false, has_ica = false;
 };
 
+// Cell trees of the cable mode, built on the host at mech_bind_cable.
+struct CableHost {
+    int n_cells = 0;
+    std::vector<int32_t> cell_first, child_ptr, child_idx, elim_nodes, elim_ptr, cell_elim, back_nodes, back_ptr,
+        cell_back, parent, small_cells, large_cells;
+    int small_max = 0;
+};
+
+// Cells of at most this many nodes keep the solve's D and R (16 B per node)
+// in LDS; 64 KiB per workgroup is available on every CDNA part.
+constexpr int kCableLdsNodes = 4096;
+
+// Validates Hines order and contiguous cells and fills the schedules.
+// Returns an empty string on success, else the reason.
+std::string build_cable(int64_t N, const int32_t *parent, CableHost &h) {
+    h = CableHost();
+    for (int64_t n = 0; n < N; ++n) {
+        const int32_t p = parent[n];
+        if (p < -1 || p >= n) return "parent[n] must be -1 or a node index below n (Hines order)";
+        if (p < 0) h.cell_first.push_back((int32_t)n);
+        else if (h.cell_first.empty() || p < h.cell_first.back())
+            return "every cell must be a contiguous node range starting at its root";
+    }
+    if (N > 0 && (h.cell_first.empty() || h.cell_first[0] != 0)) return "node 0 must be a root";
+    h.n_cells = (int)h.cell_first.size();
+    h.cell_first.push_back((int32_t)N);
+    h.parent.assign(parent, parent + N);
+    h.child_ptr.assign(N + 1, 0);
+    for (int64_t n = 0; n < N; ++n)
+        if (parent[n] >= 0) ++h.child_ptr[parent[n] + 1];
+    for (int64_t n = 0; n < N; ++n) h.child_ptr[n + 1] += h.child_ptr[n];
+    h.child_idx.assign(std::max<int32_t>(h.child_ptr[N], 1), 0);
+    {
+        std::vector<int32_t> fill(h.child_ptr.begin(), h.child_ptr.end() - 1);
+        for (int64_t n = 0; n < N; ++n)
+            if (parent[n] >= 0) h.child_idx[fill[parent[n]]++] = (int32_t)n;
+    }
+    std::vector<int32_t> lev(N, 0), dep(N, 0);
+    for (int64_t n = N - 1; n >= 0; --n)
+        if (parent[n] >= 0) lev[parent[n]] = std::max(lev[parent[n]], lev[n] + 1);
+    for (int64_t n = 0; n < N; ++n) dep[n] = parent[n] < 0 ? 0 : dep[parent[n]] + 1;
+    h.elim_ptr.push_back(0);
+    h.back_ptr.push_back(0);
+    for (int c = 0; c < h.n_cells; ++c) {
+        const int32_t a = h.cell_first[c], b = h.cell_first[c + 1];
+        int32_t maxl = 0, maxd = 0;
+        for (int32_t n = a; n < b; ++n) { maxl = std::max(maxl, lev[n]); maxd = std::max(maxd, dep[n]); }
+        h.cell_elim.push_back((int32_t)h.elim_ptr.size() - 1);
+        std::vector<std::vector<int32_t>> byl(maxl + 1), byd(maxd + 1);
+        for (int32_t n = a; n < b; ++n) { byl[lev[n]].push_back(n); byd[dep[n]].push_back(n); }
+        for (int32_t L = 1; L <= maxl; ++L) {
+            h.elim_nodes.insert(h.elim_nodes.end(), byl[L].begin(), byl[L].end());
+            h.elim_ptr.push_back((int32_t)h.elim_nodes.size());
+        }
+        h.cell_back.push_back((int32_t)h.back_ptr.size() - 1);
+        for (int32_t d = 0; d <= maxd; ++d) {
+            h.back_nodes.insert(h.back_nodes.end(), byd[d].begin(), byd[d].end());
+            h.back_ptr.push_back((int32_t)h.back_nodes.size());
+        }
+    }
+    h.cell_elim.push_back((int32_t)h.elim_ptr.size() - 1);
+    h.cell_back.push_back((int32_t)h.back_ptr.size() - 1);
+    if (h.elim_nodes.empty()) h.elim_nodes.push_back(0);
+    if (h.back_nodes.empty()) h.back_nodes.push_back(0);
+    for (int c = 0; c < h.n_cells; ++c) {
+        const int sz = h.cell_first[c + 1] - h.cell_first[c];
+        if (sz <= kCableLdsNodes) {
+            h.small_cells.push_back(c);
+            h.small_max = std::max(h.small_max, sz);
+        } else {
+            h.large_cells.push_back(c);
+        }
+    }
+    return "";
+}
+
+// Device layout of a CableHost (256-byte aligned arrays), then D and R.
+size_t cable_layout(const CableHost &h, int64_t N, size_t *offs) {
+    const std::vector<int32_t> *arr[] = {&h.cell_first, &h.child_ptr, &h.child_idx, &h.elim_nodes,
+                                         &h.elim_ptr, &h.cell_elim, &h.back_nodes, &h.back_ptr,
+                                         &h.cell_back, &h.parent, &h.small_cells, &h.large_cells};
+    size_t off = 0;
+    for (int j = 0; j < 12; ++j) {
+        offs[j] = off;
+        off = (off + 4 * std::max<size_t>(arr[j]->size(), 1) + kAlign - 1) / kAlign * kAlign;
+    }
+    offs[12] = off;
+    off = (off + 8 * (size_t)std::max<int64_t>(N, 1) + kAlign - 1) / kAlign * kAlign;
+    offs[13] = off;
+    off = (off + 8 * (size_t)std::max<int64_t>(N, 1) + kAlign - 1) / kAlign * kAlign;
+    return off;
+}
+
 struct Layout {
     size_t total = 0;
     size_t inst_end = 0;           // end of the per-instance region
@@ -126,7 +219,8 @@ struct mech_ctx {
     Layout L;
     Globals gl;
     NodesDev nd{};
-    bool nodes_bound = false, clamp_bound = false, has_syn = false;
+    CableDev cable{};
+    bool nodes_bound = false, clamp_bound = false, has_syn = false, cable_bound = false;
     // fused-path launch shape and tile table
     int block = 256, tile_budget = 2048, tile_nodes = 1024, blocks_per_cu = 0, launch_flags = MECH_LAUNCH_XCD_ORDER;
     int64_t n_tiles = 0, max_tile_nodes = 0;
@@ -284,9 +378,11 @@ int check_ready(mech_ctx *c, int vmode) {
     if (!c->nodes_bound) return fail(c, MECH_ERR_STATE, "node vectors not bound (mech_bind_nodes)");
     if (vmode == MECH_V_CLAMP && !c->clamp_bound)
         return fail(c, MECH_ERR_STATE, "clamp waveform not bound (mech_bind_clamp)");
-    if (vmode == MECH_V_ISOLATED && !c->nd.cm)
-        return fail(c, MECH_ERR_STATE, "isolated mode needs cm (mech_bind_nodes)");
-    if (vmode < MECH_V_EXTERNAL || vmode > MECH_V_ISOLATED) return fail(c, MECH_ERR_INVAL, "bad vmode %d", vmode);
+    if ((vmode == MECH_V_ISOLATED || vmode == MECH_V_CABLE) && !c->nd.cm)
+        return fail(c, MECH_ERR_STATE, "isolated and cable modes need cm (mech_bind_nodes)");
+    if (vmode == MECH_V_CABLE && (!c->cable_bound || !c->nd.area))
+        return fail(c, MECH_ERR_STATE, "cable mode needs mech_bind_cable and area");
+    if (vmode < MECH_V_EXTERNAL || vmode > MECH_V_CABLE) return fail(c, MECH_ERR_INVAL, "bad vmode %d", vmode);
     return MECH_OK;
 }
 
@@ -374,11 +470,15 @@ void fused_shape(const mech_ctx *c, int *grid, size_t *lds) {
     *lds = 4 * sizeof(double) * (size_t)std::max<int64_t>(c->max_tile_nodes, 1);
 }
 
+// One fused pass; in cable mode the pass only writes rhs/d and the tree solve
+// follows it on the same stream to provide v_{k+1}.
 int launch_fused_phase(mech_ctx *c, int phases, int vmode, const GlobDev &g, int kofs, hipStream_t s) {
     int grid;
     size_t lds;
     fused_shape(c, &grid, &lds);
-    HIPCHK(c, launch_fused(c->fp32, phases, vmode, fused_args(c, g, kofs), grid, c->block, lds, s));
+    const int vm = vmode == MECH_V_CABLE ? MECH_V_EXTERNAL : vmode;
+    HIPCHK(c, launch_fused(c->fp32, phases, vm, fused_args(c, g, kofs), grid, c->block, lds, s));
+    if (vmode == MECH_V_CABLE && (phases & kDoCur)) HIPCHK(c, launch_cable(c->cable, c->nd, g, s));
     return MECH_OK;
 }
 
@@ -421,6 +521,7 @@ int step_plain(mech_ctx *c, int64_t nsteps, int64_t k0, double dt, int vmode) {
         if (rc) return rc;
         if (vmode == MECH_V_CLAMP) HIPCHK(c, launch_vclamp(c->nd, (double)(k + 1) * dt, c->stream));
         if (vmode == MECH_V_ISOLATED) HIPCHK(c, launch_visolated(c->nd, g, c->stream));
+        if (vmode == MECH_V_CABLE) HIPCHK(c, launch_cable(c->cable, c->nd, g, c->stream));
         rc = launch_plain_phase(c, false, k, g, 0);
         if (rc) return rc;
     }
@@ -617,6 +718,60 @@ int mech_bind_nodes(mech_ctx *c, double *v, double *rhs, double *d, const double
     c->nd.area = area;
     c->nd.cm = cm;
     c->nodes_bound = true;
+    clear_graphs(c);
+    return MECH_OK;
+}
+
+int mech_cable_required_bytes(int64_t n_nodes, const int32_t *parent, size_t *out) {
+    if (!out || n_nodes < 0 || (n_nodes > 0 && !parent)) return fail(nullptr, MECH_ERR_INVAL, "null argument");
+    CableHost h;
+    std::string why = build_cable(n_nodes, parent, h);
+    if (!why.empty()) return fail(nullptr, MECH_ERR_INVAL, "%s", why.c_str());
+    size_t offs[14];
+    *out = cable_layout(h, n_nodes, offs);
+    return MECH_OK;
+}
+
+int mech_bind_cable(mech_ctx *c, const int32_t *parent, const double *g_axial, void *dev_buf, size_t dev_bytes) {
+    if (!c) return fail(nullptr, MECH_ERR_INVAL, "null ctx");
+    if (c->n_nodes > 0 && (!parent || !g_axial || !dev_buf))
+        return fail(c, MECH_ERR_INVAL, "parent, g_axial and dev_buf are required");
+    if (((uintptr_t)dev_buf % kAlign) != 0) return fail(c, MECH_ERR_INVAL, "dev_buf must be %d-byte aligned", kAlign);
+    CableHost h;
+    std::string why = build_cable(c->n_nodes, parent, h);
+    if (!why.empty()) return fail(c, MECH_ERR_INVAL, "%s", why.c_str());
+    size_t offs[14];
+    const size_t need = cable_layout(h, c->n_nodes, offs);
+    if (dev_bytes < need) return fail(c, MECH_ERR_NOMEM, "cable buffer has %zu bytes, %zu required", dev_bytes, need);
+    char *b = (char *)dev_buf;
+    const std::vector<int32_t> *arr[] = {&h.cell_first, &h.child_ptr, &h.child_idx, &h.elim_nodes,
+                                         &h.elim_ptr, &h.cell_elim, &h.back_nodes, &h.back_ptr,
+                                         &h.cell_back, &h.parent, &h.small_cells, &h.large_cells};
+    for (int j = 0; j < 12; ++j)
+        if (!arr[j]->empty())
+            HIPCHK(c, hipMemcpy(b + offs[j], arr[j]->data(), 4 * arr[j]->size(), hipMemcpyHostToDevice));
+    CableDev d{};
+    d.g_axial = g_axial;
+    d.cell_first = (const int *)(b + offs[0]);
+    d.child_ptr = (const int *)(b + offs[1]);
+    d.child_idx = (const int *)(b + offs[2]);
+    d.elim_nodes = (const int *)(b + offs[3]);
+    d.elim_ptr = (const int *)(b + offs[4]);
+    d.cell_elim = (const int *)(b + offs[5]);
+    d.back_nodes = (const int *)(b + offs[6]);
+    d.back_ptr = (const int *)(b + offs[7]);
+    d.cell_back = (const int *)(b + offs[8]);
+    d.parent = (const int *)(b + offs[9]);
+    d.small_cells = (const int *)(b + offs[10]);
+    d.large_cells = (const int *)(b + offs[11]);
+    d.D = (double *)(b + offs[12]);
+    d.R = (double *)(b + offs[13]);
+    d.n_cells = h.n_cells;
+    d.n_small = (int)h.small_cells.size();
+    d.n_large = (int)h.large_cells.size();
+    d.small_max_nodes = h.small_max;
+    c->cable = d;
+    c->cable_bound = true;
     clear_graphs(c);
     return MECH_OK;
 }

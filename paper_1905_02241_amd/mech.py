@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(PKG, "libmech.so")
 OK, ERR_INVAL, ERR_RANGE, ERR_NOMEM, ERR_STATE, ERR_HIP, ERR_NONFINITE = 0, -1, -2, -3, -4, -5, -6
 KIND = {"pas": 0, "hh": 1, "ih": 2, "cahva": 3, "syn": 4, "kmarkov": 5, "capump": 6}
 PREC = {"fp64": 0, "fp32": 1}
-VMODE = {"external": 0, "clamp": 1, "isolated": 2}
+VMODE = {"external": 0, "clamp": 1, "isolated": 2, "cable": 3}
 PATH = {"plain": 0, "batched": 1}
 GLOBAL_NAMES = ("celsius", "ena", "ek", "eh", "cao", "cai0", "tau_ca", "ca_gamma", "ca_depth", "e_syn",
                 "mg", "tau_r_ampa", "tau_d_ampa", "tau_r_nmda", "tau_d_nmda", "event_rate_hz", "event_seed",
@@ -28,7 +28,8 @@ GLOBAL_NAMES = ("celsius", "ena", "ek", "eh", "cao", "cai0", "tau_ca", "ca_gamma
                 "newton_iters")
 
 # Exported symbols of include/mech.h (checked by the CPU tests).
-SYMBOLS = ("mech_required_bytes", "mech_alloc", "mech_bind_nodes", "mech_bind_clamp", "mech_set_params",
+SYMBOLS = ("mech_required_bytes", "mech_alloc", "mech_bind_nodes", "mech_bind_clamp", "mech_cable_required_bytes",
+           "mech_bind_cable", "mech_set_params",
            "mech_set_global", "mech_init", "mech_cur", "mech_state", "mech_step", "mech_set_launch",
            "mech_get_launch", "mech_autotune", "mech_get_state", "mech_set_state", "mech_spike_counts",
            "mech_sync", "mech_info", "mech_probe_stream", "mech_last_error", "mech_strerror", "mech_free")
@@ -68,6 +69,8 @@ def load_library(path: str = LIB_PATH):
         "mech_alloc": [C.POINTER(vp), C.c_int64, C.POINTER(TypeDesc), C.c_int, C.c_int, vp, C.c_size_t, vp],
         "mech_bind_nodes": [vp, vp, vp, vp, vp, vp],
         "mech_bind_clamp": [vp, vp, vp, vp, vp],
+        "mech_cable_required_bytes": [C.c_int64, ip, C.POINTER(C.c_size_t)],
+        "mech_bind_cable": [vp, ip, vp, vp, C.c_size_t],
         "mech_set_params": [vp, C.c_int, C.c_char_p, dp, C.c_int64],
         "mech_set_global": [vp, C.c_char_p, C.c_double],
         "mech_init": [vp],
@@ -176,6 +179,18 @@ class Mechanisms:
     def set_clamp(self, off, amp, freq, phase):
         for t, a in zip(self.clamp, (off, amp, freq, phase)):
             t.copy_(self.torch.as_tensor(np.asarray(a, dtype=np.float64)).to(self.device))
+
+    def bind_cable(self, parent, g_axial):
+        """Cell trees for the cable mode: parent (-1 at roots, Hines order,
+        contiguous cells) and axial conductances in uS."""
+        par = np.ascontiguousarray(parent, dtype=np.int32)
+        nbytes = C.c_size_t(0)
+        ip = C.POINTER(C.c_int32)
+        self._check(self.L.mech_cable_required_bytes(self.n_nodes, par.ctypes.data_as(ip), C.byref(nbytes)), None)
+        self.cable_buf = self.torch.empty(max(int(nbytes.value), 256), dtype=self.torch.uint8, device=self.device)
+        self.g_axial = self.torch.as_tensor(np.asarray(g_axial, dtype=np.float64)).to(self.device)
+        self._check(self.L.mech_bind_cable(self.ctx, par.ctypes.data_as(ip), _ptr(self.g_axial),
+                                           self.cable_buf.data_ptr(), int(nbytes.value)))
 
     def set_params(self, slot: int, name: str, values):
         a = np.ascontiguousarray(np.atleast_1d(np.asarray(values, dtype=np.float64)))
@@ -305,6 +320,8 @@ def from_workload(w, prec: str = "fp64", init: bool = True) -> Mechanisms:
         m.set_node_array("cm", w.cm)
     if w.clamp_off is not None:
         m.set_clamp(w.clamp_off, w.clamp_amp, w.clamp_freq, w.clamp_phase)
+    if getattr(w, "parent", None) is not None:
+        m.bind_cable(w.parent, w.g_axial)
     m.v.fill_(float(w.v_init))
     if init:
         m.init()

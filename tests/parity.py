@@ -98,7 +98,7 @@ def compare_nodes(got, M, prec, nodes=None, label="", check_v=True):
         assert r <= 1.0, f"{label} {key} parity ratio {r}"
     if check_v:
         g = got["v"] if nodes is None else got["v"][nodes]
-        if M.w.vmode == "isolated":
+        if M.w.vmode in ("isolated", "cable"):
             # v integrates rhs/(1e-3 cm/dt + d): the rhs bar (1e-11 S_n, S_n up
             # to a few mA/cm2 at a spike) over c + d >= 0.04 S/cm2 injects up
             # to ~1e-9 mV per step, which the membrane's leak contracts

@@ -380,3 +380,64 @@ def test_implicit_kinds_isolated_fp64(path):
     assert np.array_equal(got["spikes"], M.spikes)
     compare_states(got, M, "fp64", label="implicit isolated")
     compare_nodes(got, M, "fp64", label="implicit isolated")
+
+
+# ------------------------------------------------ cable mode: Hines (F4) --
+@pytest.mark.parametrize("path", PATHS)
+def test_cable_cells_fp64(path):
+    """Branched cells coupled by axial conductances, solved by the tree
+    elimination between the current and the state update."""
+    w = W.make_cells(51, n_cells=6, lo=40, hi=400, kinds=("pas", "hh", "cahva", "syn"), nsteps=400)
+    got, m = run_gpu(w, 400, path, "fp64")
+    M = run_oracle(w, 400)
+    log(f"cable {path}: spikes gpu {got['spikes'].sum()} oracle {M.spikes.sum()}")
+    assert M.spikes.sum() > 0
+    assert np.array_equal(got["spikes"], M.spikes)
+    compare_states(got, M, "fp64", label="cable")
+    compare_nodes(got, M, "fp64", label="cable")
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_cable_cells_fp32_reports(path):
+    w = W.make_cells(52, n_cells=6, lo=40, hi=400, kinds=("pas", "hh", "syn"), nsteps=400)
+    got, m = run_gpu(w, 400, path, "fp32")
+    M = run_oracle(w, 400)
+    match = np.mean(got["spikes"] == M.spikes)
+    log(f"cable fp32 {path}: spike match {match:.3f}, max |dv| {np.max(np.abs(got['v'] - M.v)):.3g} mV")
+    assert match >= 0.9
+
+
+def test_cable_single_nodes_equal_isolated():
+    """Cells of one compartment: the tree solve reduces to the isolated
+    update exactly (same rounding path for D and R)."""
+    w = W.make_tiny(53, kinds=("pas", "hh", "syn"), n_nodes=300, vmode="isolated", nsteps=200,
+                    event_rate_hz=300.0, shuffle=False)
+    w.slots[-1].params["weight"][:] *= 6.0
+    a, _ = run_gpu(w, 200, "batched", "fp64")
+    w.vmode = "cable"
+    w.parent = np.full(w.n_nodes, -1, dtype=np.int32)
+    w.g_axial = np.zeros(w.n_nodes)
+    b, _ = run_gpu(w, 200, "batched", "fp64")
+    assert np.array_equal(a["spikes"], b["spikes"])
+    assert np.allclose(a["v"], b["v"], rtol=1e-13, atol=1e-12)
+
+
+def test_config4_cable_whole_cell_sample():
+    """C4's 64 branched cells in cable mode at full size; the oracle runs
+    three whole cells (a cell is the unit the tree solve couples)."""
+    w = W.make_config(4)
+    w.vmode = "cable"
+    nsteps = 400
+    with Timer() as tg:
+        got, m = run_gpu(w, nsteps, "batched", "fp64")
+    cells = [0, 17, 40]
+    sub, keep = W.cells_subset(w, cells)
+    with Timer() as to:
+        M = run_oracle(sub, nsteps)
+    starts = np.concatenate([[0], np.cumsum(w.cell_sizes)])
+    nodes = np.concatenate([np.arange(starts[c], starts[c + 1]) for c in cells])
+    ws = compare_states(got, M, "fp64", keep=keep, label="c4 cable")
+    wn = compare_nodes({k: got[k] for k in ("v", "rhs", "d")}, M, "fp64", nodes=nodes, label="c4 cable")
+    assert np.array_equal(got["spikes"][nodes], M.spikes)
+    log(f"c4 cable: gpu {tg.dt:.1f}s oracle {to.dt:.1f}s worst state {max(v[0] for v in ws.values()):.3g} "
+        f"nodes {wn} spikes {int(M.spikes.sum())}")
