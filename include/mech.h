@@ -157,7 +157,10 @@ int mech_cable_required_bytes(int64_t n_nodes, const int32_t *parent, size_t *ou
  * owned): the axial conductance in uS between node n and its parent.  The
  * library builds per-cell elimination schedules into dev_buf (dev_bytes >=
  * mech_cable_required_bytes, 256-byte aligned, caller owned, MECH_ERR_NOMEM
- * if short).  Needs area and cm bound (mech_bind_nodes).                  */
+ * if short) and computes the coupling coefficients 100 g/area from the
+ * bound area and g_axial, so area (mech_bind_nodes, MECH_ERR_STATE if not
+ * bound) and g_axial must hold their values at this call; bind again after
+ * changing either.  cm is read every step.                                 */
 int mech_bind_cable(mech_ctx *ctx, const int32_t *parent, const double *g_axial, void *dev_buf,
                     size_t dev_bytes);
 

@@ -74,17 +74,17 @@ struct CableDev {
     const int *cell_first;     // [n_cells + 1]
     const int *child_ptr;      // [n_nodes + 1]
     const int *child_idx;
-    const int *elim_nodes;     // non-leaf nodes, per cell by level
-    const int *elim_ptr;       // level boundaries into elim_nodes
+    const int *elim_n;         // child n of every tree edge, per cell by n's elimination level
+    const int *elim_p;         // its parent
+    const int *elim_ptr;       // level boundaries into elim_n / elim_p
     const int *cell_elim;      // [n_cells + 1] into elim_ptr
-    const int *back_nodes;     // all nodes, per cell by depth
-    const int *back_ptr;       // depth boundaries into back_nodes
-    const int *cell_back;      // [n_cells + 1] into back_ptr
+    double *ekn, *ekp;         // per edge record: 100 g/area_n, 100 g/area_p
+    double *kn, *kp;           // per node: 100 g/area_n, 100 g/area_parent (0 at a root)
     double *D, *R;             // per-node scratch of the solve (cells too large for LDS)
     int n_cells;
     const int *small_cells;    // cells solved with D and R in LDS
     const int *large_cells;    // cells solved in global scratch
-    int n_small, n_large, small_max_nodes;
+    int n_small, n_large, small_max_nodes, max_levels;
 };
 
 struct FusedArgs {
@@ -124,6 +124,8 @@ hipError_t launch_plain_cur(bool fp32, const PlainArgs &a, hipStream_t s);
 hipError_t launch_plain_state(bool fp32, const PlainArgs &a, hipStream_t s);
 hipError_t launch_stream(int op, int unroll, void *dst, const void *src, size_t n16, int grid, hipStream_t s);
 hipError_t launch_cable(const CableDev &c, const NodesDev &nd, const GlobDev &g, hipStream_t s);
+hipError_t cable_allow_lds(size_t bytes);
+hipError_t launch_cable_coeffs(const CableDev &c, const double *area, int n_nodes, int n_edges, hipStream_t s);
 hipError_t launch_fused(bool fp32, int phases, int vmode, const FusedArgs &a, int grid, int block,
                         size_t lds_bytes, hipStream_t s);
 

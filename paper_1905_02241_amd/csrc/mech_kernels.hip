@@ -619,74 +619,149 @@ __global__ void k_visolated(NodesDev nd, GlobDev g) {
 // Backward Euler of the cable equation on each cell's tree (Hines 1984), one
 // workgroup per cell.  Row n of the system: D_n dv_n - k_{n,p} dv_p -
 // sum_c k_{n,c} dv_c = R_n with D_n = 1e-3 cm/dt + d_n + k_{n,p} + sum_c
-// k_{n,c}, k_{n,j} = 100 g/area_n.  Elimination runs level by level from the
-// leaves: a node gathers its children's finished rows (no atomics), and a
-// barrier separates levels; back-substitution runs depth by depth from the
-// root.  In the LDS variant the cell's D and R (16 B per node) stay in LDS,
-// so each of the level steps costs a barrier and LDS traffic rather than L2
-// round trips; cells too large for LDS use the global scratch arrays.
+// k_{n,c}, k_{n,j} = 100 g/area_n.
+//
+// Elimination runs level by level from the leaves (a node's level is one more
+// than its highest child's): every edge child -> parent of the level folds
+// the finished child row into its parent, D_p -= k_{p,n} k_{n,p}/D_n and
+// R_p += k_{p,n} R_n/D_n, by atomic adds (several children may share a
+// parent).  Back-substitution then walks the same levels downwards from the
+// root: dv_n = (R_n + k_{n,p} dv_p)/D_n.  Each level is one barrier; the edge
+// records of the next level are loaded before it, and the coupling
+// coefficients are precomputed per node and per record at mech_bind_cable,
+// so a level waits on no dependent global load.  D and R live in LDS (16 B per node) for cells that
+// fit, else in global scratch accessed at device scope.
+template <bool LDS> __device__ __forceinline__ double ldc(const double *p) {
+    if constexpr (LDS) return *p;
+    else return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <bool LDS> __device__ __forceinline__ void stc(double *p, double v) {
+    if constexpr (LDS) *p = v;
+    else __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <bool LDS> __device__ __forceinline__ void addc(double *p, double v) {
+    if constexpr (LDS) atomicAdd(p, v);
+    else __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+constexpr int kCableLevelsLds = 1024;   // level boundaries staged in LDS
+
+// Workgroup barrier for phases that share data only through LDS: it waits
+// for LDS traffic alone, so global loads issued before it (the next level's
+// records) stay in flight across it.  The global-scratch variant needs the
+// full barrier, whose fence also drains global memory operations.
+template <bool LDS> __device__ __forceinline__ void level_barrier() {
+    if constexpr (LDS) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    } else {
+        __syncthreads();
+    }
+}
+
 template <bool LDS>
-__global__ __launch_bounds__(256) void k_cable(CableDev c, NodesDev nd, GlobDev g, const int *cells) {
+__global__ __launch_bounds__(512) void k_cable(CableDev c, NodesDev nd, GlobDev g, const int *cells) {
     extern __shared__ double lds[];
+    __shared__ int lvl[kCableLevelsLds + 1];
+    const int tid = (int)threadIdx.x, B = (int)blockDim.x;
     const int cell = cells[blockIdx.x];
     const int n0 = c.cell_first[cell], n1 = c.cell_first[cell + 1];
-    // node n's row sits at index n - base of Dp / Rp
-    double *Dp = LDS ? lds : c.D;
-    double *Rp = LDS ? lds + (n1 - n0) : c.R;
+    // node n's row sits at index n - base of D / R
+    double *D = LDS ? lds : c.D;
+    double *R = LDS ? lds + (n1 - n0) : c.R;
     const int base = LDS ? n0 : 0;
-    for (int n = n0 + (int)threadIdx.x; n < n1; n += (int)blockDim.x) {
-        const double vn = nd.v[n];
-        double D = 1e-3 * nd.cm[n] / g.dt + nd.d[n];
-        double R = nd.rhs[n];
-        const int p = c.parent[n];
-        if (p >= 0) {
-            const double kn = 1e2 * c.g_axial[n] / nd.area[n];
-            D += kn;
-            R += kn * (nd.v[p] - vn);
-        }
-        const double an = nd.area[n];
-        for (int q = c.child_ptr[n]; q < c.child_ptr[n + 1]; ++q) {
-            const int ch = c.child_idx[q];
-            const double kp = 1e2 * c.g_axial[ch] / an;
-            D += kp;
-            R += kp * (nd.v[ch] - vn);
-        }
-        Dp[n - base] = D;
-        Rp[n - base] = R;
+
+    // rows of the system: every node adds its own terms and its parent's
+    // (the coupling coefficients are precomputed per node)
+    for (int n = n0 + tid; n < n1; n += B) {
+        stc<LDS>(D + (n - base), 0.0);
+        stc<LDS>(R + (n - base), 0.0);
     }
     __syncthreads();
-    // leaves to root: children (lower levels) are final when a level starts
-    for (int L = c.cell_elim[cell]; L < c.cell_elim[cell + 1]; ++L) {
-        for (int q = c.elim_ptr[L] + (int)threadIdx.x; q < c.elim_ptr[L + 1]; q += (int)blockDim.x) {
-            const int n = c.elim_nodes[q];
-            const double an = nd.area[n];
-            double D = Dp[n - base], R = Rp[n - base];
-            for (int j = c.child_ptr[n + 1] - 1; j >= c.child_ptr[n]; --j) {
-                const int ch = c.child_idx[j];
-                const double ga = c.g_axial[ch];
-                const double kp = 1e2 * ga / an, kn = 1e2 * ga / nd.area[ch];
-                const double f = kp / Dp[ch - base];
-                D -= f * kn;
-                R += f * Rp[ch - base];
+    for (int n = n0 + tid; n < n1; n += B) {
+        const double vn = nd.v[n];
+        double Dn = 1e-3 * nd.cm[n] / g.dt + nd.d[n];
+        double Rn = nd.rhs[n];
+        const int p = c.parent[n];
+        if (p >= 0) {
+            const double kn = c.kn[n], kp = c.kp[n], dv = nd.v[p] - vn;
+            Dn += kn;
+            Rn += kn * dv;
+            addc<LDS>(D + (p - base), kp);
+            addc<LDS>(R + (p - base), -kp * dv);
+        }
+        addc<LDS>(D + (n - base), Dn);
+        addc<LDS>(R + (n - base), Rn);
+    }
+    const int L0 = c.cell_elim[cell], L1 = c.cell_elim[cell + 1];
+    const int nlev = L1 - L0;
+    const bool lv_lds = nlev < kCableLevelsLds;
+    if (lv_lds)
+        for (int j = tid; j <= nlev; j += B) lvl[j] = c.elim_ptr[L0 + j];
+    __syncthreads();
+
+    // leaves to root, one level per barrier, next level's records prefetched
+    auto lv = [&](int j) { return lv_lds ? lvl[j] : c.elim_ptr[L0 + j]; };
+    int q = nlev > 0 ? lv(0) + tid : 0;
+    bool has = nlev > 0 && q < lv(1);
+    int rn = has ? c.elim_n[q] : 0, rp = has ? c.elim_p[q] : 0;
+    double rkn = has ? c.ekn[q] : 0.0, rkp = has ? c.ekp[q] : 0.0;
+    for (int j = 0; j < nlev; ++j) {
+        const int qend = lv(j + 1);
+        while (has) {
+            const double Dn = ldc<LDS>(D + (rn - base));
+            const double f = rkp / Dn;
+            addc<LDS>(D + (rp - base), -f * rkn);
+            addc<LDS>(R + (rp - base), f * ldc<LDS>(R + (rn - base)));
+            q += B;
+            has = q < qend;
+            if (has) {
+                rn = c.elim_n[q];
+                rp = c.elim_p[q];
+                rkn = c.ekn[q];
+                rkp = c.ekp[q];
             }
-            Dp[n - base] = D;
-            Rp[n - base] = R;
         }
-        __syncthreads();
-    }
-    // root to leaves: dv overwrites R
-    for (int L = c.cell_back[cell]; L < c.cell_back[cell + 1]; ++L) {
-        for (int q = c.back_ptr[L] + (int)threadIdx.x; q < c.back_ptr[L + 1]; q += (int)blockDim.x) {
-            const int n = c.back_nodes[q];
-            const int p = c.parent[n];
-            double r = Rp[n - base];
-            if (p >= 0) r += 1e2 * c.g_axial[n] / nd.area[n] * Rp[p - base];
-            Rp[n - base] = r / Dp[n - base];
+        if (j + 1 < nlev) {
+            q = qend + tid;
+            has = q < lv(j + 2);
+            if (has) {
+                rn = c.elim_n[q];
+                rp = c.elim_p[q];
+                rkn = c.ekn[q];
+                rkp = c.ekp[q];
+            }
         }
-        __syncthreads();
+        level_barrier<LDS>();
     }
-    for (int n = n0 + (int)threadIdx.x; n < n1; n += (int)blockDim.x) {
-        const double v0 = nd.v[n], v1 = v0 + Rp[n - base];
+
+    // root to leaves: dv overwrites R.  The elimination records in reverse
+    // level order visit every parent before its children (a parent's level is
+    // higher), so they serve the back-substitution too; the root goes first.
+    if (tid == 0) stc<LDS>(R + (n0 - base), ldc<LDS>(R + (n0 - base)) / ldc<LDS>(D + (n0 - base)));
+    level_barrier<LDS>();
+    q = nlev > 0 ? lv(nlev - 1) + tid : 0;
+    has = nlev > 0 && q < lv(nlev);
+    if (has) { rn = c.elim_n[q]; rp = c.elim_p[q]; rkn = c.ekn[q]; }
+    for (int j = nlev - 1; j >= 0; --j) {
+        const int qend = lv(j + 1);
+        while (has) {
+            const double r = ldc<LDS>(R + (rn - base)) + rkn * ldc<LDS>(R + (rp - base));
+            stc<LDS>(R + (rn - base), r / ldc<LDS>(D + (rn - base)));
+            q += B;
+            has = q < qend;
+            if (has) { rn = c.elim_n[q]; rp = c.elim_p[q]; rkn = c.ekn[q]; }
+        }
+        if (j > 0) {
+            q = lv(j - 1) + tid;
+            has = q < lv(j);
+            if (has) { rn = c.elim_n[q]; rp = c.elim_p[q]; rkn = c.ekn[q]; }
+        }
+        level_barrier<LDS>();
+    }
+    for (int n = n0 + tid; n < n1; n += B) {
+        const double v0 = nd.v[n], v1 = v0 + ldc<LDS>(R + (n - base));
         if (v0 < g.vthresh && v1 >= g.vthresh) nd.spikes[n] += 1;
         nd.v[n] = v1;
     }
@@ -694,9 +769,37 @@ __global__ __launch_bounds__(256) void k_cable(CableDev c, NodesDev nd, GlobDev 
 
 hipError_t launch_cable(const CableDev &c, const NodesDev &nd, const GlobDev &g, hipStream_t s) {
     if (c.n_small > 0)
-        k_cable<true><<<c.n_small, 256, 16 * (size_t)c.small_max_nodes, s>>>(c, nd, g, c.small_cells);
-    if (c.n_large > 0) k_cable<false><<<c.n_large, 256, 0, s>>>(c, nd, g, c.large_cells);
+        k_cable<true><<<c.n_small, 512, 16 * (size_t)c.small_max_nodes, s>>>(c, nd, g, c.small_cells);
+    if (c.n_large > 0) k_cable<false><<<c.n_large, 512, 0, s>>>(c, nd, g, c.large_cells);
     return hipGetLastError();
+}
+
+// Coupling coefficients of the tree from the bound area and g_axial: per node
+// (towards its parent, and the parent's towards it) and per edge record.
+__global__ void k_cable_coeffs(CableDev c, const double *area, int n_nodes, int n_edges) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_nodes) {
+        const int p = c.parent[i];
+        const double ga = c.g_axial[i];
+        c.kn[i] = p >= 0 ? 1e2 * ga / area[i] : 0.0;
+        c.kp[i] = p >= 0 ? 1e2 * ga / area[p] : 0.0;
+    }
+    if (i < n_edges) {
+        const int n = c.elim_n[i], p = c.elim_p[i];
+        const double ga = c.g_axial[n];
+        c.ekn[i] = 1e2 * ga / area[n];
+        c.ekp[i] = 1e2 * ga / area[p];
+    }
+}
+
+hipError_t launch_cable_coeffs(const CableDev &c, const double *area, int n_nodes, int n_edges, hipStream_t s) {
+    const int n = n_nodes > n_edges ? n_nodes : n_edges;
+    if (n > 0) k_cable_coeffs<<<(n + 255) / 256, 256, 0, s>>>(c, area, n_nodes, n_edges);
+    return hipGetLastError();
+}
+
+hipError_t cable_allow_lds(size_t bytes) {
+    return hipFuncSetAttribute((const void *)k_cable<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 // ---------------------------------------------------------- fused path --

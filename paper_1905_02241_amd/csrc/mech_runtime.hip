@@ -76,18 +76,16 @@ struct SlotHost {
 // Cell trees of the cable mode, built on the host at mech_bind_cable.
 struct CableHost {
     int n_cells = 0;
-    std::vector<int32_t> cell_first, child_ptr, child_idx, elim_nodes, elim_ptr, cell_elim, back_nodes, back_ptr,
-        cell_back, parent, small_cells, large_cells;
-    int small_max = 0;
+    std::vector<int32_t> cell_first, child_ptr, child_idx, elim_n, elim_p, elim_ptr, cell_elim, parent,
+        small_cells, large_cells;
+    int small_max = 0, max_levels = 0;
 };
 
-// Cells of at most this many nodes keep the solve's D and R (16 B per node)
-// in LDS; 64 KiB per workgroup is available on every CDNA part.
-constexpr int kCableLdsNodes = 4096;
-
-// Validates Hines order and contiguous cells and fills the schedules.
-// Returns an empty string on success, else the reason.
-std::string build_cable(int64_t N, const int32_t *parent, CableHost &h) {
+// Validates Hines order and contiguous cells and fills the schedules: edge
+// records (child, parent) per cell by the child's elimination level, and the
+// split into cells whose D and R fit in LDS (lds_nodes, 16 B per node) and
+// the rest.  Returns "" on success.
+std::string build_cable(int64_t N, const int32_t *parent, int lds_nodes, CableHost &h) {
     h = CableHost();
     for (int64_t n = 0; n < N; ++n) {
         const int32_t p = parent[n];
@@ -110,60 +108,69 @@ std::string build_cable(int64_t N, const int32_t *parent, CableHost &h) {
         for (int64_t n = 0; n < N; ++n)
             if (parent[n] >= 0) h.child_idx[fill[parent[n]]++] = (int32_t)n;
     }
-    std::vector<int32_t> lev(N, 0), dep(N, 0);
+    std::vector<int32_t> lev(N, 0);
     for (int64_t n = N - 1; n >= 0; --n)
         if (parent[n] >= 0) lev[parent[n]] = std::max(lev[parent[n]], lev[n] + 1);
-    for (int64_t n = 0; n < N; ++n) dep[n] = parent[n] < 0 ? 0 : dep[parent[n]] + 1;
     h.elim_ptr.push_back(0);
-    h.back_ptr.push_back(0);
     for (int c = 0; c < h.n_cells; ++c) {
         const int32_t a = h.cell_first[c], b = h.cell_first[c + 1];
-        int32_t maxl = 0, maxd = 0;
-        for (int32_t n = a; n < b; ++n) { maxl = std::max(maxl, lev[n]); maxd = std::max(maxd, dep[n]); }
+        const int32_t maxl = lev[a];   // the root has the highest level
+        h.max_levels = std::max(h.max_levels, (int)maxl);
+        std::vector<std::vector<int32_t>> byl(maxl + 1);
+        for (int32_t n = a; n < b; ++n)
+            if (parent[n] >= 0) byl[lev[n]].push_back(n);
         h.cell_elim.push_back((int32_t)h.elim_ptr.size() - 1);
-        std::vector<std::vector<int32_t>> byl(maxl + 1), byd(maxd + 1);
-        for (int32_t n = a; n < b; ++n) { byl[lev[n]].push_back(n); byd[dep[n]].push_back(n); }
-        for (int32_t L = 1; L <= maxl; ++L) {
-            h.elim_nodes.insert(h.elim_nodes.end(), byl[L].begin(), byl[L].end());
-            h.elim_ptr.push_back((int32_t)h.elim_nodes.size());
+        for (int32_t L = 0; L < maxl; ++L) {
+            for (int32_t n : byl[L]) { h.elim_n.push_back(n); h.elim_p.push_back(parent[n]); }
+            h.elim_ptr.push_back((int32_t)h.elim_n.size());
         }
-        h.cell_back.push_back((int32_t)h.back_ptr.size() - 1);
-        for (int32_t d = 0; d <= maxd; ++d) {
-            h.back_nodes.insert(h.back_nodes.end(), byd[d].begin(), byd[d].end());
-            h.back_ptr.push_back((int32_t)h.back_nodes.size());
-        }
-    }
-    h.cell_elim.push_back((int32_t)h.elim_ptr.size() - 1);
-    h.cell_back.push_back((int32_t)h.back_ptr.size() - 1);
-    if (h.elim_nodes.empty()) h.elim_nodes.push_back(0);
-    if (h.back_nodes.empty()) h.back_nodes.push_back(0);
-    for (int c = 0; c < h.n_cells; ++c) {
-        const int sz = h.cell_first[c + 1] - h.cell_first[c];
-        if (sz <= kCableLdsNodes) {
+        const int sz = b - a;
+        if (sz <= lds_nodes) {
             h.small_cells.push_back(c);
             h.small_max = std::max(h.small_max, sz);
         } else {
             h.large_cells.push_back(c);
         }
     }
+    h.cell_elim.push_back((int32_t)h.elim_ptr.size() - 1);
     return "";
 }
 
-// Device layout of a CableHost (256-byte aligned arrays), then D and R.
+// Device layout of a CableHost (256-byte aligned arrays), then the double
+// scratch: ekn, ekp (per edge record), D, R (per node).
+constexpr int kCableIntArrays = 10;
 size_t cable_layout(const CableHost &h, int64_t N, size_t *offs) {
-    const std::vector<int32_t> *arr[] = {&h.cell_first, &h.child_ptr, &h.child_idx, &h.elim_nodes,
-                                         &h.elim_ptr, &h.cell_elim, &h.back_nodes, &h.back_ptr,
-                                         &h.cell_back, &h.parent, &h.small_cells, &h.large_cells};
+    const std::vector<int32_t> *arr[kCableIntArrays] = {
+        &h.cell_first, &h.child_ptr, &h.child_idx, &h.elim_n, &h.elim_p, &h.elim_ptr, &h.cell_elim,
+        &h.parent, &h.small_cells, &h.large_cells};
     size_t off = 0;
-    for (int j = 0; j < 12; ++j) {
-        offs[j] = off;
-        off = (off + 4 * std::max<size_t>(arr[j]->size(), 1) + kAlign - 1) / kAlign * kAlign;
-    }
-    offs[12] = off;
-    off = (off + 8 * (size_t)std::max<int64_t>(N, 1) + kAlign - 1) / kAlign * kAlign;
-    offs[13] = off;
-    off = (off + 8 * (size_t)std::max<int64_t>(N, 1) + kAlign - 1) / kAlign * kAlign;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = (off + std::max<size_t>(bytes, 8) + kAlign - 1) / kAlign * kAlign;
+        return o;
+    };
+    for (int j = 0; j < kCableIntArrays; ++j) offs[j] = take(4 * arr[j]->size());
+    const size_t E = h.elim_n.size(), NN = (size_t)std::max<int64_t>(N, 1);
+    offs[kCableIntArrays + 0] = take(8 * E);    // ekn
+    offs[kCableIntArrays + 1] = take(8 * E);    // ekp
+    offs[kCableIntArrays + 2] = take(8 * NN);   // D
+    offs[kCableIntArrays + 3] = take(8 * NN);   // R
+    offs[kCableIntArrays + 4] = take(8 * NN);   // kn
+    offs[kCableIntArrays + 5] = take(8 * NN);   // kp
     return off;
+}
+
+// Nodes per cell whose D and R (16 B each node) fit the LDS a workgroup may
+// take on the current device.
+int cable_lds_nodes() {
+    int dev = 0, bytes = 65536;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int b = 0;
+        if (hipDeviceGetAttribute(&b, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && b > 0)
+            bytes = b;
+    }
+    // the level-boundary table of k_cable takes 4 KiB of static LDS
+    return std::max(0, (bytes - 8192) / 16);
 }
 
 struct Layout {
@@ -725,10 +732,12 @@ int mech_bind_nodes(mech_ctx *c, double *v, double *rhs, double *d, const double
 int mech_cable_required_bytes(int64_t n_nodes, const int32_t *parent, size_t *out) {
     if (!out || n_nodes < 0 || (n_nodes > 0 && !parent)) return fail(nullptr, MECH_ERR_INVAL, "null argument");
     CableHost h;
-    std::string why = build_cable(n_nodes, parent, h);
+    std::string why = build_cable(n_nodes, parent, 0, h);
     if (!why.empty()) return fail(nullptr, MECH_ERR_INVAL, "%s", why.c_str());
-    size_t offs[14];
-    *out = cable_layout(h, n_nodes, offs);
+    size_t offs[kCableIntArrays + 6];
+    // the LDS split of mech_bind_cable (device dependent) moves cells between
+    // two lists; each list's rounding to kAlign can add one alignment unit
+    *out = cable_layout(h, n_nodes, offs) + 2 * kAlign;
     return MECH_OK;
 }
 
@@ -737,17 +746,22 @@ int mech_bind_cable(mech_ctx *c, const int32_t *parent, const double *g_axial, v
     if (c->n_nodes > 0 && (!parent || !g_axial || !dev_buf))
         return fail(c, MECH_ERR_INVAL, "parent, g_axial and dev_buf are required");
     if (((uintptr_t)dev_buf % kAlign) != 0) return fail(c, MECH_ERR_INVAL, "dev_buf must be %d-byte aligned", kAlign);
+    int lds_nodes = cable_lds_nodes();
+    if (lds_nodes * 16 > 65536 && cable_allow_lds((size_t)lds_nodes * 16) != hipSuccess) {
+        (void)hipGetLastError();
+        lds_nodes = (65536 - 8192) / 16;
+    }
     CableHost h;
-    std::string why = build_cable(c->n_nodes, parent, h);
+    std::string why = build_cable(c->n_nodes, parent, lds_nodes, h);
     if (!why.empty()) return fail(c, MECH_ERR_INVAL, "%s", why.c_str());
-    size_t offs[14];
+    size_t offs[kCableIntArrays + 6];
     const size_t need = cable_layout(h, c->n_nodes, offs);
     if (dev_bytes < need) return fail(c, MECH_ERR_NOMEM, "cable buffer has %zu bytes, %zu required", dev_bytes, need);
     char *b = (char *)dev_buf;
-    const std::vector<int32_t> *arr[] = {&h.cell_first, &h.child_ptr, &h.child_idx, &h.elim_nodes,
-                                         &h.elim_ptr, &h.cell_elim, &h.back_nodes, &h.back_ptr,
-                                         &h.cell_back, &h.parent, &h.small_cells, &h.large_cells};
-    for (int j = 0; j < 12; ++j)
+    const std::vector<int32_t> *arr[kCableIntArrays] = {
+        &h.cell_first, &h.child_ptr, &h.child_idx, &h.elim_n, &h.elim_p, &h.elim_ptr, &h.cell_elim,
+        &h.parent, &h.small_cells, &h.large_cells};
+    for (int j = 0; j < kCableIntArrays; ++j)
         if (!arr[j]->empty())
             HIPCHK(c, hipMemcpy(b + offs[j], arr[j]->data(), 4 * arr[j]->size(), hipMemcpyHostToDevice));
     CableDev d{};
@@ -755,21 +769,29 @@ int mech_bind_cable(mech_ctx *c, const int32_t *parent, const double *g_axial, v
     d.cell_first = (const int *)(b + offs[0]);
     d.child_ptr = (const int *)(b + offs[1]);
     d.child_idx = (const int *)(b + offs[2]);
-    d.elim_nodes = (const int *)(b + offs[3]);
-    d.elim_ptr = (const int *)(b + offs[4]);
-    d.cell_elim = (const int *)(b + offs[5]);
-    d.back_nodes = (const int *)(b + offs[6]);
-    d.back_ptr = (const int *)(b + offs[7]);
-    d.cell_back = (const int *)(b + offs[8]);
-    d.parent = (const int *)(b + offs[9]);
-    d.small_cells = (const int *)(b + offs[10]);
-    d.large_cells = (const int *)(b + offs[11]);
-    d.D = (double *)(b + offs[12]);
-    d.R = (double *)(b + offs[13]);
+    d.elim_n = (const int *)(b + offs[3]);
+    d.elim_p = (const int *)(b + offs[4]);
+    d.elim_ptr = (const int *)(b + offs[5]);
+    d.cell_elim = (const int *)(b + offs[6]);
+    d.parent = (const int *)(b + offs[7]);
+    d.small_cells = (const int *)(b + offs[8]);
+    d.large_cells = (const int *)(b + offs[9]);
+    d.ekn = (double *)(b + offs[kCableIntArrays + 0]);
+    d.ekp = (double *)(b + offs[kCableIntArrays + 1]);
+    d.D = (double *)(b + offs[kCableIntArrays + 2]);
+    d.R = (double *)(b + offs[kCableIntArrays + 3]);
+    d.kn = (double *)(b + offs[kCableIntArrays + 4]);
+    d.kp = (double *)(b + offs[kCableIntArrays + 5]);
     d.n_cells = h.n_cells;
     d.n_small = (int)h.small_cells.size();
     d.n_large = (int)h.large_cells.size();
     d.small_max_nodes = h.small_max;
+    d.max_levels = h.max_levels;
+    if (c->n_nodes > 0) {
+        if (!c->nd.area) return fail(c, MECH_ERR_STATE, "bind area (mech_bind_nodes) before mech_bind_cable");
+        HIPCHK(c, launch_cable_coeffs(d, c->nd.area, (int)c->n_nodes, (int)h.elim_n.size(), c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
     c->cable = d;
     c->cable_bound = true;
     clear_graphs(c);

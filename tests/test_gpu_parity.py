@@ -436,6 +436,8 @@ def test_config4_cable_whole_cell_sample():
         M = run_oracle(sub, nsteps)
     starts = np.concatenate([[0], np.cumsum(w.cell_sizes)])
     nodes = np.concatenate([np.arange(starts[c], starts[c + 1]) for c in cells])
+    dv = np.max(np.abs(got["v"][nodes] - M.v))
+    log(f"c4 cable: max |dv| {dv:.3g} mV, spikes gpu {int(got['spikes'][nodes].sum())} oracle {int(M.spikes.sum())}")
     ws = compare_states(got, M, "fp64", keep=keep, label="c4 cable")
     wn = compare_nodes({k: got[k] for k in ("v", "rhs", "d")}, M, "fp64", nodes=nodes, label="c4 cable")
     assert np.array_equal(got["spikes"][nodes], M.spikes)
