@@ -147,22 +147,47 @@ int mech_bind_nodes(mech_ctx *ctx, double *v, double *rhs, double *d, const doub
                     const double *cm);
 
 /* Bytes of the device buffer the cell trees of MECH_V_CABLE need, from the
- * host parent array (int32, n_nodes entries).                              */
-int mech_cable_required_bytes(int64_t n_nodes, const int32_t *parent, size_t *out_bytes);
+ * host parent array (int32, n_nodes entries) and the unit_nodes that
+ * mech_bind_cable will be given, for the current device.                   */
+int mech_cable_required_bytes(int64_t n_nodes, const int32_t *parent, int32_t unit_nodes,
+                              size_t *out_bytes);
 
 /* Bind the cell trees for MECH_V_CABLE.  parent (host, int32[n_nodes]):
  * the parent of each node, -1 for a cell's root, with parent[n] < n (Hines
  * order) and every cell a contiguous node range that starts at its root
  * (MECH_ERR_INVAL otherwise).  g_axial (device, double[n_nodes], caller
- * owned): the axial conductance in uS between node n and its parent.  The
- * library builds per-cell elimination schedules into dev_buf (dev_bytes >=
+ * owned): the axial conductance in uS between node n and its parent.
+ * unit_nodes bounds the nodes one workgroup solves together in LDS (36 B
+ * per node): 0 takes the library's default of 1024, a value above the
+ * device's LDS capacity (4323 nodes on gfx950) is reduced to it, a
+ * negative one is MECH_ERR_INVAL.  Any bound gives the same elimination up
+ * to rounding; it only changes how cells are cut.  A cell larger than the bound is cut into subtrees that
+ * fit and a trunk, which is solved in global memory if it is still too
+ * large (a long unbranched cell).  The library builds the elimination
+ * schedules into dev_buf (dev_bytes >=
  * mech_cable_required_bytes, 256-byte aligned, caller owned, MECH_ERR_NOMEM
  * if short) and computes the coupling coefficients 100 g/area from the
  * bound area and g_axial, so area (mech_bind_nodes, MECH_ERR_STATE if not
  * bound) and g_axial must hold their values at this call; bind again after
  * changing either.  cm is read every step.                                 */
-int mech_bind_cable(mech_ctx *ctx, const int32_t *parent, const double *g_axial, void *dev_buf,
-                    size_t dev_bytes);
+int mech_bind_cable(mech_ctx *ctx, const int32_t *parent, const double *g_axial, int32_t unit_nodes,
+                    void *dev_buf, size_t dev_bytes);
+
+/* The cut of the cell trees that mech_bind_cable makes for this parent
+ * array and unit_nodes on the current device, on the host only (no device
+ * memory is touched), for inspection and tests.  sizes (int32[14])
+ * receives the lengths of the plan's arrays, in this order: parent,
+ * pos_node, pos_par, pos_src (per position: its node, the position of its
+ * parent's row in the same unit or -1, for a ghost the piece root's own
+ * position else -1), elim_n, elim_p (edge records: child and parent
+ * position, a root paired with itself), elim_ptr (height boundaries),
+ * unit_pos, unit_elim (per unit: position range, range into elim_ptr),
+ * unit_mode (0 whole cells, 1 subtrees of a cut cell, 2 its trunk), and
+ * the launch lists up, top (in LDS), top in global memory, down.  If buf is
+ * not NULL the arrays are written back to back into it (int32, buf_len
+ * entries; MECH_ERR_NOMEM if short).                                        */
+int mech_cable_plan(int64_t n_nodes, const int32_t *parent, int32_t unit_nodes, int32_t *sizes,
+                    int32_t *buf, int64_t buf_len);
 
 /* Bind the clamp waveform (device, double, n_nodes each) for MECH_V_CLAMP. */
 int mech_bind_clamp(mech_ctx *ctx, const double *off, const double *amp, const double *freq_hz,

@@ -68,23 +68,38 @@ struct NodesDev {
 // Cell trees of the cable mode: per cell a contiguous node range, the
 // children of every node (CSR), the non-leaf nodes grouped by elimination
 // level and all nodes grouped by depth.
+// Cell trees of the cable mode, cut into units that one workgroup solves.
+// A unit is a whole cell (FULL), a forest of subtrees whose roots hang off a
+// larger cell's trunk (PIECE), or that trunk (TOP) with the piece roots as
+// ghost rows.  Rows of the solve live at positions: every node has one, and
+// every piece root has a second one as a ghost in its trunk's unit.
+enum { kUnitFull = 0, kUnitPiece = 1, kUnitTop = 2 };
+// LDS of a unit solved there, per position: D and R (16 B) and one edge
+// record (two packed 16-bit rows, two couplings: 20 B).
+constexpr int kCableLdsBytesPerNode = 36;
+
 struct CableDev {
     const double *g_axial;     // uS to the parent
-    const int *parent;
-    const int *cell_first;     // [n_cells + 1]
-    const int *child_ptr;      // [n_nodes + 1]
-    const int *child_idx;
-    const int *elim_n;         // child n of every tree edge, per cell by n's elimination level
-    const int *elim_p;         // its parent
-    const int *elim_ptr;       // level boundaries into elim_n / elim_p
-    const int *cell_elim;      // [n_cells + 1] into elim_ptr
+    const int *parent;         // [n_nodes]
+    const int *pos_node;       // [n_pos] node of each position
+    const int *pos_pnode;      // [n_pos] that node's parent node, or -1
+    const int *pos_par;        // [n_pos] position of the parent's row in the same unit, or -1
+    const int *pos_src;        // [n_pos] ghost: the piece root's own position; -1 otherwise
+    const int *elim_n;         // edge records: child position, per unit by the child's height
+    const int *elim_p;         // parent position
+    const int *elim_ptr;       // height boundaries into elim_n / elim_p
+    const int *unit_pos;       // [n_units + 1] position ranges
+    const int *unit_elim;      // [n_units + 1] into elim_ptr
+    const int *unit_mode;      // [n_units] kUnit*
+    const int *list_up;        // FULL and PIECE units (LDS), tallest first
+    const int *list_top;       // TOP units that fit in LDS
+    const int *list_top_g;     // TOP units solved in global scratch
+    const int *list_down;      // PIECE units, second pass
+    int n_up, n_top, n_top_g, n_down;
+    int lds_max_nodes;         // largest unit solved in LDS
     double *ekn, *ekp;         // per edge record: 100 g/area_n, 100 g/area_p
     double *kn, *kp;           // per node: 100 g/area_n, 100 g/area_parent (0 at a root)
-    double *D, *R;             // per-node scratch of the solve (cells too large for LDS)
-    int n_cells;
-    const int *small_cells;    // cells solved with D and R in LDS
-    const int *large_cells;    // cells solved in global scratch
-    int n_small, n_large, small_max_nodes, max_levels;
+    double *D, *R;             // per position: rows handed between passes, global-scratch units
 };
 
 struct FusedArgs {

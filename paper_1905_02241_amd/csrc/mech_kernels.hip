@@ -59,10 +59,13 @@ __device__ __forceinline__ float one_minus_exp_f(float z) {
 // r <- r + r (1 - b r), then one residual correction of the quotient.  Valid
 // for normal, finite, non-zero b and a/b in the normal range, which holds
 // for every rate expression it is used on.
-__device__ __forceinline__ double fdiv(double a, double b) {
+__device__ __forceinline__ double rcp_d(double b) {
     double r = __builtin_amdgcn_rcp(b);
     r = fma(fma(-b, r, 1.0), r, r);
-    r = fma(fma(-b, r, 1.0), r, r);
+    return fma(fma(-b, r, 1.0), r, r);
+}
+__device__ __forceinline__ double fdiv(double a, double b) {
+    const double r = rcp_d(b);
     const double q = a * r;
     return fma(fma(-b, q, a), r, q);
 }
@@ -616,21 +619,30 @@ __global__ void k_visolated(NodesDev nd, GlobDev g) {
 }
 
 // ---------------------------------------------------------- cable solve --
-// Backward Euler of the cable equation on each cell's tree (Hines 1984), one
-// workgroup per cell.  Row n of the system: D_n dv_n - k_{n,p} dv_p -
-// sum_c k_{n,c} dv_c = R_n with D_n = 1e-3 cm/dt + d_n + k_{n,p} + sum_c
-// k_{n,c}, k_{n,j} = 100 g/area_n.
+// Backward Euler of the cable equation on each cell's tree (Hines 1984).  Row
+// n of the system: D_n dv_n - k_{n,p} dv_p - sum_c k_{n,c} dv_c = R_n with
+// D_n = 1e-3 cm/dt + d_n + k_{n,p} + sum_c k_{n,c}, k_{n,j} = 100 g/area_n.
 //
-// Elimination runs level by level from the leaves (a node's level is one more
-// than its highest child's): every edge child -> parent of the level folds
+// Elimination runs by height from the leaves (a node's height is one more
+// than its highest child's): every edge child -> parent of a height folds
 // the finished child row into its parent, D_p -= k_{p,n} k_{n,p}/D_n and
 // R_p += k_{p,n} R_n/D_n, by atomic adds (several children may share a
-// parent).  Back-substitution then walks the same levels downwards from the
-// root: dv_n = (R_n + k_{n,p} dv_p)/D_n.  Each level is one barrier; the edge
-// records of the next level are loaded before it, and the coupling
-// coefficients are precomputed per node and per record at mech_bind_cable,
-// so a level waits on no dependent global load.  D and R live in LDS (16 B per node) for cells that
-// fit, else in global scratch accessed at device scope.
+// parent).  Back-substitution walks the same heights downwards from the
+// root: dv_n = (R_n + k_{n,p} dv_p)/D_n.  Each height is one barrier.  The
+// coupling coefficients are precomputed per node and per record at
+// mech_bind_cable, and a unit's records are staged in LDS once, so a height
+// waits on LDS alone.
+//
+// A workgroup solves one unit with its rows and edge records in LDS (36 B
+// per position); a FULL unit holds one or more whole cells.  A cell too large for LDS is cut: every maximal subtree that fits becomes a
+// piece (small pieces share a unit as a forest), and the rest, the trunk,
+// one TOP unit.  Pieces eliminate up to their roots and hand the rows over
+// in global memory; the trunk's unit takes each piece root's row as a ghost
+// leaf, solves, and hands back the root's dv; the pieces then
+// back-substitute.  The elimination order within each tree stays a valid
+// Hines order, so the result is the same elimination up to rounding.  A
+// trunk larger than LDS is solved with its rows in global memory, accessed
+// at device scope.
 template <bool LDS> __device__ __forceinline__ double ldc(const double *p) {
     if constexpr (LDS) return *p;
     else return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -645,6 +657,7 @@ template <bool LDS> __device__ __forceinline__ void addc(double *p, double v) {
 }
 
 constexpr int kCableLevelsLds = 1024;   // level boundaries staged in LDS
+constexpr int kBatch = 4;               // loop iterations whose loads are issued together
 
 // Workgroup barrier for phases that share data only through LDS: it waits
 // for LDS traffic alone, so global loads issued before it (the next level's
@@ -661,121 +674,236 @@ template <bool LDS> __device__ __forceinline__ void level_barrier() {
 }
 
 template <bool LDS>
-__global__ __launch_bounds__(512) void k_cable(CableDev c, NodesDev nd, GlobDev g, const int *cells) {
+__global__ __launch_bounds__(512) void k_cable(CableDev c, NodesDev nd, GlobDev g, const int *units, int down) {
     extern __shared__ double lds[];
     __shared__ int lvl[kCableLevelsLds + 1];
     const int tid = (int)threadIdx.x, B = (int)blockDim.x;
-    const int cell = cells[blockIdx.x];
-    const int n0 = c.cell_first[cell], n1 = c.cell_first[cell + 1];
-    // node n's row sits at index n - base of D / R
+    const int u = units[blockIdx.x];
+    const int p0 = c.unit_pos[u], p1 = c.unit_pos[u + 1], np = p1 - p0;
+    const int mode = c.unit_mode[u];
+    const int L0 = c.unit_elim[u], L1 = c.unit_elim[u + 1], nlev = L1 - L0;
+    const int e0 = c.elim_ptr[L0], ne = c.elim_ptr[L1] - e0;
+    // Rows: in LDS at position - p0, in global memory at the position.
+    // Records (index q - e0): in LDS the unit's records, staged once, with
+    // both row indices packed into one int (a unit in LDS has < 2^16 rows).
+    const int base = LDS ? p0 : 0;
     double *D = LDS ? lds : c.D;
-    double *R = LDS ? lds + (n1 - n0) : c.R;
-    const int base = LDS ? n0 : 0;
-
-    // rows of the system: every node adds its own terms and its parent's
-    // (the coupling coefficients are precomputed per node)
-    for (int n = n0 + tid; n < n1; n += B) {
-        stc<LDS>(D + (n - base), 0.0);
-        stc<LDS>(R + (n - base), 0.0);
-    }
-    __syncthreads();
-    for (int n = n0 + tid; n < n1; n += B) {
-        const double vn = nd.v[n];
-        double Dn = 1e-3 * nd.cm[n] / g.dt + nd.d[n];
-        double Rn = nd.rhs[n];
-        const int p = c.parent[n];
-        if (p >= 0) {
-            const double kn = c.kn[n], kp = c.kp[n], dv = nd.v[p] - vn;
-            Dn += kn;
-            Rn += kn * dv;
-            addc<LDS>(D + (p - base), kp);
-            addc<LDS>(R + (p - base), -kp * dv);
-        }
-        addc<LDS>(D + (n - base), Dn);
-        addc<LDS>(R + (n - base), Rn);
-    }
-    const int L0 = c.cell_elim[cell], L1 = c.cell_elim[cell + 1];
-    const int nlev = L1 - L0;
+    double *R = LDS ? lds + np : c.R;
+    double *ekn = LDS ? lds + 2 * np : c.ekn + e0;
+    double *ekp = LDS ? lds + 2 * np + ne : c.ekp + e0;
+    int *rec = (int *)(lds + 2 * np + 2 * ne);
     const bool lv_lds = nlev < kCableLevelsLds;
     if (lv_lds)
-        for (int j = tid; j <= nlev; j += B) lvl[j] = c.elim_ptr[L0 + j];
-    __syncthreads();
+        for (int j = tid; j <= nlev; j += B) lvl[j] = c.elim_ptr[L0 + j] - e0;
+    auto lv = [&](int j) { return lv_lds ? lvl[j] : c.elim_ptr[L0 + j] - e0; };
+    // Passes over a unit's positions or records take kBatch iterations at a
+    // time and issue all their global loads before using any, so a pass
+    // waits about n / (kBatch B) memory latencies instead of n / B.
+    if constexpr (LDS)
+        for (int q0 = tid; q0 < ne; q0 += kBatch * B) {
+            int a[kBatch], b[kBatch];
+            double x[kBatch], y[kBatch];
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                const int q = q0 + k * B;
+                if (q < ne) {
+                    a[k] = c.elim_n[e0 + q];
+                    b[k] = c.elim_p[e0 + q];
+                    x[k] = c.ekn[e0 + q];
+                    y[k] = c.ekp[e0 + q];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                const int q = q0 + k * B;
+                if (q < ne) {
+                    rec[q] = (a[k] - p0) | ((b[k] - p0) << 16);
+                    ekn[q] = x[k];
+                    ekp[q] = y[k];
+                }
+            }
+        }
+    auto rows = [&](int q, int &rn, int &rp) {
+        if constexpr (LDS) {
+            const unsigned r = (unsigned)rec[q];
+            rn = (int)(r & 0xffffu);
+            rp = (int)(r >> 16);
+        } else {
+            rn = c.elim_n[e0 + q];
+            rp = c.elim_p[e0 + q];
+        }
+    };
 
-    // leaves to root, one level per barrier, next level's records prefetched
-    auto lv = [&](int j) { return lv_lds ? lvl[j] : c.elim_ptr[L0 + j]; };
-    int q = nlev > 0 ? lv(0) + tid : 0;
-    bool has = nlev > 0 && q < lv(1);
-    int rn = has ? c.elim_n[q] : 0, rp = has ? c.elim_p[q] : 0;
-    double rkn = has ? c.ekn[q] : 0.0, rkp = has ? c.ekp[q] : 0.0;
-    for (int j = 0; j < nlev; ++j) {
-        const int qend = lv(j + 1);
-        while (has) {
-            const double Dn = ldc<LDS>(D + (rn - base));
-            const double f = rkp / Dn;
-            addc<LDS>(D + (rp - base), -f * rkn);
-            addc<LDS>(R + (rp - base), f * ldc<LDS>(R + (rn - base)));
-            q += B;
-            has = q < qend;
-            if (has) {
-                rn = c.elim_n[q];
-                rp = c.elim_p[q];
-                rkn = c.ekn[q];
-                rkp = c.ekp[q];
+    if (!down) {
+        // rows: every position adds its own terms and its parent's (ghosts
+        // bring the piece root's eliminated row instead of their own terms)
+        for (int i = p0 + tid; i < p1; i += B) {
+            stc<LDS>(D + (i - base), 0.0);
+            stc<LDS>(R + (i - base), 0.0);
+        }
+        __syncthreads();
+        for (int i0 = p0 + tid; i0 < p1; i0 += kBatch * B) {
+            int n[kBatch], p[kBatch], lp[kBatch], src[kBatch];
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                const int i = i0 + k * B;
+                if (i < p1) {
+                    n[k] = c.pos_node[i];
+                    p[k] = c.pos_pnode[i];
+                    lp[k] = c.pos_par[i];
+                    src[k] = c.pos_src[i];
+                }
+            }
+            double vn[kBatch], vp[kBatch], a[kBatch], b[kBatch], e[kBatch], f[kBatch], kp[kBatch];
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                const int i = i0 + k * B;
+                if (i < p1) {
+                    vn[k] = nd.v[n[k]];
+                    vp[k] = p[k] >= 0 ? nd.v[p[k]] : vn[k];
+                    kp[k] = lp[k] >= 0 ? c.kp[n[k]] : 0.0;
+                    if (src[k] >= 0) {
+                        a[k] = c.D[src[k]];
+                        b[k] = c.R[src[k]];
+                    } else {
+                        a[k] = nd.cm[n[k]];
+                        b[k] = nd.rhs[n[k]];
+                        e[k] = nd.d[n[k]];
+                        f[k] = c.kn[n[k]];
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                const int i = i0 + k * B;
+                if (i < p1) {
+                    const double dv = p[k] >= 0 ? vp[k] - vn[k] : 0.0;
+                    double Dn = a[k], Rn = b[k];
+                    if (src[k] < 0) {
+                        Dn = 1e-3 * a[k] / g.dt + e[k] + f[k];
+                        Rn = b[k] + f[k] * dv;
+                    }
+                    if (lp[k] >= 0) {
+                        addc<LDS>(D + (lp[k] - base), kp[k]);
+                        addc<LDS>(R + (lp[k] - base), -kp[k] * dv);
+                    }
+                    addc<LDS>(D + (i - base), Dn);
+                    addc<LDS>(R + (i - base), Rn);
+                }
             }
         }
-        if (j + 1 < nlev) {
-            q = qend + tid;
-            has = q < lv(j + 2);
-            if (has) {
-                rn = c.elim_n[q];
-                rp = c.elim_p[q];
-                rkn = c.ekn[q];
-                rkp = c.ekp[q];
+        __syncthreads();
+
+        // leaves to root, one height per barrier.  The top height of a FULL
+        // or TOP unit holds its roots' records (a root paired with itself,
+        // couplings 0), which serve the back-substitution alone.
+        const int nel = mode == kUnitPiece ? nlev : nlev - 1;
+        for (int j = 0; j < nel; ++j) {
+            const int qend = lv(j + 1);
+            for (int q = lv(j) + tid; q < qend; q += B) {
+                int rn, rp;
+                rows(q, rn, rp);
+                // both loads ahead of the writes, which the compiler cannot
+                // place apart from the child's row
+                const double Dn = ldc<LDS>(D + rn), Rn = ldc<LDS>(R + rn);
+                const double f = ekp[q] / Dn;
+                addc<LDS>(D + rp, -f * ekn[q]);
+                addc<LDS>(R + rp, f * Rn);
             }
+            level_barrier<LDS>();
         }
-        level_barrier<LDS>();
+        if (mode == kUnitPiece) {
+            // eliminated rows go to the trunk's unit and to the second pass
+            if constexpr (LDS)
+                for (int i = p0 + tid; i < p1; i += B) {
+                    c.D[i] = D[i - base];
+                    c.R[i] = R[i - base];
+                }
+            return;
+        }
+    } else {
+        // second pass of a piece: its eliminated rows, and at each root the
+        // dv its trunk's unit handed back
+        if constexpr (LDS)
+            for (int i0 = p0 + tid; i0 < p1; i0 += kBatch * B) {
+                double x[kBatch], y[kBatch];
+#pragma unroll
+                for (int k = 0; k < kBatch; ++k) {
+                    const int i = i0 + k * B;
+                    if (i < p1) {
+                        x[k] = c.D[i];
+                        y[k] = c.R[i];
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < kBatch; ++k) {
+                    const int i = i0 + k * B;
+                    if (i < p1) {
+                        D[i - base] = x[k];
+                        R[i - base] = y[k];
+                    }
+                }
+            }
+        __syncthreads();
     }
 
-    // root to leaves: dv overwrites R.  The elimination records in reverse
-    // level order visit every parent before its children (a parent's level is
-    // higher), so they serve the back-substitution too; the root goes first.
-    if (tid == 0) stc<LDS>(R + (n0 - base), ldc<LDS>(R + (n0 - base)) / ldc<LDS>(D + (n0 - base)));
-    level_barrier<LDS>();
-    q = nlev > 0 ? lv(nlev - 1) + tid : 0;
-    has = nlev > 0 && q < lv(nlev);
-    if (has) { rn = c.elim_n[q]; rp = c.elim_p[q]; rkn = c.ekn[q]; }
+    // root to leaves: dv overwrites R.  The records in reverse height order
+    // visit every parent before its children; a root's own record gives
+    // dv = R/D.
     for (int j = nlev - 1; j >= 0; --j) {
         const int qend = lv(j + 1);
-        while (has) {
-            const double r = ldc<LDS>(R + (rn - base)) + rkn * ldc<LDS>(R + (rp - base));
-            stc<LDS>(R + (rn - base), r / ldc<LDS>(D + (rn - base)));
-            q += B;
-            has = q < qend;
-            if (has) { rn = c.elim_n[q]; rp = c.elim_p[q]; rkn = c.ekn[q]; }
-        }
-        if (j > 0) {
-            q = lv(j - 1) + tid;
-            has = q < lv(j);
-            if (has) { rn = c.elim_n[q]; rp = c.elim_p[q]; rkn = c.ekn[q]; }
+        for (int q = lv(j) + tid; q < qend; q += B) {
+            int rn, rp;
+            rows(q, rn, rp);
+            const double r = ldc<LDS>(R + rn) + ekn[q] * ldc<LDS>(R + rp);
+            stc<LDS>(R + rn, r / ldc<LDS>(D + rn));
         }
         level_barrier<LDS>();
     }
-    for (int n = n0 + tid; n < n1; n += B) {
-        const double v0 = nd.v[n], v1 = v0 + ldc<LDS>(R + (n - base));
-        if (v0 < g.vthresh && v1 >= g.vthresh) nd.spikes[n] += 1;
-        nd.v[n] = v1;
+    for (int i0 = p0 + tid; i0 < p1; i0 += kBatch * B) {
+        int n[kBatch], src[kBatch];
+        double v0[kBatch];
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            const int i = i0 + k * B;
+            if (i < p1) {
+                n[k] = c.pos_node[i];
+                src[k] = c.pos_src[i];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            const int i = i0 + k * B;
+            if (i < p1 && src[k] < 0) v0[k] = nd.v[n[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            const int i = i0 + k * B;
+            if (i >= p1) continue;
+            const double dv = ldc<LDS>(R + (i - base));
+            if (src[k] >= 0) {
+                c.R[src[k]] = dv;   // the piece root's dv, for its second pass
+                continue;
+            }
+            const double v1 = v0[k] + dv;
+            if (v0[k] < g.vthresh && v1 >= g.vthresh) nd.spikes[n[k]] += 1;
+            nd.v[n[k]] = v1;
+        }
     }
 }
 
 hipError_t launch_cable(const CableDev &c, const NodesDev &nd, const GlobDev &g, hipStream_t s) {
-    if (c.n_small > 0)
-        k_cable<true><<<c.n_small, 512, 16 * (size_t)c.small_max_nodes, s>>>(c, nd, g, c.small_cells);
-    if (c.n_large > 0) k_cable<false><<<c.n_large, 512, 0, s>>>(c, nd, g, c.large_cells);
+    const size_t lds = kCableLdsBytesPerNode * (size_t)c.lds_max_nodes;
+    if (c.n_up > 0) k_cable<true><<<c.n_up, 512, lds, s>>>(c, nd, g, c.list_up, 0);
+    if (c.n_top > 0) k_cable<true><<<c.n_top, 512, lds, s>>>(c, nd, g, c.list_top, 0);
+    if (c.n_top_g > 0) k_cable<false><<<c.n_top_g, 512, 0, s>>>(c, nd, g, c.list_top_g, 0);
+    if (c.n_down > 0) k_cable<true><<<c.n_down, 512, lds, s>>>(c, nd, g, c.list_down, 1);
     return hipGetLastError();
 }
 
 // Coupling coefficients of the tree from the bound area and g_axial: per node
-// (towards its parent, and the parent's towards it) and per edge record.
+// (towards its parent, and the parent's towards it) and per edge record (0
+// for a root's own record).
 __global__ void k_cable_coeffs(CableDev c, const double *area, int n_nodes, int n_edges) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n_nodes) {
@@ -785,10 +913,10 @@ __global__ void k_cable_coeffs(CableDev c, const double *area, int n_nodes, int 
         c.kp[i] = p >= 0 ? 1e2 * ga / area[p] : 0.0;
     }
     if (i < n_edges) {
-        const int n = c.elim_n[i], p = c.elim_p[i];
+        const int n = c.pos_node[c.elim_n[i]], p = c.parent[n];
         const double ga = c.g_axial[n];
-        c.ekn[i] = 1e2 * ga / area[n];
-        c.ekp[i] = 1e2 * ga / area[p];
+        c.ekn[i] = p >= 0 ? 1e2 * ga / area[n] : 0.0;
+        c.ekp[i] = p >= 0 ? 1e2 * ga / area[p] : 0.0;
     }
 }
 

@@ -73,76 +73,185 @@ struct SlotHost {
     bool has_gid = false, has_ica = false;
 };
 
-// Cell trees of the cable mode, built on the host at mech_bind_cable.
+// Cell trees of the cable mode, cut into units on the host at
+// mech_bind_cable (the unit kinds and positions are described with CableDev).
 struct CableHost {
-    int n_cells = 0;
-    std::vector<int32_t> cell_first, child_ptr, child_idx, elim_n, elim_p, elim_ptr, cell_elim, parent,
-        small_cells, large_cells;
-    int small_max = 0, max_levels = 0;
+    std::vector<int32_t> parent, pos_node, pos_par, pos_src, elim_n, elim_p, elim_ptr, unit_pos, unit_elim,
+        unit_mode, list_up, list_top, list_top_g, list_down, pos_pnode;
+    int lds_max = 0;
 };
 
-// Validates Hines order and contiguous cells and fills the schedules: edge
-// records (child, parent) per cell by the child's elimination level, and the
-// split into cells whose D and R fit in LDS (lds_nodes, 16 B per node) and
-// the rest.  Returns "" on success.
-std::string build_cable(int64_t N, const int32_t *parent, int lds_nodes, CableHost &h) {
+// Validates Hines order and contiguous cells, then cuts the trees into units
+// of at most `cap` positions (a trunk may exceed it) and writes each unit's
+// edge records bucketed by the child's height.  Returns "" on success.
+std::string build_cable(int64_t N, const int32_t *parent, int cap, CableHost &h) {
     h = CableHost();
+    if (cap < 1) cap = 1;
+    std::vector<int32_t> first;
     for (int64_t n = 0; n < N; ++n) {
         const int32_t p = parent[n];
         if (p < -1 || p >= n) return "parent[n] must be -1 or a node index below n (Hines order)";
-        if (p < 0) h.cell_first.push_back((int32_t)n);
-        else if (h.cell_first.empty() || p < h.cell_first.back())
+        if (p < 0) first.push_back((int32_t)n);
+        else if (first.empty() || p < first.back())
             return "every cell must be a contiguous node range starting at its root";
     }
-    if (N > 0 && (h.cell_first.empty() || h.cell_first[0] != 0)) return "node 0 must be a root";
-    h.n_cells = (int)h.cell_first.size();
-    h.cell_first.push_back((int32_t)N);
+    if (N > 0 && (first.empty() || first[0] != 0)) return "node 0 must be a root";
+    const int n_cells = (int)first.size();
+    first.push_back((int32_t)N);
     h.parent.assign(parent, parent + N);
-    h.child_ptr.assign(N + 1, 0);
-    for (int64_t n = 0; n < N; ++n)
-        if (parent[n] >= 0) ++h.child_ptr[parent[n] + 1];
-    for (int64_t n = 0; n < N; ++n) h.child_ptr[n + 1] += h.child_ptr[n];
-    h.child_idx.assign(std::max<int32_t>(h.child_ptr[N], 1), 0);
-    {
-        std::vector<int32_t> fill(h.child_ptr.begin(), h.child_ptr.end() - 1);
-        for (int64_t n = 0; n < N; ++n)
-            if (parent[n] >= 0) h.child_idx[fill[parent[n]]++] = (int32_t)n;
-    }
-    std::vector<int32_t> lev(N, 0);
+    std::vector<int32_t> sub(N, 1), ht(N, 0);
     for (int64_t n = N - 1; n >= 0; --n)
-        if (parent[n] >= 0) lev[parent[n]] = std::max(lev[parent[n]], lev[n] + 1);
+        if (parent[n] >= 0) {
+            sub[parent[n]] += sub[n];
+            ht[parent[n]] = std::max(ht[parent[n]], ht[n] + 1);
+        }
+    std::vector<int32_t> pos(N, -1), th(N, 0), levels;
+    h.unit_pos.push_back(0);
     h.elim_ptr.push_back(0);
-    for (int c = 0; c < h.n_cells; ++c) {
-        const int32_t a = h.cell_first[c], b = h.cell_first[c + 1];
-        const int32_t maxl = lev[a];   // the root has the highest level
-        h.max_levels = std::max(h.max_levels, (int)maxl);
-        std::vector<std::vector<int32_t>> byl(maxl + 1);
-        for (int32_t n = a; n < b; ++n)
-            if (parent[n] >= 0) byl[lev[n]].push_back(n);
-        h.cell_elim.push_back((int32_t)h.elim_ptr.size() - 1);
-        for (int32_t L = 0; L < maxl; ++L) {
-            for (int32_t n : byl[L]) { h.elim_n.push_back(n); h.elim_p.push_back(parent[n]); }
+    struct Rec { int32_t h, n, p; };
+    // closes the unit whose positions were placed last; recs are (height,
+    // child position, parent position), a root paired with itself
+    auto add_unit = [&](int mode, std::vector<Rec> &recs, int nlev) {
+        const int u = (int)h.unit_mode.size();
+        h.unit_mode.push_back(mode);
+        h.unit_pos.push_back((int32_t)h.pos_node.size());
+        h.unit_elim.push_back((int32_t)h.elim_ptr.size() - 1);
+        std::stable_sort(recs.begin(), recs.end(), [](const Rec &x, const Rec &y) { return x.h < y.h; });
+        size_t k = 0;
+        for (int L = 0; L < nlev; ++L) {
+            for (; k < recs.size() && recs[k].h == L; ++k) {
+                h.elim_n.push_back(recs[k].n);
+                h.elim_p.push_back(recs[k].p);
+            }
             h.elim_ptr.push_back((int32_t)h.elim_n.size());
         }
-        const int sz = b - a;
-        if (sz <= lds_nodes) {
-            h.small_cells.push_back(c);
-            h.small_max = std::max(h.small_max, sz);
-        } else {
-            h.large_cells.push_back(c);
+        levels.push_back(nlev);
+        const int size = h.unit_pos[u + 1] - h.unit_pos[u];
+        if (mode != kUnitTop || size <= cap) h.lds_max = std::max(h.lds_max, size);
+        if (mode == kUnitFull || mode == kUnitPiece) h.list_up.push_back(u);
+        if (mode == kUnitPiece) h.list_down.push_back(u);
+        if (mode == kUnitTop) (size <= cap ? h.list_top : h.list_top_g).push_back(u);
+    };
+    auto place = [&](int32_t n, int32_t par_pos, int32_t src) {
+        const int32_t i = (int32_t)h.pos_node.size();
+        h.pos_node.push_back(n);
+        h.pos_pnode.push_back(parent[n]);
+        h.pos_par.push_back(par_pos);
+        h.pos_src.push_back(src);
+        return i;
+    };
+
+    // whole cells that fit, packed into forests of up to `pack` nodes so that
+    // many small cells do not each take a workgroup
+    int64_t fit_nodes = 0;
+    for (int c = 0; c < n_cells; ++c)
+        if (first[c + 1] - first[c] <= cap) fit_nodes += first[c + 1] - first[c];
+    const int pack = (int)std::min<int64_t>(cap, std::max<int64_t>(1024, (fit_nodes + 511) / 512));
+    std::vector<Rec> recs;
+    int nlev = 0, cur = 0;
+    auto close_full = [&]() {
+        // every root's own record goes to the unit's top height
+        for (Rec &r : recs)
+            if (r.h < 0) r.h = nlev - 1;
+        if (cur > 0) add_unit(kUnitFull, recs, nlev);
+        recs.clear();
+        nlev = 0;
+        cur = 0;
+    };
+    for (int c = 0; c < n_cells; ++c) {
+        const int32_t a = first[c], b = first[c + 1];
+        if (b - a > cap) continue;
+        if (cur + (b - a) > pack) close_full();
+        for (int32_t n = a; n < b; ++n) {
+            const int32_t p = parent[n];
+            pos[n] = place(n, p >= 0 ? pos[p] : -1, -1);
+            recs.push_back({p >= 0 ? ht[n] : -1, pos[n], p >= 0 ? pos[p] : pos[n]});
         }
+        nlev = std::max(nlev, ht[a] + 1);
+        cur += b - a;
     }
-    h.cell_elim.push_back((int32_t)h.elim_ptr.size() - 1);
+    close_full();
+
+    // cells too large: maximal subtrees that fit become pieces, packed into
+    // forests; the trunk (subtree larger than cap) is one unit
+    for (int c = 0; c < n_cells; ++c) {
+        const int32_t a = first[c], b = first[c + 1];
+        if (b - a <= cap) continue;
+        std::vector<int32_t> pid(b - a, -1), roots, unit_of;
+        std::vector<int> piece_unit_size;
+        for (int32_t n = a; n < b; ++n) {
+            if (sub[n] > cap) continue;
+            const int32_t p = parent[n];
+            if (sub[p] > cap) {
+                pid[n - a] = (int32_t)roots.size();
+                roots.push_back(n);
+            } else {
+                pid[n - a] = pid[p - a];
+            }
+        }
+        // greedy packing in root order
+        int units = 0, fill = 0;
+        for (int32_t r : roots) {
+            if (units == 0 || fill + sub[r] > cap) {
+                ++units;
+                fill = 0;
+            }
+            fill += sub[r];
+            unit_of.push_back(units - 1);
+        }
+        std::vector<std::vector<int32_t>> members(units);
+        for (int32_t n = a; n < b; ++n)
+            if (pid[n - a] >= 0) members[unit_of[pid[n - a]]].push_back(n);
+        for (int k = 0; k < units; ++k) {
+            recs.clear();
+            int nl = 0;
+            for (int32_t n : members[k]) {
+                const int32_t p = parent[n];
+                const bool root = sub[p] > cap;
+                pos[n] = place(n, root ? -1 : pos[p], -1);
+                if (root) nl = std::max(nl, ht[n]);
+                else recs.push_back({ht[n], pos[n], pos[p]});
+            }
+            add_unit(kUnitPiece, recs, nl);
+        }
+        // the trunk with the piece roots as ghost leaves; heights counted
+        // within the unit (a ghost is a leaf)
+        std::vector<int32_t> tn;
+        for (int32_t n = a; n < b; ++n)
+            if (sub[n] > cap || (parent[n] >= 0 && sub[parent[n]] > cap)) tn.push_back(n);
+        for (auto it = tn.rbegin(); it != tn.rend(); ++it) th[*it] = 0;
+        for (auto it = tn.rbegin(); it != tn.rend(); ++it)
+            if (parent[*it] >= 0) th[parent[*it]] = std::max(th[parent[*it]], th[*it] + 1);
+        recs.clear();
+        for (size_t k = 0; k < tn.size(); ++k) {
+            const int32_t n = tn[k], p = parent[n];
+            const bool ghost = sub[n] <= cap;
+            const int32_t i = place(n, p >= 0 ? pos[p] : -1, ghost ? pos[n] : -1);
+            if (!ghost) pos[n] = i;   // trunk nodes: their only position
+            recs.push_back({th[n], i, p >= 0 ? pos[p] : i});
+        }
+        add_unit(kUnitTop, recs, th[a] + 1);
+    }
+    h.unit_elim.push_back((int32_t)h.elim_ptr.size() - 1);
+    // tallest units first so that the longest chains of barriers start first
+    auto by_height = [&](std::vector<int32_t> &l) {
+        std::stable_sort(l.begin(), l.end(), [&](int32_t x, int32_t y) { return levels[x] > levels[y]; });
+    };
+    by_height(h.list_up);
+    by_height(h.list_top);
+    by_height(h.list_top_g);
+    by_height(h.list_down);
     return "";
 }
 
 // Device layout of a CableHost (256-byte aligned arrays), then the double
-// scratch: ekn, ekp (per edge record), D, R (per node).
-constexpr int kCableIntArrays = 10;
+// arrays: ekn, ekp (per edge record), D, R (per position), kn, kp (per node).
+constexpr int kCableIntArrays = 15;
 size_t cable_layout(const CableHost &h, int64_t N, size_t *offs) {
     const std::vector<int32_t> *arr[kCableIntArrays] = {
-        &h.cell_first, &h.child_ptr, &h.child_idx, &h.elim_n, &h.elim_p, &h.elim_ptr, &h.cell_elim,
-        &h.parent, &h.small_cells, &h.large_cells};
+        &h.parent, &h.pos_node, &h.pos_par, &h.pos_src, &h.elim_n, &h.elim_p, &h.elim_ptr,
+        &h.unit_pos, &h.unit_elim, &h.unit_mode, &h.list_up, &h.list_top, &h.list_top_g, &h.list_down,
+        &h.pos_pnode};
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -150,18 +259,18 @@ size_t cable_layout(const CableHost &h, int64_t N, size_t *offs) {
         return o;
     };
     for (int j = 0; j < kCableIntArrays; ++j) offs[j] = take(4 * arr[j]->size());
-    const size_t E = h.elim_n.size(), NN = (size_t)std::max<int64_t>(N, 1);
+    const size_t E = h.elim_n.size(), P = h.pos_node.size(), NN = (size_t)std::max<int64_t>(N, 1);
     offs[kCableIntArrays + 0] = take(8 * E);    // ekn
     offs[kCableIntArrays + 1] = take(8 * E);    // ekp
-    offs[kCableIntArrays + 2] = take(8 * NN);   // D
-    offs[kCableIntArrays + 3] = take(8 * NN);   // R
+    offs[kCableIntArrays + 2] = take(8 * P);    // D
+    offs[kCableIntArrays + 3] = take(8 * P);    // R
     offs[kCableIntArrays + 4] = take(8 * NN);   // kn
     offs[kCableIntArrays + 5] = take(8 * NN);   // kp
     return off;
 }
 
-// Nodes per cell whose D and R (16 B each node) fit the LDS a workgroup may
-// take on the current device.
+// Positions of a unit whose rows and records fit the LDS a workgroup may
+// take on the current device (packed record rows need fewer than 2^16).
 int cable_lds_nodes() {
     int dev = 0, bytes = 65536;
     if (hipGetDevice(&dev) == hipSuccess) {
@@ -170,7 +279,7 @@ int cable_lds_nodes() {
             bytes = b;
     }
     // the level-boundary table of k_cable takes 4 KiB of static LDS
-    return std::max(0, (bytes - 8192) / 16);
+    return std::min(65535, std::max(0, (bytes - 8192) / kCableLdsBytesPerNode));
 }
 
 struct Layout {
@@ -729,64 +838,112 @@ int mech_bind_nodes(mech_ctx *c, double *v, double *rhs, double *d, const double
     return MECH_OK;
 }
 
-int mech_cable_required_bytes(int64_t n_nodes, const int32_t *parent, size_t *out) {
-    if (!out || n_nodes < 0 || (n_nodes > 0 && !parent)) return fail(nullptr, MECH_ERR_INVAL, "null argument");
-    CableHost h;
-    std::string why = build_cable(n_nodes, parent, 0, h);
-    if (!why.empty()) return fail(nullptr, MECH_ERR_INVAL, "%s", why.c_str());
-    size_t offs[kCableIntArrays + 6];
-    // the LDS split of mech_bind_cable (device dependent) moves cells between
-    // two lists; each list's rounding to kAlign can add one alignment unit
-    *out = cable_layout(h, n_nodes, offs) + 2 * kAlign;
+// The unit size bound for a requested unit_nodes, at most the device's LDS
+// capacity; the fallback capacity is the one without the large-LDS opt-in.
+// The default, 1024 nodes, was the fastest bound on branched cells of 200 to
+// 20 000 compartments (units of 512 to 4096 nodes measured): smaller units
+// run more workgroups at once, larger ones leave fewer trunk heights.
+constexpr int kCableFallbackNodes = (65536 - 8192) / kCableLdsBytesPerNode;
+constexpr int kCableDefaultUnit = 1024;
+int cable_cap(int32_t unit_nodes, int lds_nodes) {
+    return std::min<int>(unit_nodes > 0 ? unit_nodes : kCableDefaultUnit, lds_nodes);
+}
+
+int mech_cable_required_bytes(int64_t n_nodes, const int32_t *parent, int32_t unit_nodes, size_t *out) {
+    if (!out || n_nodes < 0 || (n_nodes > 0 && !parent) || unit_nodes < 0)
+        return fail(nullptr, MECH_ERR_INVAL, "null argument or negative unit_nodes");
+    size_t need = 0, offs[kCableIntArrays + 6];
+    // mech_bind_cable cuts with the device's capacity, or with the fallback
+    // if the device refuses the large LDS request: size for both
+    for (int lds : {std::max(cable_lds_nodes(), 1), kCableFallbackNodes}) {
+        CableHost h;
+        std::string why = build_cable(n_nodes, parent, cable_cap(unit_nodes, lds), h);
+        if (!why.empty()) return fail(nullptr, MECH_ERR_INVAL, "%s", why.c_str());
+        need = std::max(need, cable_layout(h, n_nodes, offs));
+    }
+    *out = need;
     return MECH_OK;
 }
 
-int mech_bind_cable(mech_ctx *c, const int32_t *parent, const double *g_axial, void *dev_buf, size_t dev_bytes) {
+int mech_cable_plan(int64_t n_nodes, const int32_t *parent, int32_t unit_nodes, int32_t *sizes, int32_t *buf,
+                    int64_t buf_len) {
+    if (!sizes || n_nodes < 0 || (n_nodes > 0 && !parent) || unit_nodes < 0 || buf_len < 0)
+        return fail(nullptr, MECH_ERR_INVAL, "null argument or negative size");
+    CableHost h;
+    std::string why = build_cable(n_nodes, parent, cable_cap(unit_nodes, std::max(cable_lds_nodes(), 1)), h);
+    if (!why.empty()) return fail(nullptr, MECH_ERR_INVAL, "%s", why.c_str());
+    constexpr int kPlanArrays = 14;   // pos_pnode (parent of pos_node) is not part of the plan
+    const std::vector<int32_t> *arr[kPlanArrays] = {
+        &h.parent, &h.pos_node, &h.pos_par, &h.pos_src, &h.elim_n, &h.elim_p, &h.elim_ptr,
+        &h.unit_pos, &h.unit_elim, &h.unit_mode, &h.list_up, &h.list_top, &h.list_top_g, &h.list_down};
+    int64_t total = 0;
+    for (int j = 0; j < kPlanArrays; ++j) {
+        sizes[j] = (int32_t)arr[j]->size();
+        total += sizes[j];
+    }
+    if (!buf) return MECH_OK;
+    if (buf_len < total) return fail(nullptr, MECH_ERR_NOMEM, "plan needs %lld entries", (long long)total);
+    for (int j = 0; j < kPlanArrays; ++j) buf = std::copy(arr[j]->begin(), arr[j]->end(), buf);
+    return MECH_OK;
+}
+
+int mech_bind_cable(mech_ctx *c, const int32_t *parent, const double *g_axial, int32_t unit_nodes, void *dev_buf,
+                    size_t dev_bytes) {
     if (!c) return fail(nullptr, MECH_ERR_INVAL, "null ctx");
     if (c->n_nodes > 0 && (!parent || !g_axial || !dev_buf))
         return fail(c, MECH_ERR_INVAL, "parent, g_axial and dev_buf are required");
+    if (unit_nodes < 0) return fail(c, MECH_ERR_INVAL, "unit_nodes must be >= 0");
     if (((uintptr_t)dev_buf % kAlign) != 0) return fail(c, MECH_ERR_INVAL, "dev_buf must be %d-byte aligned", kAlign);
-    int lds_nodes = cable_lds_nodes();
-    if (lds_nodes * 16 > 65536 && cable_allow_lds((size_t)lds_nodes * 16) != hipSuccess) {
+    int lds_nodes = std::max(cable_lds_nodes(), 1);
+    if (lds_nodes * kCableLdsBytesPerNode > 65536 &&
+        cable_allow_lds((size_t)lds_nodes * kCableLdsBytesPerNode) != hipSuccess) {
         (void)hipGetLastError();
-        lds_nodes = (65536 - 8192) / 16;
+        lds_nodes = kCableFallbackNodes;
     }
     CableHost h;
-    std::string why = build_cable(c->n_nodes, parent, lds_nodes, h);
+    std::string why = build_cable(c->n_nodes, parent, cable_cap(unit_nodes, lds_nodes), h);
     if (!why.empty()) return fail(c, MECH_ERR_INVAL, "%s", why.c_str());
     size_t offs[kCableIntArrays + 6];
     const size_t need = cable_layout(h, c->n_nodes, offs);
     if (dev_bytes < need) return fail(c, MECH_ERR_NOMEM, "cable buffer has %zu bytes, %zu required", dev_bytes, need);
     char *b = (char *)dev_buf;
     const std::vector<int32_t> *arr[kCableIntArrays] = {
-        &h.cell_first, &h.child_ptr, &h.child_idx, &h.elim_n, &h.elim_p, &h.elim_ptr, &h.cell_elim,
-        &h.parent, &h.small_cells, &h.large_cells};
+        &h.parent, &h.pos_node, &h.pos_par, &h.pos_src, &h.elim_n, &h.elim_p, &h.elim_ptr,
+        &h.unit_pos, &h.unit_elim, &h.unit_mode, &h.list_up, &h.list_top, &h.list_top_g, &h.list_down,
+        &h.pos_pnode};
     for (int j = 0; j < kCableIntArrays; ++j)
         if (!arr[j]->empty())
             HIPCHK(c, hipMemcpy(b + offs[j], arr[j]->data(), 4 * arr[j]->size(), hipMemcpyHostToDevice));
+    const int *I[kCableIntArrays];
+    for (int j = 0; j < kCableIntArrays; ++j) I[j] = (const int *)(b + offs[j]);
     CableDev d{};
     d.g_axial = g_axial;
-    d.cell_first = (const int *)(b + offs[0]);
-    d.child_ptr = (const int *)(b + offs[1]);
-    d.child_idx = (const int *)(b + offs[2]);
-    d.elim_n = (const int *)(b + offs[3]);
-    d.elim_p = (const int *)(b + offs[4]);
-    d.elim_ptr = (const int *)(b + offs[5]);
-    d.cell_elim = (const int *)(b + offs[6]);
-    d.parent = (const int *)(b + offs[7]);
-    d.small_cells = (const int *)(b + offs[8]);
-    d.large_cells = (const int *)(b + offs[9]);
+    d.parent = I[0];
+    d.pos_node = I[1];
+    d.pos_par = I[2];
+    d.pos_src = I[3];
+    d.elim_n = I[4];
+    d.elim_p = I[5];
+    d.elim_ptr = I[6];
+    d.unit_pos = I[7];
+    d.unit_elim = I[8];
+    d.unit_mode = I[9];
+    d.list_up = I[10];
+    d.list_top = I[11];
+    d.list_top_g = I[12];
+    d.list_down = I[13];
+    d.pos_pnode = I[14];
+    d.n_up = (int)h.list_up.size();
+    d.n_top = (int)h.list_top.size();
+    d.n_top_g = (int)h.list_top_g.size();
+    d.n_down = (int)h.list_down.size();
+    d.lds_max_nodes = h.lds_max;
     d.ekn = (double *)(b + offs[kCableIntArrays + 0]);
     d.ekp = (double *)(b + offs[kCableIntArrays + 1]);
     d.D = (double *)(b + offs[kCableIntArrays + 2]);
     d.R = (double *)(b + offs[kCableIntArrays + 3]);
     d.kn = (double *)(b + offs[kCableIntArrays + 4]);
     d.kp = (double *)(b + offs[kCableIntArrays + 5]);
-    d.n_cells = h.n_cells;
-    d.n_small = (int)h.small_cells.size();
-    d.n_large = (int)h.large_cells.size();
-    d.small_max_nodes = h.small_max;
-    d.max_levels = h.max_levels;
     if (c->n_nodes > 0) {
         if (!c->nd.area) return fail(c, MECH_ERR_STATE, "bind area (mech_bind_nodes) before mech_bind_cable");
         HIPCHK(c, launch_cable_coeffs(d, c->nd.area, (int)c->n_nodes, (int)h.elim_n.size(), c->stream));

@@ -29,6 +29,7 @@ GLOBAL_NAMES = ("celsius", "ena", "ek", "eh", "cao", "cai0", "tau_ca", "ca_gamma
 
 # Exported symbols of include/mech.h (checked by the CPU tests).
 SYMBOLS = ("mech_required_bytes", "mech_alloc", "mech_bind_nodes", "mech_bind_clamp", "mech_cable_required_bytes",
+           "mech_cable_plan",
            "mech_bind_cable", "mech_set_params",
            "mech_set_global", "mech_init", "mech_cur", "mech_state", "mech_step", "mech_set_launch",
            "mech_get_launch", "mech_autotune", "mech_get_state", "mech_set_state", "mech_spike_counts",
@@ -69,8 +70,9 @@ def load_library(path: str = LIB_PATH):
         "mech_alloc": [C.POINTER(vp), C.c_int64, C.POINTER(TypeDesc), C.c_int, C.c_int, vp, C.c_size_t, vp],
         "mech_bind_nodes": [vp, vp, vp, vp, vp, vp],
         "mech_bind_clamp": [vp, vp, vp, vp, vp],
-        "mech_cable_required_bytes": [C.c_int64, ip, C.POINTER(C.c_size_t)],
-        "mech_bind_cable": [vp, ip, vp, vp, C.c_size_t],
+        "mech_cable_required_bytes": [C.c_int64, ip, C.c_int32, C.POINTER(C.c_size_t)],
+        "mech_cable_plan": [C.c_int64, ip, C.c_int32, ip, ip, C.c_int64],
+        "mech_bind_cable": [vp, ip, vp, C.c_int32, vp, C.c_size_t],
         "mech_set_params": [vp, C.c_int, C.c_char_p, dp, C.c_int64],
         "mech_set_global": [vp, C.c_char_p, C.c_double],
         "mech_init": [vp],
@@ -180,16 +182,18 @@ class Mechanisms:
         for t, a in zip(self.clamp, (off, amp, freq, phase)):
             t.copy_(self.torch.as_tensor(np.asarray(a, dtype=np.float64)).to(self.device))
 
-    def bind_cable(self, parent, g_axial):
+    def bind_cable(self, parent, g_axial, unit_nodes: int = 0):
         """Cell trees for the cable mode: parent (-1 at roots, Hines order,
-        contiguous cells) and axial conductances in uS."""
+        contiguous cells) and axial conductances in uS.  unit_nodes bounds
+        the subtree one workgroup solves (0: the device's LDS capacity)."""
         par = np.ascontiguousarray(parent, dtype=np.int32)
         nbytes = C.c_size_t(0)
         ip = C.POINTER(C.c_int32)
-        self._check(self.L.mech_cable_required_bytes(self.n_nodes, par.ctypes.data_as(ip), C.byref(nbytes)), None)
+        self._check(self.L.mech_cable_required_bytes(self.n_nodes, par.ctypes.data_as(ip), int(unit_nodes),
+                                                     C.byref(nbytes)), None)
         self.cable_buf = self.torch.empty(max(int(nbytes.value), 256), dtype=self.torch.uint8, device=self.device)
         self.g_axial = self.torch.as_tensor(np.asarray(g_axial, dtype=np.float64)).to(self.device)
-        self._check(self.L.mech_bind_cable(self.ctx, par.ctypes.data_as(ip), _ptr(self.g_axial),
+        self._check(self.L.mech_bind_cable(self.ctx, par.ctypes.data_as(ip), _ptr(self.g_axial), int(unit_nodes),
                                            self.cable_buf.data_ptr(), int(nbytes.value)))
 
     def set_params(self, slot: int, name: str, values):
@@ -305,10 +309,37 @@ def probe_stream(op: str = "copy", nbytes: int = 1 << 32, unroll: int = 4, block
     return moved / ts[len(ts) // 2] / 1e9
 
 
-def from_workload(w, prec: str = "fp64", init: bool = True) -> Mechanisms:
+PLAN_ARRAYS = ("parent", "pos_node", "pos_par", "pos_src", "elim_n", "elim_p", "elim_ptr", "unit_pos",
+               "unit_elim", "unit_mode", "list_up", "list_top", "list_top_g", "list_down")
+
+
+def cable_plan(parent, unit_nodes: int = 0) -> Dict[str, np.ndarray]:
+    """The cut of the cell trees that bind_cable makes (mech_cable_plan),
+    as host arrays by name; host only."""
+    L = load_library()
+    par = np.ascontiguousarray(parent, dtype=np.int32)
+    ip = C.POINTER(C.c_int32)
+    sizes = np.zeros(len(PLAN_ARRAYS), dtype=np.int32)
+    rc = L.mech_cable_plan(par.shape[0], par.ctypes.data_as(ip), int(unit_nodes), sizes.ctypes.data_as(ip), None, 0)
+    if rc != OK:
+        raise MechError(rc, L.mech_last_error(None).decode())
+    buf = np.zeros(max(int(sizes.sum()), 1), dtype=np.int32)
+    rc = L.mech_cable_plan(par.shape[0], par.ctypes.data_as(ip), int(unit_nodes), sizes.ctypes.data_as(ip),
+                           buf.ctypes.data_as(ip), buf.shape[0])
+    if rc != OK:
+        raise MechError(rc, L.mech_last_error(None).decode())
+    out, k = {}, 0
+    for name, n in zip(PLAN_ARRAYS, sizes):
+        out[name] = buf[k:k + n].copy()
+        k += n
+    return out
+
+
+def from_workload(w, prec: str = "fp64", init: bool = True, unit_nodes: int = 0) -> Mechanisms:
     """Build a context from a workload (paper_1905_02241_amd.workloads):
-    node index, parameters, globals, node arrays; v = v_init everywhere and,
-    if `init`, every STATE at its steady state there."""
+    node index, parameters, globals, node arrays (and cell trees, cut into
+    units of at most unit_nodes, 0 for the device's capacity); v = v_init
+    everywhere and, if `init`, every STATE at its steady state there."""
     m = Mechanisms(w.n_nodes, [(s.kind, s.node) for s in w.slots], prec=prec)
     m.set_globals(w.globals)
     for i, s in enumerate(w.slots):
@@ -321,7 +352,7 @@ def from_workload(w, prec: str = "fp64", init: bool = True) -> Mechanisms:
     if w.clamp_off is not None:
         m.set_clamp(w.clamp_off, w.clamp_amp, w.clamp_freq, w.clamp_phase)
     if getattr(w, "parent", None) is not None:
-        m.bind_cable(w.parent, w.g_axial)
+        m.bind_cable(w.parent, w.g_axial, unit_nodes)
     m.v.fill_(float(w.v_init))
     if init:
         m.init()

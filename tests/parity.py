@@ -35,9 +35,9 @@ def log(msg: str):
     sys.stdout.flush()
 
 
-def run_gpu(w, nsteps, path="batched", prec="fp64", k0=0, launch=None, vmode=None):
+def run_gpu(w, nsteps, path="batched", prec="fp64", k0=0, launch=None, vmode=None, unit_nodes=0):
     from paper_1905_02241_amd import mech
-    m = mech.from_workload(w, prec)
+    m = mech.from_workload(w, prec, unit_nodes=unit_nodes)
     if launch is not None:
         m.set_launch(*launch)
     m.step(nsteps, k0, w.dt, vmode or w.vmode, path)

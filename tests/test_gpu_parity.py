@@ -8,7 +8,7 @@ section 8 / Table 3 (current update, state update, "other").
 import numpy as np
 import pytest
 
-from paper_1905_02241_amd import workloads as W
+from paper_1905_02241_amd import mech, workloads as W
 from tests.parity import (Timer, compare_nodes, compare_states, log, run_gpu, run_oracle)
 
 pytestmark = pytest.mark.gpu
@@ -395,6 +395,47 @@ def test_cable_cells_fp64(path):
     assert np.array_equal(got["spikes"], M.spikes)
     compare_states(got, M, "fp64", label="cable")
     compare_nodes(got, M, "fp64", label="cable")
+
+
+@pytest.mark.parametrize("unit_nodes", [1, 7, 64])
+def test_cable_cut_cells_fp64(unit_nodes):
+    """The same cells cut into subtrees of at most unit_nodes nodes, packed
+    forests of pieces and trunks (a trunk above the bound runs with its rows
+    in global memory): the same elimination up to rounding."""
+    w = W.make_cells(51, n_cells=6, lo=40, hi=400, kinds=("pas", "hh", "cahva", "syn"), nsteps=400)
+    plan = mech.cable_plan(w.parent, unit_nodes)
+    modes = np.bincount(plan["unit_mode"], minlength=3)
+    log(f"cable cut {unit_nodes}: units full/piece/top {modes.tolist()}, "
+        f"trunks in global memory {plan['list_top_g'].shape[0]}")
+    assert modes[1] > 0 and modes[2] > 0
+    got, m = run_gpu(w, 400, "batched", "fp64", unit_nodes=unit_nodes)
+    M = run_oracle(w, 400)
+    assert np.array_equal(got["spikes"], M.spikes)
+    compare_states(got, M, "fp64", label=f"cable cut {unit_nodes}")
+    compare_nodes(got, M, "fp64", label=f"cable cut {unit_nodes}")
+
+
+def test_cable_long_chain_trunk_fp64():
+    """A branched cell and one unbranched cable of 3000 compartments, cut at
+    50 nodes: the cable's trunk (2950 nodes, more heights than the LDS level
+    table holds) is solved in global memory beside pieces in LDS."""
+    rng = np.random.default_rng(54)
+    pc, ac, gc = W.random_cell(rng, 300, 0)
+    n = 3000
+    w = W.make_tiny(54, kinds=("pas", "hh"), n_nodes=300 + n, vmode="cable", nsteps=100, shuffle=False)
+    chain = np.arange(299, 299 + n, dtype=np.int32)
+    chain[0] = -1
+    w.parent = np.concatenate([pc, chain])
+    w.area = np.concatenate([ac, rng.uniform(100.0, 300.0, n)])
+    w.g_axial = np.concatenate([gc, rng.uniform(0.05, 0.3, n)])
+    w.g_axial[w.parent < 0] = 0.0
+    w.cm = np.ones(w.n_nodes)
+    plan = mech.cable_plan(w.parent, 50)
+    assert plan["list_top_g"].shape[0] == 1
+    got, m = run_gpu(w, 100, "plain", "fp64", unit_nodes=50)
+    M = run_oracle(w, 100)
+    compare_states(got, M, "fp64", label="cable chain")
+    compare_nodes(got, M, "fp64", label="cable chain")
 
 
 @pytest.mark.parametrize("path", PATHS)
