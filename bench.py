@@ -44,7 +44,7 @@ def node_bytes(w) -> int:
     b = 8 + 8 + 8 + 8            # v read, v written, rhs written, d written
     if w.area is not None and any(s.kind == "syn" for s in w.slots):
         b += 8
-    if w.vmode == "isolated":
+    if w.vmode in ("isolated", "cable"):
         b += 8                   # cm
     if w.vmode == "clamp":
         b += 32                  # clamp waveform (off, amp, freq, phase)
@@ -137,7 +137,17 @@ def cpu_baseline(w, target_s: float, nodes: int):
     from oracle import oracle as O
     from paper_1905_02241_amd import workloads as W
     rng = np.random.default_rng(7)
-    sub, _ = W.subset(w, rng.choice(w.n_nodes, size=min(nodes, w.n_nodes), replace=False))
+    if w.vmode == "cable":
+        # whole cells (the tree solve couples a cell's nodes), drawn until the sample is full
+        pick, total = [], 0
+        for c in rng.permutation(len(w.cell_sizes)):
+            if total and total + int(w.cell_sizes[c]) > nodes:
+                continue
+            pick.append(int(c))
+            total += int(w.cell_sizes[c])
+        sub, _ = W.cells_subset(w, pick)
+    else:
+        sub, _ = W.subset(w, rng.choice(w.n_nodes, size=min(nodes, w.n_nodes), replace=False))
     M = O.Model(sub)
     M.init()
     t = time.perf_counter()
@@ -216,6 +226,9 @@ def main():
     ap.add_argument("--cpu-nodes", type=int, default=20000)
     ap.add_argument("--precision-report", type=int, default=0, metavar="NODES",
                     help="instead of timing: per-state error of FP64 and FP32-mixed vs the oracle on a node sample")
+    ap.add_argument("--vmode", default=None, choices=("clamp", "isolated", "cable"),
+                    help="voltage provision instead of the workload's own (cable needs a workload with cell "
+                         "trees, config 4)")
     ap.add_argument("--launch", default=None,
                     help="fixed batched launch shape 'block,tile_instances,tile_nodes,blocks_per_cu' (no autotune)")
     args = ap.parse_args()
@@ -235,7 +248,16 @@ def main():
 
     t0 = time.perf_counter()
     w = W.make_config(args.config, scale=args.scale)
-    log(f"workload {w.name}: {w.n_nodes} nodes, {w.instance_counts()}, built in {time.perf_counter() - t0:.1f}s")
+    if args.vmode:
+        if args.vmode == "cable" and getattr(w, "parent", None) is None:
+            print(f"workload {w.name} has no cell trees for the cable mode", file=sys.stderr)
+            sys.exit(2)
+        if args.vmode == "clamp" and w.clamp_off is None:
+            print(f"workload {w.name} has no clamp waveform", file=sys.stderr)
+            sys.exit(2)
+        w.vmode = args.vmode
+    log(f"workload {w.name}: {w.n_nodes} nodes, {w.instance_counts()}, vmode {w.vmode}, "
+        f"built in {time.perf_counter() - t0:.1f}s")
 
     if args.precision_report:
         rep = precision_report(w, args.steps, args.precision_report, torch, mech)
@@ -275,7 +297,7 @@ def main():
                    "dt_ms": w.dt, "vmode": w.vmode, "path": head_key, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(w, prec),
-                     "kernel": "k_fused (state+cur, isolated)",
+                     "kernel": f"k_fused (state+cur, {w.vmode})",
                      "alg_bytes_per_launch": head["alg_bytes_per_step"],
                      "copy_probe_GBps": probe,
                      "frac_of_copy_probe": (achieved / probe) if probe else None},
