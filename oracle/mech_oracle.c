@@ -25,6 +25,8 @@
  *   kmarkov  three-state C1-C2-O potassium scheme, implicit Euler (sparse)
  *   capump   Ca-HVA gates with a pool emptied by a saturable pump, implicit
  *            Euler solved by Newton's method (derivimplicit)
+ *   shared_ca  calcium as a per-node ion (USEION, section 3): the calcium
+ *            currents of all instances on a node feed one pool per node
  */
 #include "mech_oracle.h"
 
@@ -216,9 +218,15 @@ uint64_t orc_event_threshold(double rate_hz, double dt) {
 }
 
 /* ------------------------------------------------------------- current -- */
+/* The calcium concentration a cahva or capump instance sees: its own pool,
+ * or under shared_ca its node's.                                           */
+static double ca_conc(const orc_globals *gl, const orc_nodes *nd, const orc_slot *s, int64_t i) {
+    return (gl->shared_ca && nd && nd->cai) ? nd->cai[s->node[i]] : s->st[2][i];
+}
+
 /* Current of one instance at potential v with every STATE frozen:
  * density mechanisms in mA/cm2, the synapse in nA.                         */
-static double instance_i(const orc_globals *gl, const orc_slot *s, int64_t i, double v) {
+static double instance_i(const orc_globals *gl, const orc_nodes *nd, const orc_slot *s, int64_t i, double v) {
     switch (s->kind) {
     case ORC_PAS:
         return s->par[0][i] * (v - s->par[1][i]);
@@ -233,7 +241,7 @@ static double instance_i(const orc_globals *gl, const orc_slot *s, int64_t i, do
     case ORC_CAHVA:
     case ORC_CAPUMP: {
         double m = s->st[0][i], h = s->st[1][i];
-        double eca = orc_nernst_ca(s->st[2][i], gl->cao, gl->celsius);
+        double eca = orc_nernst_ca(ca_conc(gl, nd, s, i), gl->cao, gl->celsius);
         return s->par[0][i] * m * m * h * (v - eca);
     }
     case ORC_KMARKOV:
@@ -279,14 +287,14 @@ static double instance_g(const orc_globals *gl, const orc_slot *s, int64_t i, do
     return 0.0;
 }
 
-void orc_instance_current(const orc_globals *gl, const orc_slot *s, int64_t i,
+void orc_instance_current(const orc_globals *gl, const orc_nodes *nd, const orc_slot *s, int64_t i,
                           double v, double *cur, double *cond) {
-    double i0 = instance_i(gl, s, i, v);
+    double i0 = instance_i(gl, nd, s, i, v);
     *cur = i0;
     if (gl->analytic_conductance) {
         *cond = instance_g(gl, s, i, v);
     } else {
-        double i1 = instance_i(gl, s, i, v + gl->fd_dv);
+        double i1 = instance_i(gl, nd, s, i, v + gl->fd_dv);
         *cond = (i1 - i0) / gl->fd_dv;
     }
 }
@@ -331,6 +339,10 @@ void orc_init(const orc_globals *gl, orc_nodes *nd, orc_slot *slots, int nslots)
     }
     if (nd->spikes)
         for (int64_t n = 0; n < nd->n_nodes; ++n) nd->spikes[n] = 0;
+    if (nd->cai)
+        for (int64_t n = 0; n < nd->n_nodes; ++n) nd->cai[n] = gl->cai0;
+    if (nd->ica)
+        for (int64_t n = 0; n < nd->n_nodes; ++n) nd->ica[n] = 0.0;
 }
 
 void orc_events(const orc_globals *gl, orc_slot *slots, int nslots, int64_t k, double dt) {
@@ -354,14 +366,20 @@ void orc_events(const orc_globals *gl, orc_slot *slots, int nslots, int64_t k, d
 }
 
 void orc_cur(const orc_globals *gl, orc_nodes *nd, orc_slot *slots, int nslots) {
+    const int shared = gl->shared_ca && nd->cai && nd->ica;
     for (int64_t n = 0; n < nd->n_nodes; ++n) { nd->rhs[n] = 0.0; nd->d[n] = 0.0; }
+    if (shared)
+        for (int64_t n = 0; n < nd->n_nodes; ++n) nd->ica[n] = 0.0;
     for (int s = 0; s < nslots; ++s) {
         orc_slot *sl = &slots[s];
         for (int64_t i = 0; i < sl->n; ++i) {
             int32_t ni = sl->node[i];
             double I0, g;
-            orc_instance_current(gl, sl, i, nd->v[ni], &I0, &g);
-            if ((sl->kind == ORC_CAHVA || sl->kind == ORC_CAPUMP) && sl->ica) sl->ica[i] = I0;
+            orc_instance_current(gl, nd, sl, i, nd->v[ni], &I0, &g);
+            if (sl->kind == ORC_CAHVA || sl->kind == ORC_CAPUMP) {
+                if (sl->ica) sl->ica[i] = I0;
+                if (shared) nd->ica[ni] += I0;   /* the node's calcium current */
+            }
             if (sl->kind == ORC_SYN) {
                 /* nA/um2 -> mA/cm2 and uS/um2 -> S/cm2: both a factor 100 */
                 double sc = 1e2 / nd->area[ni];
@@ -454,6 +472,7 @@ static double cnexp(const orc_globals *gl, double x, double xinf, double tau, do
 
 void orc_state(const orc_globals *gl, orc_nodes *nd, orc_slot *slots, int nslots, double dt) {
     double kappa = orc_ca_kappa(gl->ca_gamma, gl->ca_depth);
+    const int shared = gl->shared_ca && nd->cai && nd->ica;
     for (int s = 0; s < nslots; ++s) {
         orc_slot *sl = &slots[s];
         for (int64_t i = 0; i < sl->n; ++i) {
@@ -476,15 +495,17 @@ void orc_state(const orc_globals *gl, orc_nodes *nd, orc_slot *slots, int nslots
                 sl->st[1][i] = cnexp(gl, sl->st[1][i], o[1], o[3], dt);
                 /* linear in cai with ica held at its stored value:
                  * cai_inf = cai0 - kappa*tau_ca*ica, time constant tau_ca   */
-                double cinf = gl->cai0 - kappa * gl->tau_ca * sl->ica[i];
-                sl->st[2][i] = cnexp(gl, sl->st[2][i], cinf, gl->tau_ca, dt);
+                if (!shared) {
+                    double cinf = gl->cai0 - kappa * gl->tau_ca * sl->ica[i];
+                    sl->st[2][i] = cnexp(gl, sl->st[2][i], cinf, gl->tau_ca, dt);
+                }
                 break;
             }
             case ORC_CAPUMP: {
                 orc_cahva_inf_tau(v, o);
                 sl->st[0][i] = cnexp(gl, sl->st[0][i], o[0], o[2], dt);
                 sl->st[1][i] = cnexp(gl, sl->st[1][i], o[1], o[3], dt);
-                orc_capump_step(gl, sl->ica[i], dt, &sl->st[2][i], gl->newton_iters);
+                if (!shared) orc_capump_step(gl, sl->ica[i], dt, &sl->st[2][i], gl->newton_iters);
                 break;
             }
             case ORC_KMARKOV: {
@@ -504,6 +525,13 @@ void orc_state(const orc_globals *gl, orc_nodes *nd, orc_slot *slots, int nslots
             }
         }
     }
+    /* one pool per node, driven by the node's total calcium current: the same
+     * linear law as a cahva instance's own pool                             */
+    if (shared)
+        for (int64_t n = 0; n < nd->n_nodes; ++n) {
+            double cinf = gl->cai0 - kappa * gl->tau_ca * nd->ica[n];
+            nd->cai[n] = cnexp(gl, nd->cai[n], cinf, gl->tau_ca, dt);
+        }
 }
 
 int orc_run(const orc_globals *gl, orc_nodes *nd, orc_slot *slots, int nslots,

@@ -87,6 +87,11 @@ typedef struct {
      * solve its implicit Euler equation (section 5.2, derivimplicit).        */
     double pump_vmax, pump_kp;
     int32_t newton_iters;
+    /* shared_ca: calcium is a per-node ion (USEION ca, section 3): every
+     * cahva and capump instance reads its node's cai and adds its ica to the
+     * node's total, and one pool per node relaxes by the linear pool law
+     * from that total (the instances' own pools are not used).              */
+    int32_t shared_ca;
 } orc_globals;
 
 typedef struct {
@@ -102,6 +107,9 @@ typedef struct {
      * between node n and its parent.                                        */
     const int32_t *parent;
     const double *g_axial;
+    /* shared_ca: the node's calcium concentration (mM) and total calcium
+     * current density (mA/cm2) of the last current update.                  */
+    double *cai, *ica;
 } orc_nodes;
 
 /* ---- single-point functions (used by the pins) ----------------------- */
@@ -127,8 +135,10 @@ double orc_nernst_ca(double cai, double cao, double celsius);     /* mV      */
 double orc_ca_kappa(double gamma, double depth);   /* mM/ms per mA/cm2      */
 uint64_t orc_event_hash(uint64_t seed, int64_t gid, int64_t k);
 uint64_t orc_event_threshold(double rate_hz, double dt);
-/* current of one instance at v with frozen states: *i = I(v), *g = FD di/dv */
-void orc_instance_current(const orc_globals *gl, const orc_slot *s, int64_t i,
+/* current of one instance at v with frozen states: *i = I(v), *g = di/dv
+ * (finite difference, or closed form under analytic_conductance); nd gives
+ * the node's cai under shared_ca and may be NULL otherwise                  */
+void orc_instance_current(const orc_globals *gl, const orc_nodes *nd, const orc_slot *s, int64_t i,
                           double v, double *cur, double *cond);
 
 /* ---- phases and the full step loop ------------------------------------ */

@@ -47,13 +47,14 @@ FLAG_FIELDS = ("analytic_conductance", "pade_cnexp")
 class _Globals(C.Structure):
     _fields_ = ([(f, C.c_double) for f in GLOBAL_FIELDS] + [("event_seed", C.c_uint64)] +
                 [(f, C.c_int32) for f in FLAG_FIELDS] +
-                [("pump_vmax", C.c_double), ("pump_kp", C.c_double), ("newton_iters", C.c_int32)])
+                [("pump_vmax", C.c_double), ("pump_kp", C.c_double), ("newton_iters", C.c_int32),
+                 ("shared_ca", C.c_int32)])
 
 
 class _Nodes(C.Structure):
     _fields_ = [("n_nodes", C.c_int64), ("v", _dp), ("rhs", _dp), ("d", _dp), ("area", _dp), ("cm", _dp),
                 ("clamp_off", _dp), ("clamp_amp", _dp), ("clamp_freq", _dp), ("clamp_phase", _dp),
-                ("spikes", _ip), ("parent", _ip), ("g_axial", _dp)]
+                ("spikes", _ip), ("parent", _ip), ("g_axial", _dp), ("cai", _dp), ("ica", _dp)]
 
 
 def build(force: bool = False) -> str:
@@ -96,7 +97,8 @@ def lib():
         L.orc_kmarkov_step.argtypes = [C.c_double, C.c_double, C.c_double, _dp]
         L.orc_capump_step.argtypes = [C.POINTER(_Globals), C.c_double, C.c_double, _dp, C.c_int]
         L.orc_capump_step.restype = C.c_double
-        L.orc_instance_current.argtypes = [C.POINTER(_Globals), C.POINTER(_Slot), C.c_int64, C.c_double, _dp, _dp]
+        L.orc_instance_current.argtypes = [C.POINTER(_Globals), C.POINTER(_Nodes), C.POINTER(_Slot), C.c_int64,
+                                           C.c_double, _dp, _dp]
         sig = [C.POINTER(_Globals), C.POINTER(_Nodes), C.POINTER(_Slot), C.c_int]
         L.orc_init.argtypes = sig
         L.orc_cur.argtypes = sig
@@ -183,7 +185,8 @@ class Model:
     """Owns FP64 copies of one workload's arrays and runs the oracle on them.
 
     ``states[s][name]`` are the STATE arrays of slot s in the caller's
-    instance order; ``v``, ``rhs``, ``d``, ``spikes`` are node arrays."""
+    instance order; ``v``, ``rhs``, ``d``, ``spikes`` and, under shared_ca,
+    ``cai`` and ``ica`` are node arrays."""
 
     def __init__(self, w):
         self.w = w
@@ -230,9 +233,12 @@ class Model:
         self.g_axial = f64(getattr(w, "g_axial", None))
         if self.parent is not None and self.parent.size and np.any(self.parent >= np.arange(n)):
             raise ValueError("parent[n] must be < n (Hines order)")
+        # per-node calcium (shared_ca): concentration and total current
+        self.cai = np.full(n, float(self.globals["cai0"]))
+        self.ica = np.zeros(n)
         self._nodes = _Nodes(n, _ptr(self.v), _ptr(self.rhs), _ptr(self.d), _ptr(self.area), _ptr(self.cm),
                              *[_ptr(a) for a in self.clamp], _ptr(self.spikes, _ip),
-                             _ptr(self.parent, _ip), _ptr(self.g_axial))
+                             _ptr(self.parent, _ip), _ptr(self.g_axial), _ptr(self.cai), _ptr(self.ica))
         self._g = self._make_globals()
 
     def _make_globals(self):
@@ -245,6 +251,7 @@ class Model:
         g.pump_vmax = float(self.globals.get("pump_vmax", 1e-4))
         g.pump_kp = float(self.globals.get("pump_kp", 1e-3))
         g.newton_iters = int(self.globals.get("newton_iters", 4))
+        g.shared_ca = int(self.globals.get("shared_ca", 0))
         return g
 
     def set_global(self, name, value):
@@ -297,5 +304,6 @@ class Model:
 
     def instance_current(self, s: int, i: int, v: float):
         cur, cond = C.c_double(), C.c_double()
-        lib().orc_instance_current(C.byref(self._g), C.byref(self._slots[s]), i, v, C.byref(cur), C.byref(cond))
+        lib().orc_instance_current(C.byref(self._g), C.byref(self._nodes), C.byref(self._slots[s]), i, v,
+                                   C.byref(cur), C.byref(cond))
         return cur.value, cond.value

@@ -77,6 +77,7 @@ DEFAULT_GLOBALS = {
     "pump_vmax": 1e-4,           # capump: maximal pump rate (mM/ms)
     "pump_kp": 1e-3,             # capump: pump half-activation (mM)
     "newton_iters": 4,           # capump: Newton steps per implicit Euler step
+    "shared_ca": 0,              # 1: calcium is a per-node ion shared by the cahva/capump instances of a node
 }
 
 VMODES = ("external", "clamp", "isolated", "cable")

@@ -686,3 +686,76 @@ def test_cable_spreads_current_along_the_tree(oracle):
     dv = np.array([(r[0] * a[1, 1] - a[0, 1] * r[1]) / det, (a[0, 0] * r[1] - a[1, 0] * r[0]) / det])
     M.vcable()
     assert np.allclose(M.v, np.array([-65.0, -20.0]) + dv, rtol=0, atol=1e-12)
+
+
+# ------------------------------------ per-node calcium ion, USEION (F4) --
+def _ca_mesh(seed, kinds, per_node, vmode, gbar=None, frac=0.7):
+    w = W.make_tiny(seed, kinds=kinds, n_nodes=60, per_node=per_node, vmode=vmode, nsteps=300,
+                    shuffle=False, density_fraction=frac)
+    if gbar is not None:
+        for s in w.slots:
+            if s.kind in ("cahva", "capump"):
+                s.params["gbar"][:] = gbar(s.n)
+    return w
+
+
+def _run(oracle, w, shared, nsteps=300):
+    w.globals["shared_ca"] = shared
+    M = oracle.Model(w)
+    M.init()
+    M.run(0, nsteps)
+    return M
+
+
+def test_shared_calcium_with_one_channel_per_node_is_the_own_pool(oracle):
+    """One Ca-HVA instance per node: the node's pool sees exactly that
+    instance's current (0 + ica), so the shared ion reproduces the
+    per-instance pool bit for bit; nodes without a calcium channel keep
+    cai0 exactly."""
+    w = _ca_mesh(81, ("pas", "hh", "cahva"), 1, "isolated")
+    own = _run(oracle, w, 0)
+    shared = _run(oracle, w, 1)
+    s = [i for i, sl in enumerate(w.slots) if sl.kind == "cahva"][0]
+    node = w.slots[s].node
+    assert np.array_equal(own.v, shared.v)
+    assert np.array_equal(own.states[s]["m"], shared.states[s]["m"])
+    assert np.array_equal(own.states[s]["cai"], shared.cai[node])
+    rest = np.setdiff1d(np.arange(w.n_nodes), node)
+    assert rest.size > 0 and np.all(shared.cai[rest] == w.globals["cai0"])
+    assert np.all(shared.cai[node] != w.globals["cai0"])
+
+
+def test_shared_calcium_sums_channels_on_a_node(oracle):
+    """Two Ca-HVA instances with equal gates on a node (same v, same initial
+    state) and conductances g1, g2 feed one pool: the same as one instance of
+    g1 + g2, up to the rounding of the split product.  Without the shared ion
+    each instance's own pool sees half the influx, a different result."""
+    import copy
+    two = _ca_mesh(82, ("cahva",), 2, "clamp")
+    node = two.slots[0].node
+    assert np.array_equal(node[::2], node[1::2])
+    g = two.slots[0].params["gbar"]
+    one = copy.deepcopy(two)
+    one.slots[0] = W._slot("cahva", node[::2].copy(), {"gbar": g[::2] + g[1::2]})
+    a = _run(oracle, two, 1)
+    b = _run(oracle, one, 1)
+    assert np.allclose(a.cai, b.cai, rtol=1e-12, atol=0.0)
+    assert np.allclose(a.rhs, b.rhs, rtol=1e-12, atol=1e-18)
+    own = _run(oracle, two, 0)
+    assert np.max(np.abs(own.states[0]["cai"] - a.cai[node]) / a.cai[node]) > 1e-3
+
+
+def test_shared_calcium_capump_channel_feeds_the_linear_pool(oracle):
+    """Under the shared ion a capump instance contributes its channel current
+    (the Ca-HVA gates and current) and the node's pool follows the linear
+    law: one capump per node then equals Ca-HVA with its own pool exactly."""
+    wa = _ca_mesh(83, ("pas", "capump"), 1, "isolated")
+    wb = _ca_mesh(83, ("pas", "cahva"), 1, "isolated")
+    for s in wb.slots:
+        if s.kind == "cahva":
+            s.params["gbar"][:] = [x for x in wa.slots if x.kind == "capump"][0].params["gbar"]
+    a = _run(oracle, wa, 1)
+    b = _run(oracle, wb, 0)
+    sb = [i for i, sl in enumerate(wb.slots) if sl.kind == "cahva"][0]
+    assert np.array_equal(a.v, b.v)
+    assert np.array_equal(a.cai[wb.slots[sb].node], b.states[sb]["cai"])
