@@ -209,12 +209,23 @@ int mech_set_params(mech_ctx *ctx, int type_slot, const char *name, const double
  *                         (1,1) Pade approximant (1 - y/2)/(1 + y/2),
  *                         y = dt/tau (requires y < 2 to keep gates in
  *                         [0, 1]);
- * and the pump of MECH_CAPUMP: pump_vmax (mM/ms), pump_kp (mM),
- * newton_iters (1..16 Newton steps per implicit Euler step, default 4).    */
+ * the pump of MECH_CAPUMP: pump_vmax (mM/ms), pump_kp (mM),
+ * newton_iters (1..16 Newton steps per implicit Euler step, default 4);
+ * and shared_ca (0 or 1, default 0): calcium as a per-node ion, the USEION
+ * dependency between mechanisms (section 3).  Every MECH_CAHVA and
+ * MECH_CAPUMP instance then reads its node's cai and adds its calcium
+ * current to the node's total ica; one pool per node relaxes by the linear
+ * pool law, cai_inf = cai0 - kappa tau_ca ica with time constant tau_ca,
+ * from that total; the instances' own pools are left untouched.  Needs a
+ * calcium type (MECH_ERR_STATE otherwise); set it before mech_init, which
+ * sets every node's cai to cai0.  The node arrays are read with
+ * mech_get_state(ctx, -1, "cai" or "ica", ...).  Changing a global drops
+ * the captured step graphs (rebuilt on the next batched step).             */
 int mech_set_global(mech_ctx *ctx, const char *name, double value);
 
 /* INITIAL (section 3): every gate at its steady state x_inf(v) at the bound
- * v, synapse states 0, cai = cai0; spike counts 0.                         */
+ * v, synapse states 0, cai = cai0 (each instance's and each node's), ica =
+ * 0; spike counts 0.                                                       */
 int mech_init(mech_ctx *ctx);
 
 /* Current update of step k (t = k*dt): synapse events of step k, then
@@ -249,12 +260,16 @@ int mech_get_launch(const mech_ctx *ctx, int *block, int *tile_instances, int *t
 
 /* Time every candidate launch shape of the BATCHED path on `nsteps` steps
  * (HIP events, median of `reps`), keep the fastest, and return its ms per
- * step.  STATEs, v, rhs, d and spike counts are saved before and restored
- * after, so the call has no visible effect besides the chosen shape.      */
+ * step.  STATEs, v, rhs, d, spike counts and the per-node calcium ion are
+ * saved before and restored after, so the call has no visible effect
+ * besides the chosen shape.                                                */
 int mech_autotune(mech_ctx *ctx, double dt, int vmode, int nsteps, int reps, double *best_ms_per_step);
 
 /* Copy STATE `name` (or "ica" for Ca-HVA and capump) of type slot `type_slot` to /
- * from host doubles in the caller's instance order; n must equal count.   */
+ * from host doubles in the caller's instance order; n must equal count.
+ * type_slot -1 names the per-node calcium ion instead: "cai" (mM) or "ica"
+ * (mA/cm2, the last current update's total), n == n_nodes, present when a
+ * calcium type exists (MECH_ERR_INVAL otherwise).                          */
 int mech_get_state(mech_ctx *ctx, int type_slot, const char *name, double *host_out, int64_t n);
 int mech_set_state(mech_ctx *ctx, int type_slot, const char *name, const double *host_in, int64_t n);
 

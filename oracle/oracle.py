@@ -185,8 +185,9 @@ class Model:
     """Owns FP64 copies of one workload's arrays and runs the oracle on them.
 
     ``states[s][name]`` are the STATE arrays of slot s in the caller's
-    instance order; ``v``, ``rhs``, ``d``, ``spikes`` and, under shared_ca,
-    ``cai`` and ``ica`` are node arrays."""
+    instance order, ``ica[s]`` the calcium current of each instance of a
+    calcium slot; ``v``, ``rhs``, ``d``, ``spikes`` and, under shared_ca,
+    ``cai_node`` and ``ica_node`` are node arrays."""
 
     def __init__(self, w):
         self.w = w
@@ -234,11 +235,12 @@ class Model:
         if self.parent is not None and self.parent.size and np.any(self.parent >= np.arange(n)):
             raise ValueError("parent[n] must be < n (Hines order)")
         # per-node calcium (shared_ca): concentration and total current
-        self.cai = np.full(n, float(self.globals["cai0"]))
-        self.ica = np.zeros(n)
+        self.cai_node = np.full(n, float(self.globals["cai0"]))
+        self.ica_node = np.zeros(n)
         self._nodes = _Nodes(n, _ptr(self.v), _ptr(self.rhs), _ptr(self.d), _ptr(self.area), _ptr(self.cm),
                              *[_ptr(a) for a in self.clamp], _ptr(self.spikes, _ip),
-                             _ptr(self.parent, _ip), _ptr(self.g_axial), _ptr(self.cai), _ptr(self.ica))
+                             _ptr(self.parent, _ip), _ptr(self.g_axial), _ptr(self.cai_node),
+                             _ptr(self.ica_node))
         self._g = self._make_globals()
 
     def _make_globals(self):

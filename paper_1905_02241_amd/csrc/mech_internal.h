@@ -55,6 +55,7 @@ struct GlobDev {
     double kappa;              // calcium influx per unit current, mM/ms per mA/cm2
     double pump_vmax, pump_kp, pump_rest;   // pump_rest = vmax cai0/(cai0 + kp)
     int newton_iters;
+    int shared_ca;             // calcium as a per-node ion (NodesDev::cai, ica)
 };
 
 struct NodesDev {
@@ -63,11 +64,12 @@ struct NodesDev {
     const double *c_off, *c_amp, *c_freq, *c_phase;
     int *spikes;
     int n_nodes;
+    // per-node calcium ion (library region; null without a calcium type):
+    // concentration (mM) and the total calcium current density (mA/cm2) of
+    // the last current update, used when GlobDev::shared_ca is set
+    double *cai, *ica;
 };
 
-// Cell trees of the cable mode: per cell a contiguous node range, the
-// children of every node (CSR), the non-leaf nodes grouped by elimination
-// level and all nodes grouped by depth.
 // Cell trees of the cable mode, cut into units that one workgroup solves.
 // A unit is a whole cell (FULL), a forest of subtrees whose roots hang off a
 // larger cell's trunk (PIECE), or that trunk (TOP) with the piece roots as
@@ -141,7 +143,11 @@ hipError_t launch_stream(int op, int unroll, void *dst, const void *src, size_t 
 hipError_t launch_cable(const CableDev &c, const NodesDev &nd, const GlobDev &g, hipStream_t s);
 hipError_t cable_allow_lds(size_t bytes);
 hipError_t launch_cable_coeffs(const CableDev &c, const double *area, int n_nodes, int n_edges, hipStream_t s);
-hipError_t launch_fused(bool fp32, int phases, int vmode, const FusedArgs &a, int grid, int block,
-                        size_t lds_bytes, hipStream_t s);
+hipError_t launch_fused(bool fp32, int phases, int vmode, const FusedArgs &a, int grid, int block, int tile_nodes,
+                        hipStream_t s);
+size_t fused_lds_bytes(int tile_nodes, bool ion);
+hipError_t fused_allow_lds(size_t bytes);
+hipError_t launch_ion_pool(const NodesDev &nd, const GlobDev &g, int *err, hipStream_t s);
+hipError_t launch_ion_init(const NodesDev &nd, const GlobDev &g, hipStream_t s);
 
 }  // namespace mech

@@ -486,6 +486,34 @@ __device__ __forceinline__ void instance(const SlotDev &sl, int i, double v, con
     }
 }
 
+// A cahva or capump instance under the shared calcium ion: its gates, and its
+// current at the node's cai (ica returned for the node's total); the pool
+// is the node's (ion_pool), not the instance's.
+template <class S, int PH, bool NT = false>
+__device__ __forceinline__ void ca_shared(const SlotDev &sl, int i, double v, double cai, const GlobDev &g,
+                                          double &ci, double &cg, double &ica, int &flag) {
+    ci = 0.0;
+    cg = 0.0;
+    ica = 0.0;
+    S *M = (S *)sl.st[0], *H = (S *)sl.st[1], *ICA = (S *)sl.ica;
+    S m = ld<NT>(M + i), h = ld<NT>(H + i);
+    if (PH & kDoState) {
+        ca_gates(v, g, m, h);
+        flag |= bad(m) | bad(h);
+        st<NT>(M + i, m); st<NT>(H + i, h);
+    }
+    if (PH & kDoCur) {
+        const S gbar = ld<NT>((const S *)sl.par[0] + i);
+        const S ic = (S)ca_cur<S>(v, m, h, (S)cai, gbar, g, ci, cg);
+        st<NT>(ICA + i, ic);
+        ica = (double)ic;
+    }
+}
+
+// The node's calcium pool: the linear pool law driven by the node's total
+// calcium current, in FP64 for both storage types.
+__device__ __forceinline__ void ion_pool(const GlobDev &g, double ica, double &cai) { ca_pool(g, ica, cai); }
+
 // ---------------------------------------------------------- plain path --
 // Segmented inclusive sum over a wave of instances sorted by node: after the
 // log2(64) shuffle steps each lane holds the sum of its node's run up to
@@ -516,7 +544,13 @@ __global__ __launch_bounds__(256) void k_plain_cur(PlainArgs a) {
     if (i < a.slot.n) {
         ni = a.slot.ni[i];
         const double v = a.nd.v[ni];
-        instance<S, KIND, kDoCur>(a.slot, i, v, a.g, a.k, ci, cg, flag);
+        if ((KIND == MECH_CAHVA || KIND == MECH_CAPUMP) && a.g.shared_ca) {
+            double ica;
+            ca_shared<S, kDoCur>(a.slot, i, v, a.nd.cai[ni], a.g, ci, cg, ica, flag);
+            unsafeAtomicAdd(&a.nd.ica[ni], ica);
+        } else {
+            instance<S, KIND, kDoCur>(a.slot, i, v, a.g, a.k, ci, cg, flag);
+        }
         if (KIND == MECH_SYN) {
             const double sc = 1e2 / a.nd.area[ni];
             ci *= sc;
@@ -545,9 +579,30 @@ __global__ __launch_bounds__(256) void k_plain_state(PlainArgs a) {
     if (i < a.slot.n) {
         const double v = a.nd.v[a.slot.ni[i]];
         double ci, cg;
-        instance<S, KIND, kDoState>(a.slot, i, v, a.g, a.k, ci, cg, flag);
+        if ((KIND == MECH_CAHVA || KIND == MECH_CAPUMP) && a.g.shared_ca) {
+            double ica;
+            ca_shared<S, kDoState>(a.slot, i, v, 0.0, a.g, ci, cg, ica, flag);
+        } else {
+            instance<S, KIND, kDoState>(a.slot, i, v, a.g, a.k, ci, cg, flag);
+        }
     }
     if (flag) atomicOr(a.err, 1);
+}
+
+// Per-node calcium ion: pools after the gates (plain path), and INITIAL.
+__global__ void k_ion_pool(NodesDev nd, GlobDev g, int *err) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nd.n_nodes) return;
+    double c = nd.cai[n];
+    ion_pool(g, nd.ica[n], c);
+    nd.cai[n] = c;
+    if (bad(c)) atomicOr(err, 1);
+}
+__global__ void k_ion_init(NodesDev nd, double cai0) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nd.n_nodes) return;
+    nd.cai[n] = cai0;
+    nd.ica[n] = 0.0;
 }
 
 // INITIAL: gates at steady state at the bound v (computed in FP64 for both
@@ -931,16 +986,24 @@ hipError_t cable_allow_lds(size_t bytes) {
 }
 
 // ---------------------------------------------------------- fused path --
-// LDS per tile node: v, 100/area, rhs and d accumulators (4 doubles).
-template <class S, int KIND, int PH, bool NT>
+// LDS per tile node: v, 100/area, rhs and d accumulators (4 doubles); under
+// the shared calcium ion also the node's cai and its calcium current
+// accumulator (6 doubles).
+template <class S, int KIND, int PH, bool NT, bool ION>
 __device__ __forceinline__ void tile_slot(const SlotDev &sl, int lo, int hi, int nlo, const double *vl,
-                                          const double *sc, double *ar, double *ad, const GlobDev &g,
-                                          long long k, int &flag) {
+                                          const double *sc, double *ar, double *ad, const double *cl, double *ai,
+                                          const GlobDev &g, long long k, int &flag) {
     for (int i = lo + (int)threadIdx.x; i < hi; i += (int)blockDim.x) {
         // an identity slot (instance i on node i) needs no index load
         const int j = (sl.identity ? i : ld<NT>(sl.ni + i)) - nlo;
         double ci, cg;
-        instance<S, KIND, PH, NT, true>(sl, i, vl[j], g, k, ci, cg, flag);
+        if constexpr (ION && (KIND == MECH_CAHVA || KIND == MECH_CAPUMP)) {
+            double ica;
+            ca_shared<S, PH, NT>(sl, i, vl[j], cl[j], g, ci, cg, ica, flag);
+            if (PH & kDoCur) atomicAdd(&ai[j], ica);
+        } else {
+            instance<S, KIND, PH, NT, true>(sl, i, vl[j], g, k, ci, cg, flag);
+        }
         if (PH & kDoCur) {
             if (KIND == MECH_SYN) {
                 ci *= sc[j];
@@ -963,10 +1026,14 @@ __device__ __forceinline__ int tile_of(int b, int T, int xcd_order) {
     return x * q + min(x, r) + j;
 }
 
-template <class S, int PH, int VM, bool NT>
+// ION: the shared calcium ion (its own instantiations, so the others keep
+// their register budget).
+template <class S, int PH, int VM, bool NT, bool ION = false>
 __global__ __launch_bounds__(1024) void k_fused(FusedArgs a, int tn) {
     extern __shared__ double lds[];
     double *vl = lds, *sc = lds + tn, *ar = lds + 2 * tn, *ad = lds + 3 * tn;
+    double *cl = lds + 4 * tn, *ai = lds + 5 * tn;
+    constexpr bool ion = ION;
     const long long k = *a.kdev + a.kofs;
     int flag = 0;
     for (int b = blockIdx.x; b < a.n_tiles; b += gridDim.x) {
@@ -980,6 +1047,10 @@ __global__ __launch_bounds__(1024) void k_fused(FusedArgs a, int tn) {
                 ar[j] = 0.0;
                 ad[j] = 0.0;
                 if (a.has_syn) sc[j] = 1e2 / a.nd.area[nlo + j];
+                if constexpr (ion) {
+                    cl[j] = a.nd.cai[nlo + j];
+                    ai[j] = 0.0;
+                }
             }
         }
         __syncthreads();
@@ -988,14 +1059,14 @@ __global__ __launch_bounds__(1024) void k_fused(FusedArgs a, int tn) {
             const int lo = r0[1 + s], hi = r1[1 + s];
             switch (sl.kind) {
             case MECH_PAS:
-                if (PH & kDoCur) tile_slot<S, MECH_PAS, PH, NT>(sl, lo, hi, nlo, vl, sc, ar, ad, a.g, k, flag);
+                if (PH & kDoCur) tile_slot<S, MECH_PAS, PH, NT, ION>(sl, lo, hi, nlo, vl, sc, ar, ad, cl, ai, a.g, k, flag);
                 break;
-            case MECH_HH: tile_slot<S, MECH_HH, PH, NT>(sl, lo, hi, nlo, vl, sc, ar, ad, a.g, k, flag); break;
-            case MECH_IH: tile_slot<S, MECH_IH, PH, NT>(sl, lo, hi, nlo, vl, sc, ar, ad, a.g, k, flag); break;
-            case MECH_CAHVA: tile_slot<S, MECH_CAHVA, PH, NT>(sl, lo, hi, nlo, vl, sc, ar, ad, a.g, k, flag); break;
-            case MECH_SYN: tile_slot<S, MECH_SYN, PH, NT>(sl, lo, hi, nlo, vl, sc, ar, ad, a.g, k, flag); break;
-            case MECH_KMARKOV: tile_slot<S, MECH_KMARKOV, PH, NT>(sl, lo, hi, nlo, vl, sc, ar, ad, a.g, k, flag); break;
-            case MECH_CAPUMP: tile_slot<S, MECH_CAPUMP, PH, NT>(sl, lo, hi, nlo, vl, sc, ar, ad, a.g, k, flag); break;
+            case MECH_HH: tile_slot<S, MECH_HH, PH, NT, ION>(sl, lo, hi, nlo, vl, sc, ar, ad, cl, ai, a.g, k, flag); break;
+            case MECH_IH: tile_slot<S, MECH_IH, PH, NT, ION>(sl, lo, hi, nlo, vl, sc, ar, ad, cl, ai, a.g, k, flag); break;
+            case MECH_CAHVA: tile_slot<S, MECH_CAHVA, PH, NT, ION>(sl, lo, hi, nlo, vl, sc, ar, ad, cl, ai, a.g, k, flag); break;
+            case MECH_SYN: tile_slot<S, MECH_SYN, PH, NT, ION>(sl, lo, hi, nlo, vl, sc, ar, ad, cl, ai, a.g, k, flag); break;
+            case MECH_KMARKOV: tile_slot<S, MECH_KMARKOV, PH, NT, ION>(sl, lo, hi, nlo, vl, sc, ar, ad, cl, ai, a.g, k, flag); break;
+            case MECH_CAPUMP: tile_slot<S, MECH_CAPUMP, PH, NT, ION>(sl, lo, hi, nlo, vl, sc, ar, ad, cl, ai, a.g, k, flag); break;
             default: break;
             }
         }
@@ -1008,6 +1079,15 @@ __global__ __launch_bounds__(1024) void k_fused(FusedArgs a, int tn) {
                 a.nd.d[n] = dd;
                 if (VM == MECH_V_ISOLATED) a.nd.v[n] = isolated_v(a.nd, a.g, n, vl[j], r, dd);
                 if (VM == MECH_V_CLAMP) a.nd.v[n] = clamp_v(a.nd, n, (double)(k + 1) * a.g.dt);
+                if constexpr (ion) {
+                    // the node's pool advances with this step's calcium current,
+                    // as a cahva instance's own pool does in this pass
+                    double c = cl[j];
+                    ion_pool(a.g, ai[j], c);
+                    flag |= bad(c);
+                    a.nd.cai[n] = c;
+                    a.nd.ica[n] = ai[j];
+                }
             }
         }
         __syncthreads();
@@ -1153,31 +1233,69 @@ hipError_t launch_plain_state(bool fp32, const PlainArgs &a, hipStream_t s) {
     return fp32 ? state_t<float>(a, s) : state_t<double>(a, s);
 }
 
-template <class S, int PH, bool NT>
+template <class S, int PH, bool NT, bool ION>
 static hipError_t fused_vm(int vmode, const FusedArgs &a, int grid, int block, size_t lds, int tn,
                            hipStream_t s) {
     switch (vmode) {
-    case MECH_V_CLAMP: k_fused<S, PH, MECH_V_CLAMP, NT><<<grid, block, lds, s>>>(a, tn); break;
-    case MECH_V_ISOLATED: k_fused<S, PH, MECH_V_ISOLATED, NT><<<grid, block, lds, s>>>(a, tn); break;
-    default: k_fused<S, PH, MECH_V_EXTERNAL, NT><<<grid, block, lds, s>>>(a, tn); break;
+    case MECH_V_CLAMP: k_fused<S, PH, MECH_V_CLAMP, NT, ION><<<grid, block, lds, s>>>(a, tn); break;
+    case MECH_V_ISOLATED: k_fused<S, PH, MECH_V_ISOLATED, NT, ION><<<grid, block, lds, s>>>(a, tn); break;
+    default: k_fused<S, PH, MECH_V_EXTERNAL, NT, ION><<<grid, block, lds, s>>>(a, tn); break;
     }
     return hipGetLastError();
 }
-template <class S, bool NT>
+template <class S, bool NT, bool ION = false>
 static hipError_t fused_t(int phases, int vmode, const FusedArgs &a, int grid, int block, size_t lds, int tn,
                           hipStream_t s) {
     switch (phases) {
-    case kDoCur: return fused_vm<S, kDoCur, NT>(vmode, a, grid, block, lds, tn, s);
+    case kDoCur: return fused_vm<S, kDoCur, NT, ION>(vmode, a, grid, block, lds, tn, s);
     case kDoState:
-        k_fused<S, kDoState, MECH_V_EXTERNAL, NT><<<grid, block, lds, s>>>(a, tn);
+        k_fused<S, kDoState, MECH_V_EXTERNAL, NT, ION><<<grid, block, lds, s>>>(a, tn);
         return hipGetLastError();
-    default: return fused_vm<S, kDoCur | kDoState, NT>(vmode, a, grid, block, lds, tn, s);
+    default: return fused_vm<S, kDoCur | kDoState, NT, ION>(vmode, a, grid, block, lds, tn, s);
     }
 }
-hipError_t launch_fused(bool fp32, int phases, int vmode, const FusedArgs &a, int grid, int block,
-                        size_t lds_bytes, hipStream_t s) {
+size_t fused_lds_bytes(int tile_nodes, bool ion) { return (ion ? 6 : 4) * sizeof(double) * (size_t)tile_nodes; }
+
+// Lets every fused instantiation of the shared calcium ion take up to
+// `bytes` of dynamic LDS.
+hipError_t fused_allow_lds(size_t bytes) {
+    const int b = (int)bytes;
+    const void *fns[] = {
+#define MECH_FUSED_FNS(S)                                                                                       \
+    (const void *)k_fused<S, kDoState, MECH_V_EXTERNAL, false, true>,                                             \
+        (const void *)k_fused<S, kDoCur, MECH_V_EXTERNAL, false, true>,                                           \
+        (const void *)k_fused<S, kDoCur, MECH_V_CLAMP, false, true>,                                              \
+        (const void *)k_fused<S, kDoCur, MECH_V_ISOLATED, false, true>,                                           \
+        (const void *)k_fused<S, kDoCur | kDoState, MECH_V_EXTERNAL, false, true>,                                \
+        (const void *)k_fused<S, kDoCur | kDoState, MECH_V_CLAMP, false, true>,                                   \
+        (const void *)k_fused<S, kDoCur | kDoState, MECH_V_ISOLATED, false, true>
+        MECH_FUSED_FNS(double), MECH_FUSED_FNS(float)
+#undef MECH_FUSED_FNS
+    };
+    for (const void *f : fns) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_ion_pool(const NodesDev &nd, const GlobDev &g, int *err, hipStream_t s) {
+    if (nd.n_nodes > 0) k_ion_pool<<<blocks(nd.n_nodes, 256), 256, 0, s>>>(nd, g, err);
+    return hipGetLastError();
+}
+hipError_t launch_ion_init(const NodesDev &nd, const GlobDev &g, hipStream_t s) {
+    if (nd.n_nodes > 0) k_ion_init<<<blocks(nd.n_nodes, 256), 256, 0, s>>>(nd, g.cai0);
+    return hipGetLastError();
+}
+
+hipError_t launch_fused(bool fp32, int phases, int vmode, const FusedArgs &a, int grid, int block, int tn,
+                        hipStream_t s) {
     if (a.n_tiles == 0 || grid == 0) return hipSuccess;
-    const int tn = (int)(lds_bytes / (4 * sizeof(double)));
+    const size_t lds_bytes = fused_lds_bytes(tn, a.g.shared_ca != 0);
+    // the shared calcium ion has temporal-hint instantiations only
+    if (a.g.shared_ca)
+        return fp32 ? fused_t<float, false, true>(phases, vmode, a, grid, block, lds_bytes, tn, s)
+                    : fused_t<double, false, true>(phases, vmode, a, grid, block, lds_bytes, tn, s);
     if (a.nontemporal)
         return fp32 ? fused_t<float, true>(phases, vmode, a, grid, block, lds_bytes, tn, s)
                     : fused_t<double, true>(phases, vmode, a, grid, block, lds_bytes, tn, s);

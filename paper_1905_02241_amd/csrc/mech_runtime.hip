@@ -59,6 +59,7 @@ struct Globals {
     int pade_cnexp = 0;             // (1,1) Pade approximant of the cnexp exponential
     double pump_vmax = 1e-4, pump_kp = 1e-3;
     int newton_iters = 4;
+    int shared_ca = 0;              // calcium as a per-node ion
 };
 
 struct SlotHost {
@@ -286,6 +287,8 @@ struct Layout {
     size_t total = 0;
     size_t inst_end = 0;           // end of the per-instance region
     size_t off_spikes = 0, off_err = 0, off_kdev = 0, off_tiles = 0;
+    size_t off_ion = 0;            // cai and ica per node, when a calcium type exists
+    bool has_ion = false;
     int64_t max_tile_rows = 0;
 };
 
@@ -314,6 +317,9 @@ void compute_layout(int64_t n_nodes, std::vector<SlotHost> &slots, int prec, Lay
     L.off_spikes = off; off = align_up(off + 4 * (size_t)std::max<int64_t>(n_nodes, 1));
     L.off_err = off; off = align_up(off + 4);
     L.off_kdev = off; off = align_up(off + 8);
+    L.has_ion = false;
+    for (auto &s : slots) L.has_ion |= s.kind == MECH_CAHVA || s.kind == MECH_CAPUMP;
+    if (L.has_ion) { L.off_ion = off; off = align_up(off + 16 * (size_t)std::max<int64_t>(n_nodes, 1)); }
     L.max_tile_rows = 2 * ((total_inst + kMinTileBudget - 1) / kMinTileBudget) +
                       (n_nodes + kMinTileNodes - 1) / kMinTileNodes + 2;
     L.off_tiles = off;
@@ -337,6 +343,7 @@ struct mech_ctx {
     NodesDev nd{};
     CableDev cable{};
     bool nodes_bound = false, clamp_bound = false, has_syn = false, cable_bound = false;
+    bool ion_lds = false;          // fused kernels allowed the LDS of the shared calcium ion
     // fused-path launch shape and tile table
     int block = 256, tile_budget = 2048, tile_nodes = 1024, blocks_per_cu = 0, launch_flags = MECH_LAUNCH_XCD_ORDER;
     int64_t n_tiles = 0, max_tile_nodes = 0;
@@ -421,6 +428,7 @@ GlobDev make_glob(const mech_ctx *c, double dt) {
     g.pump_kp = G.pump_kp;
     g.pump_rest = G.pump_vmax * (G.cai0 / (G.cai0 + G.pump_kp));
     g.newton_iters = G.newton_iters;
+    g.shared_ca = G.shared_ca && c->nd.cai ? 1 : 0;
     g.seed = G.event_seed;
     // fire with probability p = rate*dt: draws below floor(p * 2^64)
     const double p = G.event_rate_hz * dt * 1e-3;
@@ -553,11 +561,14 @@ int launch_plain_phase(mech_ctx *c, bool cur, int64_t k, const GlobDev &g, int a
     a.g = g;
     a.nd = c->nd;
     if (cur && !accumulate) HIPCHK(c, launch_fill(c->nd.rhs, c->nd.d, (int)c->n_nodes, c->stream));
+    if (cur && !accumulate && g.shared_ca) HIPCHK(c, launch_fill(c->nd.ica, c->nd.ica, (int)c->n_nodes, c->stream));
     for (int s = 0; s < (int)c->slots.size(); ++s) {
         a.slot = slot_dev(c, s);
         if (cur) HIPCHK(c, launch_plain_cur(c->fp32, a, c->stream));
         else HIPCHK(c, launch_plain_state(c->fp32, a, c->stream));
     }
+    // the per-node calcium pools follow the gates, from this step's currents
+    if (!cur && g.shared_ca) HIPCHK(c, launch_ion_pool(c->nd, g, a.err, c->stream));
     return MECH_OK;
 }
 
@@ -579,21 +590,18 @@ FusedArgs fused_args(mech_ctx *c, const GlobDev &g, int kofs) {
     return a;
 }
 
-void fused_shape(const mech_ctx *c, int *grid, size_t *lds) {
+int fused_grid(const mech_ctx *c) {
     int gr = (int)c->n_tiles;
     if (c->blocks_per_cu > 0) gr = (int)std::min<int64_t>(c->n_tiles, (int64_t)c->blocks_per_cu * c->n_cu);
-    *grid = gr;
-    *lds = 4 * sizeof(double) * (size_t)std::max<int64_t>(c->max_tile_nodes, 1);
+    return gr;
 }
 
 // One fused pass; in cable mode the pass only writes rhs/d and the tree solve
 // follows it on the same stream to provide v_{k+1}.
 int launch_fused_phase(mech_ctx *c, int phases, int vmode, const GlobDev &g, int kofs, hipStream_t s) {
-    int grid;
-    size_t lds;
-    fused_shape(c, &grid, &lds);
     const int vm = vmode == MECH_V_CABLE ? MECH_V_EXTERNAL : vmode;
-    HIPCHK(c, launch_fused(c->fp32, phases, vm, fused_args(c, g, kofs), grid, c->block, lds, s));
+    const int tn = (int)std::max<int64_t>(c->max_tile_nodes, 1);
+    HIPCHK(c, launch_fused(c->fp32, phases, vm, fused_args(c, g, kofs), fused_grid(c), c->block, tn, s));
     if (vmode == MECH_V_CABLE && (phases & kDoCur)) HIPCHK(c, launch_cable(c->cable, c->nd, g, s));
     return MECH_OK;
 }
@@ -813,6 +821,10 @@ int mech_alloc(mech_ctx **out, int64_t n_nodes, const mech_type_desc *types, int
     if (rc == MECH_OK) {
         c->nd.n_nodes = (int)n_nodes;
         c->nd.spikes = (int *)(c->buf + c->L.off_spikes);
+        if (c->L.has_ion) {
+            c->nd.cai = (double *)(c->buf + c->L.off_ion);
+            c->nd.ica = c->nd.cai + std::max<int64_t>(n_nodes, 1);
+        }
         rc = build_tiles(c);
     }
     if (rc != MECH_OK) {
@@ -1000,6 +1012,19 @@ int mech_set_global(mech_ctx *c, const char *name, double value) {
         clear_graphs(c);
         return MECH_OK;
     }
+    if (!strcmp(name, "shared_ca")) {
+        if (value != 0.0 && value != 1.0) return fail(c, MECH_ERR_INVAL, "shared_ca must be 0 or 1");
+        if (value != 0.0 && !c->nd.cai)
+            return fail(c, MECH_ERR_STATE, "shared_ca needs a cahva or capump type");
+        if (value != 0.0 && !c->ion_lds) {
+            // the fused pass then keeps two more doubles per tile node in LDS
+            HIPCHK(c, fused_allow_lds(fused_lds_bytes(kMaxTileNodes, true)));
+            c->ion_lds = true;
+        }
+        G.shared_ca = value != 0.0;
+        clear_graphs(c);
+        return MECH_OK;
+    }
     if (!strcmp(name, "analytic_conductance") || !strcmp(name, "pade_cnexp")) {
         if (value != 0.0 && value != 1.0) return fail(c, MECH_ERR_INVAL, "%s must be 0 or 1", name);
         (name[0] == 'a' ? G.analytic_conductance : G.pade_cnexp) = value != 0.0;
@@ -1028,6 +1053,7 @@ int mech_init(mech_ctx *c) {
         HIPCHK(c, launch_init(c->fp32, a, c->stream));
     }
     HIPCHK(c, launch_fill_int(c->nd.spikes, (int)std::max<int64_t>(c->n_nodes, 1), c->stream));
+    if (c->nd.cai) HIPCHK(c, launch_ion_init(c->nd, a.g, c->stream));
     return MECH_OK;
 }
 
@@ -1102,15 +1128,15 @@ int mech_autotune(mech_ctx *c, double dt, int vmode, int nsteps, int reps, doubl
     if (rc) return rc;
     if (!(dt > 0.0) || nsteps < 1 || reps < 1) return fail(c, MECH_ERR_INVAL, "need dt > 0, nsteps >= 1, reps >= 1");
     // save everything a step writes
-    const size_t nb = 8 * (size_t)c->n_nodes;
-    const size_t save_bytes = c->L.inst_end + 3 * nb + 4 * (size_t)c->n_nodes;
+    const size_t nb = 8 * (size_t)c->n_nodes, ion = c->nd.cai ? 2 * nb : 0;
+    const size_t save_bytes = c->L.inst_end + 3 * nb + 4 * (size_t)c->n_nodes + ion;
     char *save = nullptr;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMalloc(&save, std::max<size_t>(save_bytes, 1)));
     auto copy_all = [&](bool to_save) -> hipError_t {
         struct { void *dev; size_t n; } parts[] = {
             {c->buf, c->L.inst_end}, {c->nd.v, nb}, {c->nd.rhs, nb}, {c->nd.d, nb},
-            {c->nd.spikes, 4 * (size_t)c->n_nodes}};
+            {c->nd.spikes, 4 * (size_t)c->n_nodes}, {c->nd.cai, ion / 2}, {c->nd.ica, ion / 2}};
         size_t o = 0;
         for (auto &p : parts) {
             if (p.n == 0) continue;
@@ -1174,8 +1200,26 @@ int mech_autotune(mech_ctx *c, double dt, int vmode, int nsteps, int reps, doubl
     return MECH_OK;
 }
 
+// slot -1: the per-node calcium ion ("cai", "ica"), n_nodes doubles.
+static int ion_array(mech_ctx *c, const char *name, int64_t n, double **out) {
+    if (!c->nd.cai) return fail(c, MECH_ERR_INVAL, "no per-node ion: the context has no calcium type");
+    if (!strcmp(name, "cai")) *out = c->nd.cai;
+    else if (!strcmp(name, "ica")) *out = c->nd.ica;
+    else return fail(c, MECH_ERR_INVAL, "per-node ion arrays are 'cai' and 'ica', not '%s'", name);
+    if (n != c->n_nodes) return fail(c, MECH_ERR_INVAL, "expected %lld nodes", (long long)c->n_nodes);
+    return MECH_OK;
+}
+
 int mech_get_state(mech_ctx *c, int slot, const char *name, double *host_out, int64_t n) {
-    if (!c || !host_out) return fail(c, MECH_ERR_INVAL, "null argument");
+    if (!c || !host_out || !name) return fail(c, MECH_ERR_INVAL, "null argument");
+    if (slot == -1) {
+        double *p;
+        int rc = ion_array(c, name, n, &p);
+        if (rc || n == 0) return rc;
+        HIPCHK(c, hipMemcpyAsync(host_out, p, 8 * n, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        return MECH_OK;
+    }
     size_t off;
     bool isd;
     int rc = find_slot_var(c, slot, name, true, &off, &isd);
@@ -1198,7 +1242,15 @@ int mech_get_state(mech_ctx *c, int slot, const char *name, double *host_out, in
 }
 
 int mech_set_state(mech_ctx *c, int slot, const char *name, const double *host_in, int64_t n) {
-    if (!c || !host_in) return fail(c, MECH_ERR_INVAL, "null argument");
+    if (!c || !host_in || !name) return fail(c, MECH_ERR_INVAL, "null argument");
+    if (slot == -1) {
+        double *p;
+        int rc = ion_array(c, name, n, &p);
+        if (rc || n == 0) return rc;
+        HIPCHK(c, hipMemcpyAsync(p, host_in, 8 * n, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        return MECH_OK;
+    }
     size_t off;
     bool isd;
     int rc = find_slot_var(c, slot, name, true, &off, &isd);

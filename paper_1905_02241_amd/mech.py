@@ -25,7 +25,7 @@ PATH = {"plain": 0, "batched": 1}
 GLOBAL_NAMES = ("celsius", "ena", "ek", "eh", "cao", "cai0", "tau_ca", "ca_gamma", "ca_depth", "e_syn",
                 "mg", "tau_r_ampa", "tau_d_ampa", "tau_r_nmda", "tau_d_nmda", "event_rate_hz", "event_seed",
                 "vthresh", "fd_dv", "analytic_conductance", "pade_cnexp", "pump_vmax", "pump_kp",
-                "newton_iters")
+                "newton_iters", "shared_ca")
 
 # Exported symbols of include/mech.h (checked by the CPU tests).
 SYMBOLS = ("mech_required_bytes", "mech_alloc", "mech_bind_nodes", "mech_bind_clamp", "mech_cable_required_bytes",
@@ -252,6 +252,16 @@ class Mechanisms:
     def set_state(self, slot: int, name: str, values):
         a = np.ascontiguousarray(values, dtype=np.float64)
         self._check(self.L.mech_set_state(self.ctx, slot, name.encode(), _dp(a), a.shape[0]))
+
+    def ion(self, name: str) -> np.ndarray:
+        """Per-node calcium ion array, 'cai' (mM) or 'ica' (mA/cm2)."""
+        out = np.empty(self.n_nodes, dtype=np.float64)
+        self._check(self.L.mech_get_state(self.ctx, -1, name.encode(), _dp(out), self.n_nodes))
+        return out
+
+    def set_ion(self, name: str, values):
+        a = np.ascontiguousarray(values, dtype=np.float64)
+        self._check(self.L.mech_set_state(self.ctx, -1, name.encode(), _dp(a), a.shape[0]))
 
     def spike_counts(self) -> np.ndarray:
         out = np.empty(self.n_nodes, dtype=np.int32)

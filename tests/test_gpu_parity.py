@@ -382,6 +382,98 @@ def test_implicit_kinds_isolated_fp64(path):
     compare_nodes(got, M, "fp64", label="implicit isolated")
 
 
+# ------------------------------- per-node calcium ion, USEION (F4) --
+def compare_ion(m, M, prec, label):
+    """Node cai against the oracle's at the calcium bar; node ica, a sum of
+    instance currents in another order, against A_n = sum |ica_i| at the
+    node with the rhs bar's factors."""
+    from tests.parity import CAI_REL
+    A = np.zeros(M.n_nodes)
+    for s, sl in enumerate(M.w.slots):
+        if sl.kind in ("cahva", "capump"):
+            np.add.at(A, np.asarray(sl.node), np.abs(M.ica[s]))
+    cai, ica = m.ion("cai"), m.ion("ica")
+    rc = float(np.max(np.abs(cai - M.cai_node) / (CAI_REL[prec] * np.abs(M.cai_node))))
+    fac = 1e-11 if prec == "fp64" else 2e-3
+    ri = float(np.max(np.abs(ica - M.ica_node) / (fac * A + 1e-300)))
+    log(f"{label}: node cai ratio {rc:.3g}, node ica ratio {ri:.3g}, "
+        f"cai range {M.cai_node.min():.3g}..{M.cai_node.max():.3g} mM")
+    assert rc <= 1.0 and ri <= 1.0
+    return rc, ri
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("prec", PRECS)
+def test_shared_calcium_clamp(path, prec):
+    """Ca-HVA and capump instances, two of each per node, shuffled index,
+    feed one calcium pool per node: states, rhs/d and the node ion arrays
+    against the oracle."""
+    w = W.make_tiny(91, kinds=("pas", "hh", "cahva", "capump", "syn"), per_node=2, nsteps=120)
+    for s in w.slots:
+        if s.kind in ("cahva", "capump"):
+            s.params["gbar"][:] *= 20.0
+    w.globals["shared_ca"] = 1
+    got, m = run_gpu(w, 120, path, prec)
+    M = run_oracle(w, 120)
+    assert np.max(M.cai_node) > 2.0 * w.globals["cai0"]
+    compare_states(got, M, prec, label="shared ca")
+    compare_nodes(got, M, prec, label="shared ca")
+    compare_ion(m, M, prec, f"shared ca {path} {prec}")
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_shared_calcium_isolated_fp64(path):
+    w = W.make_tiny(92, kinds=("pas", "hh", "cahva", "capump", "syn"), n_nodes=40, per_node=2,
+                    syn_per_node=6.0, vmode="isolated", event_rate_hz=300.0, nsteps=400)
+    w.area[:] = np.linspace(100.0, 400.0, w.n_nodes)
+    w.slots[-1].params["weight"][:] *= 6.0
+    w.globals["shared_ca"] = 1
+    got, m = run_gpu(w, 400, path, "fp64")
+    M = run_oracle(w, 400)
+    assert np.array_equal(got["spikes"], M.spikes)
+    compare_states(got, M, "fp64", label="shared ca isolated")
+    compare_nodes(got, M, "fp64", label="shared ca isolated")
+    compare_ion(m, M, "fp64", f"shared ca isolated {path}")
+
+
+def test_shared_calcium_ion_arrays_checkpoint():
+    """Node cai written through the C ABI is what the next steps start from,
+    in both paths; unknown names and contexts without calcium are errors."""
+    from paper_1905_02241_amd import mech
+    w = W.make_tiny(93, kinds=("pas", "cahva"), per_node=2, nsteps=40)
+    w.globals["shared_ca"] = 1
+    a, ma = run_gpu(w, 40, "batched", "fp64")
+    b, mb = run_gpu(w, 20, "plain", "fp64")
+    mb.step(20, 20, w.dt, w.vmode, "plain")
+    mb.sync()
+    # stop after 20 steps, restart a fresh context from the saved node cai
+    # and instance states
+    mx = mech.from_workload(w, "fp64")
+    mx.step(20, 0, w.dt, w.vmode, "batched")
+    mx.sync()
+    saved = {s: {n: mx.get_state(s, n) for n in mech.STATE_NAMES[w.slots[s].kind]} for s in range(len(w.slots))}
+    cai_mid, v_mid = mx.ion("cai"), mx.nodes()["v"]
+    mc = mech.from_workload(w, "fp64")
+    mc.set_ion("cai", cai_mid)
+    for s, d in saved.items():
+        for n, x in d.items():
+            mc.set_state(s, n, x)
+    mc.set_node_array("v", v_mid)
+    mc.step(20, 20, w.dt, w.vmode, "batched")
+    mc.sync()
+    M = run_oracle(w, 40)
+    for m_ in (ma, mb, mc):
+        compare_ion(m_, M, "fp64", "shared ca checkpoint")
+    with pytest.raises(mech.MechError):
+        ma.ion("cao")
+    w2 = W.make_tiny(94, kinds=("pas", "hh"), nsteps=10)
+    m2 = mech.from_workload(w2, "fp64")
+    with pytest.raises(mech.MechError):
+        m2.set_global("shared_ca", 1)
+    with pytest.raises(mech.MechError):
+        m2.ion("cai")
+
+
 # ------------------------------------------------ cable mode: Hines (F4) --
 @pytest.mark.parametrize("path", PATHS)
 def test_cable_cells_fp64(path):

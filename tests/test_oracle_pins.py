@@ -719,10 +719,10 @@ def test_shared_calcium_with_one_channel_per_node_is_the_own_pool(oracle):
     node = w.slots[s].node
     assert np.array_equal(own.v, shared.v)
     assert np.array_equal(own.states[s]["m"], shared.states[s]["m"])
-    assert np.array_equal(own.states[s]["cai"], shared.cai[node])
+    assert np.array_equal(own.states[s]["cai"], shared.cai_node[node])
     rest = np.setdiff1d(np.arange(w.n_nodes), node)
-    assert rest.size > 0 and np.all(shared.cai[rest] == w.globals["cai0"])
-    assert np.all(shared.cai[node] != w.globals["cai0"])
+    assert rest.size > 0 and np.all(shared.cai_node[rest] == w.globals["cai0"])
+    assert np.all(shared.cai_node[node] != w.globals["cai0"])
 
 
 def test_shared_calcium_sums_channels_on_a_node(oracle):
@@ -739,10 +739,10 @@ def test_shared_calcium_sums_channels_on_a_node(oracle):
     one.slots[0] = W._slot("cahva", node[::2].copy(), {"gbar": g[::2] + g[1::2]})
     a = _run(oracle, two, 1)
     b = _run(oracle, one, 1)
-    assert np.allclose(a.cai, b.cai, rtol=1e-12, atol=0.0)
+    assert np.allclose(a.cai_node, b.cai_node, rtol=1e-12, atol=0.0)
     assert np.allclose(a.rhs, b.rhs, rtol=1e-12, atol=1e-18)
     own = _run(oracle, two, 0)
-    assert np.max(np.abs(own.states[0]["cai"] - a.cai[node]) / a.cai[node]) > 1e-3
+    assert np.max(np.abs(own.states[0]["cai"] - a.cai_node[node]) / a.cai_node[node]) > 1e-3
 
 
 def test_shared_calcium_capump_channel_feeds_the_linear_pool(oracle):
@@ -758,4 +758,4 @@ def test_shared_calcium_capump_channel_feeds_the_linear_pool(oracle):
     b = _run(oracle, wb, 0)
     sb = [i for i, sl in enumerate(wb.slots) if sl.kind == "cahva"][0]
     assert np.array_equal(a.v, b.v)
-    assert np.array_equal(a.cai[wb.slots[sb].node], b.states[sb]["cai"])
+    assert np.array_equal(a.cai_node[wb.slots[sb].node], b.states[sb]["cai"])
