@@ -235,7 +235,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the mechanism path has no "
-              "multi-GPU mode in this build", file=sys.stderr)
+              "multi-GPU mode", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -16,7 +16,7 @@
  *     approximated numerically at run time;
  *   section 8, Table 3: a timestep is State Update + Current Update + Other.
  *
- * Mechanism equations (the paper gives none; readings listed in the design doc):
+ * Mechanism equations (the paper gives none; these are readings of its names):
  *   hh    Hodgkin & Huxley (1952) kinetics, modern sign convention, rest -65 mV
  *   pas   i = g (v - e)
  *   ih    one gate, alpha = 0.005 exp(-(v+90)/20), beta = 0.005 exp((v+90)/20)

@@ -312,7 +312,7 @@ def make_c5(seed: int = SEED_BASE + 4, n_nodes: int = 30_000_000, nsteps: int = 
                     "isolated", 0.025, nsteps, area=area, cm=cm, globals=_globals(4))
 
 
-CONFIGS = {1: make_c1, 2: make_c2, 3: make_c3, 4: make_c4, 5: make_c5}
+_MAKERS = {1: make_c1, 2: make_c2, 3: make_c3, 4: make_c4, 5: make_c5}
 
 
 def make_config(i: int, scale: float = 1.0, **kw) -> Workload:
@@ -323,7 +323,7 @@ def make_config(i: int, scale: float = 1.0, **kw) -> Workload:
         else:
             base = {1: 10_000, 2: 1_000_000, 3: 500_000, 5: 30_000_000}[i]
             kw.setdefault("n_nodes", max(1, int(round(base * scale))))
-    return CONFIGS[i](**kw)
+    return _MAKERS[i](**kw)
 
 
 # ---------------------------------------------------------- small cases --

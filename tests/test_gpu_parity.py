@@ -540,6 +540,24 @@ def test_cable_cells_fp32_reports(path):
     assert match >= 0.9
 
 
+@pytest.mark.parametrize("path", PATHS)
+def test_cable_with_shared_calcium_fp64(path):
+    """The tree solve and the per-node calcium ion together: Ca-HVA and
+    capump at every compartment of branched cells share one pool per node,
+    cells cut into units of at most 64 nodes."""
+    w = W.make_cells(56, n_cells=4, lo=60, hi=300, kinds=("pas", "hh", "cahva", "capump", "syn"), nsteps=300)
+    for s in w.slots:
+        if s.kind in ("cahva", "capump"):
+            s.params["gbar"][:] *= 20.0
+    w.globals["shared_ca"] = 1
+    got, m = run_gpu(w, 300, path, "fp64", unit_nodes=64)
+    M = run_oracle(w, 300)
+    assert np.array_equal(got["spikes"], M.spikes)
+    compare_states(got, M, "fp64", label="cable shared ca")
+    compare_nodes(got, M, "fp64", label="cable shared ca")
+    compare_ion(m, M, "fp64", f"cable shared ca {path}")
+
+
 def test_cable_single_nodes_equal_isolated():
     """Cells of one compartment: the tree solve reduces to the isolated
     update exactly (same rounding path for D and R)."""
