@@ -26,12 +26,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 # Algorithmic bytes per instance per step of the fused step: node index (4,
-# none for an identity slot), STATEs read + written, PARAMETERs read (the
-# reversal potentials el / e stay FP64), ASSIGNED ica written (Ca-HVA); and
-# per node (see node_bytes).  Synapse weights are read only on an event.
+# none for an identity slot), STATEs read + written, PARAMETERs read,
+# ASSIGNED ica written (Ca-HVA); and per node (see node_bytes).  Synapse
+# weights are read only on an event.
 BYTES_PER_INSTANCE = {
     "fp64": {"pas": 4 + 8 + 8, "hh": 4 + 48 + 24 + 8, "ih": 4 + 16 + 8, "cahva": 4 + 48 + 8 + 8, "syn": 4 + 64},
-    "fp32": {"pas": 4 + 4 + 8, "hh": 4 + 24 + 12 + 8, "ih": 4 + 8 + 4, "cahva": 4 + 24 + 4 + 4, "syn": 4 + 32},
+    "fp32": {"pas": 4 + 4 + 4, "hh": 4 + 24 + 12 + 4, "ih": 4 + 8 + 4, "cahva": 4 + 24 + 4 + 4, "syn": 4 + 32},
 }
 
 

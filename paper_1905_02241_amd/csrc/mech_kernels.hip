@@ -381,7 +381,7 @@ __device__ __forceinline__ void instance(const SlotDev &sl, int i, double v, con
     if constexpr (KIND == MECH_PAS) {
         if (PH & kDoCur) {
             const S gp = ld<NT>((const S *)sl.par[0] + i);
-            const double e = ld<NT>((const double *)sl.par[1] + i);
+            const double e = (double)ld<NT>((const S *)sl.par[1] + i);
             lin_cur<S>(v, gp, e, g, ci, cg);
         }
     } else if constexpr (KIND == MECH_HH) {
@@ -396,7 +396,7 @@ __device__ __forceinline__ void instance(const SlotDev &sl, int i, double v, con
             const S gnabar = ld<NT>((const S *)sl.par[0] + i);
             const S gkbar = ld<NT>((const S *)sl.par[1] + i);
             const S gl = ld<NT>((const S *)sl.par[2] + i);
-            const double el = ld<NT>((const double *)sl.par[3] + i);
+            const double el = (double)ld<NT>((const S *)sl.par[3] + i);
             hh_cur<S>(v, m, h, n, gnabar, gkbar, gl, el, g, ci, cg);
         }
     } else if constexpr (KIND == MECH_IH) {

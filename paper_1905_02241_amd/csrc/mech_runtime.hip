@@ -25,7 +25,8 @@ namespace {
 // ----------------------------------------------------------- type table --
 struct VarDesc {
     const char *name;
-    bool is_double;  // stored as double in both precisions (else the state type)
+    bool is_double;  // stored as double in both precisions (else the state type: every RANGE
+                     // parameter read each step is, the driving force is still formed in FP64)
 };
 struct KindDesc {
     const char *name;
@@ -38,9 +39,9 @@ struct KindDesc {
 };
 
 const KindDesc kKinds[7] = {
-    {"pas", false, 0, {}, 2, {{"g", false}, {"e", true}}, {1e-3, -70.0}},
+    {"pas", false, 0, {}, 2, {{"g", false}, {"e", false}}, {1e-3, -70.0}},
     {"hh", false, 3, {"m", "h", "n"}, 4,
-     {{"gnabar", false}, {"gkbar", false}, {"gl", false}, {"el", true}}, {0.12, 0.036, 0.0003, -54.3}},
+     {{"gnabar", false}, {"gkbar", false}, {"gl", false}, {"el", false}}, {0.12, 0.036, 0.0003, -54.3}},
     {"ih", false, 1, {"m"}, 1, {{"gbar", false}}, {1e-4}},
     {"cahva", false, 3, {"m", "h", "cai"}, 1, {{"gbar", false}}, {5e-5}},
     {"syn", true, 4, {"A_ampa", "B_ampa", "A_nmda", "B_nmda"}, 1, {{"weight", true}}, {1.0}},

@@ -78,10 +78,10 @@ def test_required_bytes_layout(lib):
     fp64 = out.value
     assert lib.mech_required_bytes(1000, d, 1, 1, C.byref(out)) == 0
     fp32 = out.value
-    # 1024 padded instances: index 4 B, 3 states, 3 conductances in the state
-    # type, el in double
-    inst64 = 1024 * (4 + 3 * 8 + 3 * 8 + 8)
-    inst32 = 1024 * (4 + 3 * 4 + 3 * 4 + 8)
+    # 1024 padded instances: index 4 B, 3 states and 4 parameters (the three
+    # conductances and el) in the state type
+    inst64 = 1024 * (4 + 3 * 8 + 4 * 8)
+    inst32 = 1024 * (4 + 3 * 4 + 4 * 4)
     assert fp64 - fp32 == inst64 - inst32
     assert fp64 % 256 == 0 and fp64 > inst64
 
