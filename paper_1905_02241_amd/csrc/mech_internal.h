@@ -14,7 +14,7 @@ constexpr int kPad = 64;             // instances per padding unit (one wave)
 constexpr int kAlign = 256;          // byte alignment of every carved array
 constexpr int kMinTileBudget = 64;   // smallest tile work budget (instances)
 constexpr int kMinTileNodes = 64;
-constexpr int kMaxTileNodes = 2048;  // LDS: 32 B per node -> 64 KiB per block
+constexpr int kMaxTileNodes = 2048;  // LDS: 32 B per node -> 64 KiB per block (96 KiB with the shared calcium ion)
 
 // Step-phase flags of the fused kernel.
 enum : int { kDoState = 1, kDoCur = 2 };
