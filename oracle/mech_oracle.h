@@ -17,12 +17,17 @@
  *     2. cur      : rhs = d = 0, then for every slot in order and every instance
  *                   in index order: I0 = i(v), I1 = i(v+dv), g = (I1-I0)/dv,
  *                   rhs[node] -= s*I0, d[node] += s*g  (s = 1 for density
- *                   mechanisms, s = 100/area for point processes);
+ *                   mechanisms, s = 100/area for point processes); under
+ *                   shared_ca the calcium currents are also summed per node;
  *     3. voltage  : CLAMP    v = off + amp*sin(2*pi*freq*t_{k+1}*1e-3 + phase)
  *                   ISOLATED v += rhs/(1e-3*cm/dt + d), count upward crossings
  *                   of vthresh
+ *                   CABLE    backward Euler of the cable equation on the cell
+ *                   trees (Hines elimination), crossings counted as ISOLATED
  *                   EXTERNAL v unchanged;
- *     4. state    : cnexp update of every STATE at the new v.
+ *     4. state    : update of every STATE at the new v (cnexp, or the implicit
+ *                   solves of kmarkov and capump), then under shared_ca each
+ *                   node's calcium pool.
  *
  * Units: mV, ms, mA/cm2 and S/cm2 (density), nA and uS (point process),
  * um2, uF/cm2, mM, degC; synaptic weights and states in nS.
