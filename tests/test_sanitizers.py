@@ -4,8 +4,9 @@ The oracle (plain C) is built with AddressSanitizer and
 UndefinedBehaviorSanitizer together with a driver (tests/sanitize_oracle.c)
 that exercises every phase, mechanism kind, voltage mode and variant on
 random meshes and trees with arrays allocated at their exact sizes.  The
-host-side tree cutting of the GPU library is covered by test_cable_plan.py,
-which replays the plan it returns."""
+host side of the GPU library is built the same way with a driver
+(tests/sanitize_host.cpp) over its host-only entry points; the replay of the
+tree cut in test_cable_plan.py checks what that code computes."""
 import os
 import shutil
 import subprocess
@@ -31,7 +32,32 @@ def test_oracle_under_address_and_undefined_sanitizers(tmp_path):
     assert r.returncode == 0, r.stderr
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0",
                UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
-    env.pop("LD_PRELOAD", None) if "LD_PRELOAD" in env and "asan" in env["LD_PRELOAD"] else None
     r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=600)
     assert r.returncode == 0, r.stdout + r.stderr[-3000:]
     assert "all finite" in r.stdout
+
+
+def test_library_host_code_under_address_and_undefined_sanitizers(tmp_path):
+    """The host-only entry points of libmech (tree cutting, layouts, the
+    node-index check) with the host side of the library built under ASan and
+    UBSan; the device code is compiled as usual and never launched."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    csrc = os.path.join(ROOT, "paper_1905_02241_amd", "csrc")
+    exe = str(tmp_path / "sanitize_host")
+    cmd = [hipcc, "--offload-arch=gfx950", "-O1", "-g", "-std=c++17", "-munsafe-fp-atomics",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-Xarch_host", "-fsanitize=address",
+           "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-omit-frame-pointer",
+           "-I", os.path.join(ROOT, "include"), "-I", csrc,
+           os.path.join(ROOT, "tests", "sanitize_host.cpp"), os.path.join(csrc, "mech_kernels.hip"),
+           os.path.join(csrc, "mech_runtime.hip"), "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-3000:]
+    # leak checking is off: the HIP runtime keeps its own allocations to exit
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0", UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+    r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=600)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-3000:]
+    assert ", 0 failed" in r.stdout
