@@ -131,23 +131,34 @@ def time_variant(w, prec, path, steps, warmup, autotune, torch, mech, launch=Non
             "tiles": info["n_tiles"]}
 
 
-def cpu_baseline(w, target_s: float, nodes: int):
-    """The oracle (single thread) on a node sample of the same workload."""
+def node_sample(w, nodes: int, seed: int):
+    """A sample of about `nodes` nodes of the workload as its own workload:
+    random nodes, or in cable mode whole cells (the tree solve couples a
+    cell's nodes), drawn until the sample is full.  Returns (sub, keep,
+    node ids)."""
     import numpy as np
-    from oracle import oracle as O
     from paper_1905_02241_amd import workloads as W
-    rng = np.random.default_rng(7)
+    rng = np.random.default_rng(seed)
     if w.vmode == "cable":
-        # whole cells (the tree solve couples a cell's nodes), drawn until the sample is full
         pick, total = [], 0
         for c in rng.permutation(len(w.cell_sizes)):
             if total and total + int(w.cell_sizes[c]) > nodes:
                 continue
             pick.append(int(c))
             total += int(w.cell_sizes[c])
-        sub, _ = W.cells_subset(w, pick)
-    else:
-        sub, _ = W.subset(w, rng.choice(w.n_nodes, size=min(nodes, w.n_nodes), replace=False))
+        starts = np.concatenate([[0], np.cumsum(w.cell_sizes)])
+        ids = np.concatenate([np.arange(starts[c], starts[c + 1]) for c in sorted(pick)])
+        sub, keep = W.cells_subset(w, pick)
+        return sub, keep, ids
+    ids = np.sort(rng.choice(w.n_nodes, size=min(nodes, w.n_nodes), replace=False))
+    sub, keep = W.subset(w, ids)
+    return sub, keep, ids
+
+
+def cpu_baseline(w, target_s: float, nodes: int):
+    """The oracle (single thread) on a node sample of the same workload."""
+    from oracle import oracle as O
+    sub, _, _ = node_sample(w, nodes, 7)
     M = O.Model(sub)
     M.init()
     t = time.perf_counter()
@@ -167,10 +178,7 @@ def precision_report(w, steps: int, sample: int, torch, mech):
     oracle on a node sample after `steps` steps (the precision contract)."""
     import numpy as np
     from oracle import oracle as O
-    from paper_1905_02241_amd import workloads as W
-    rng = np.random.default_rng(11)
-    nodes = np.sort(rng.choice(w.n_nodes, size=min(sample, w.n_nodes), replace=False))
-    sub, keep = W.subset(w, nodes)
+    sub, keep, nodes = node_sample(w, sample, 11)
     M = O.Model(sub)
     M.init()
     M.run(0, steps)
@@ -199,7 +207,7 @@ def precision_report(w, steps: int, sample: int, torch, mech):
                 rep[f"{sl.kind}.{name}"] = {"max_abs": float(err.max()), "max_rel": float(rel.max())}
         v = m.v.cpu().numpy()[nodes]
         rep["v"] = {"max_abs": float(np.max(np.abs(v - M.v)))}
-        if w.vmode == "isolated":
+        if w.vmode in ("isolated", "cable"):
             sp = m.spike_counts()[nodes]
             rep["spikes"] = {"match_rate": float(np.mean(sp == M.spikes)), "oracle_total": int(M.spikes.sum()),
                              "gpu_total": int(sp.sum())}
