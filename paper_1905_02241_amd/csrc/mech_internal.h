@@ -96,7 +96,7 @@ struct CableDev {
     const int *list_up;        // FULL and PIECE units (LDS), tallest first
     const int *list_top;       // TOP units that fit in LDS
     const int *list_top_g;     // TOP units solved in global scratch
-    const int *list_down;      // PIECE units, second pass
+    const int *list_down;      // FULL and PIECE units, second pass (back-substitution)
     int n_up, n_top, n_top_g, n_down;
     int lds_max_nodes;         // largest unit solved in LDS
     double *ekn, *ekp;         // per edge record: 100 g/area_n, 100 g/area_p

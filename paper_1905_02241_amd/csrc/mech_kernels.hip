@@ -694,7 +694,8 @@ __global__ void k_visolated(NodesDev nd, GlobDev g) {
 // one TOP unit.  Pieces eliminate up to their roots and hand the rows over
 // in global memory; the trunk's unit takes each piece root's row as a ghost
 // leaf, solves, and hands back the root's dv; the pieces then
-// back-substitute.  The elimination order within each tree stays a valid
+// back-substitute, and so do whole cells, whose elimination ran beside the
+// pieces'.  The elimination order within each tree stays a valid
 // Hines order, so the result is the same elimination up to rounding.  A
 // trunk larger than LDS is solved with its rows in global memory, accessed
 // at device scope.
@@ -867,8 +868,10 @@ __global__ __launch_bounds__(512) void k_cable(CableDev c, NodesDev nd, GlobDev 
             }
             level_barrier<LDS>();
         }
-        if (mode == kUnitPiece) {
-            // eliminated rows go to the trunk's unit and to the second pass
+        if (mode != kUnitTop) {
+            // eliminated rows go to the second pass (and a piece root's to its
+            // trunk's unit): whole cells back-substitute there too, beside the
+            // pieces, which keeps this pass as short as the longest elimination
             if constexpr (LDS)
                 for (int i = p0 + tid; i < p1; i += B) {
                     c.D[i] = D[i - base];
@@ -877,8 +880,8 @@ __global__ __launch_bounds__(512) void k_cable(CableDev c, NodesDev nd, GlobDev 
             return;
         }
     } else {
-        // second pass of a piece: its eliminated rows, and at each root the
-        // dv its trunk's unit handed back
+        // second pass of a piece or whole cells: the eliminated rows, and at
+        // each piece root the dv its trunk's unit handed back
         if constexpr (LDS)
             for (int i0 = p0 + tid; i0 < p1; i0 += kBatch * B) {
                 double x[kBatch], y[kBatch];

@@ -131,7 +131,7 @@ std::string build_cable(int64_t N, const int32_t *parent, int cap, CableHost &h)
         const int size = h.unit_pos[u + 1] - h.unit_pos[u];
         if (mode != kUnitTop || size <= cap) h.lds_max = std::max(h.lds_max, size);
         if (mode == kUnitFull || mode == kUnitPiece) h.list_up.push_back(u);
-        if (mode == kUnitPiece) h.list_down.push_back(u);
+        if (mode == kUnitFull || mode == kUnitPiece) h.list_down.push_back(u);
         if (mode == kUnitTop) (size <= cap ? h.list_top : h.list_top_g).push_back(u);
     };
     auto place = [&](int32_t n, int32_t par_pos, int32_t src) {

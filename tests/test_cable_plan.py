@@ -68,7 +68,7 @@ def check_structure(plan, n, cap):
     size = np.diff(up)
     assert np.all(size[um != TOP] <= cap)
     assert sorted(plan["list_up"].tolist()) == np.flatnonzero(um != TOP).tolist()
-    assert sorted(plan["list_down"].tolist()) == np.flatnonzero(um == PIECE).tolist()
+    assert sorted(plan["list_down"].tolist()) == np.flatnonzero(um != TOP).tolist()
     tops = sorted(plan["list_top"].tolist() + plan["list_top_g"].tolist())
     assert tops == np.flatnonzero(um == TOP).tolist()
     assert np.all(size[plan["list_top"]] <= cap) and np.all(size[plan["list_top_g"]] > cap)
@@ -117,7 +117,8 @@ def replay(plan, v, rhs, d, cm, area, g, dt):
                 f = ekp[q] / Dc
                 np.add.at(D, rp, -f * ekn[q])
                 np.add.at(R, rp, f * Rc)
-            if um[u] == PIECE:
+            if um[u] != TOP:
+                # whole cells and pieces back-substitute in the second pass
                 GD[idx], GR[idx] = D[idx], R[idx]
                 return
         else:
