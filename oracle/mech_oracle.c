@@ -25,6 +25,8 @@
  *   kmarkov  three-state C1-C2-O potassium scheme, implicit Euler (sparse)
  *   capump   Ca-HVA gates with a pool emptied by a saturable pump, implicit
  *            Euler solved by Newton's method (derivimplicit)
+ *   cabuf    Ca-HVA gates with free and buffer-bound calcium, implicit Euler
+ *            solved by Newton's method on the 2x2 system (derivimplicit)
  *   shared_ca  calcium as a per-node ion (USEION, section 3): the calcium
  *            currents of all instances on a node feed one pool per node
  */
@@ -121,34 +123,36 @@ void orc_kmarkov_matrix(double v, double celsius, double dt, double *M) {
 }
 
 /* Gaussian elimination with partial pivoting on a 3x3 system (textbook). */
-static void solve3(double *M, double *x) {
-    for (int k = 0; k < 3; ++k) {
+/* M x = b for n <= 4 by Gaussian elimination with partial pivoting (row
+ * major M, x holds b on entry and the solution on return).                 */
+static void solve_n(int n, double *M, double *x) {
+    for (int k = 0; k < n; ++k) {
         int p = k;
-        for (int r = k + 1; r < 3; ++r)
-            if (fabs(M[3 * r + k]) > fabs(M[3 * p + k])) p = r;
+        for (int r = k + 1; r < n; ++r)
+            if (fabs(M[n * r + k]) > fabs(M[n * p + k])) p = r;
         if (p != k) {
-            for (int c = 0; c < 3; ++c) {
-                double t = M[3 * k + c]; M[3 * k + c] = M[3 * p + c]; M[3 * p + c] = t;
+            for (int c = 0; c < n; ++c) {
+                double t = M[n * k + c]; M[n * k + c] = M[n * p + c]; M[n * p + c] = t;
             }
             double t = x[k]; x[k] = x[p]; x[p] = t;
         }
-        for (int r = k + 1; r < 3; ++r) {
-            double f = M[3 * r + k] / M[3 * k + k];
-            for (int c = k; c < 3; ++c) M[3 * r + c] -= f * M[3 * k + c];
+        for (int r = k + 1; r < n; ++r) {
+            double f = M[n * r + k] / M[n * k + k];
+            for (int c = k; c < n; ++c) M[n * r + c] -= f * M[n * k + c];
             x[r] -= f * x[k];
         }
     }
-    for (int k = 2; k >= 0; --k) {
+    for (int k = n - 1; k >= 0; --k) {
         double sum = x[k];
-        for (int c = k + 1; c < 3; ++c) sum -= M[3 * k + c] * x[c];
-        x[k] = sum / M[3 * k + k];
+        for (int c = k + 1; c < n; ++c) sum -= M[n * k + c] * x[c];
+        x[k] = sum / M[n * k + k];
     }
 }
 
 void orc_kmarkov_step(double v, double celsius, double dt, double *x) {
     double M[9];
     orc_kmarkov_matrix(v, celsius, dt, M);
-    solve3(M, x);
+    solve_n(3, M, x);
 }
 
 /* -------------------------------------------------------------- capump -- */
@@ -167,6 +171,47 @@ double orc_capump_step(const orc_globals *gl, double ica, double dt, double *cai
     }
     *cai = c;
     return c - c0 - dt * (-kappa * ica - pump_rate(gl, c));
+}
+
+/* --------------------------------------------------------------- cabuf -- */
+/* Free calcium c and buffer-bound calcium b (total buffer btot, binding
+ * kon c (btot - b), unbinding koff b) in a pool that relaxes to cai0:
+ *   dc/dt = -kappa ica - kon c (btot - b) + koff b - (c - cai0)/tau_ca
+ *   db/dt =  kon c (btot - b) - koff b
+ * Implicit Euler (the derivimplicit method, section 5.2) gives
+ * G(c, b) = (c - c_old - dt F_c, b - b_old - dt F_b) = 0, solved by `iters`
+ * Newton steps from the old state with the analytic Jacobian
+ * I - dt dF/d(c, b); each step solves the 2x2 system.  Returns the max-norm
+ * of G at the result.                                                       */
+static void cabuf_rates(const orc_globals *gl, double kappa, double ica, double c, double b, double *F) {
+    double bind = gl->buf_kon * c * (gl->buf_total - b) - gl->buf_koff * b;
+    F[0] = -kappa * ica - bind - (c - gl->cai0) / gl->tau_ca;
+    F[1] = bind;
+}
+
+double orc_cabuf_step(const orc_globals *gl, double ica, double dt, double *cai, double *cab, int iters) {
+    double kappa = orc_ca_kappa(gl->ca_gamma, gl->ca_depth);
+    double c0 = *cai, b0 = *cab, c = c0, b = b0, F[2];
+    for (int it = 0; it < iters; ++it) {
+        cabuf_rates(gl, kappa, ica, c, b, F);
+        double G[2] = {-(c - c0 - dt * F[0]), -(b - b0 - dt * F[1])};
+        double dbind_dc = gl->buf_kon * (gl->buf_total - b), dbind_db = -gl->buf_kon * c - gl->buf_koff;
+        double J[4] = {1.0 - dt * (-dbind_dc - 1.0 / gl->tau_ca), -dt * (-dbind_db),
+                       -dt * dbind_dc, 1.0 - dt * dbind_db};
+        solve_n(2, J, G);
+        c += G[0];
+        b += G[1];
+    }
+    *cai = c;
+    *cab = b;
+    cabuf_rates(gl, kappa, ica, c, b, F);
+    double r0 = fabs(c - c0 - dt * F[0]), r1 = fabs(b - b0 - dt * F[1]);
+    return r0 > r1 ? r0 : r1;
+}
+
+/* the bound calcium in equilibrium with free calcium c                     */
+double orc_cabuf_bound(const orc_globals *gl, double c) {
+    return gl->buf_total * gl->buf_kon * c / (gl->buf_kon * c + gl->buf_koff);
 }
 
 double orc_nernst_ca(double cai, double cao, double celsius) {
@@ -239,7 +284,8 @@ static double instance_i(const orc_globals *gl, const orc_nodes *nd, const orc_s
     case ORC_IH:
         return s->par[0][i] * s->st[0][i] * (v - gl->eh);
     case ORC_CAHVA:
-    case ORC_CAPUMP: {
+    case ORC_CAPUMP:
+    case ORC_CABUF: {
         double m = s->st[0][i], h = s->st[1][i];
         double eca = orc_nernst_ca(ca_conc(gl, nd, s, i), gl->cao, gl->celsius);
         return s->par[0][i] * m * m * h * (v - eca);
@@ -271,7 +317,8 @@ static double instance_g(const orc_globals *gl, const orc_slot *s, int64_t i, do
     case ORC_IH:
         return s->par[0][i] * s->st[0][i];
     case ORC_CAHVA:
-    case ORC_CAPUMP: {
+    case ORC_CAPUMP:
+    case ORC_CABUF: {
         double m = s->st[0][i], h = s->st[1][i];
         return s->par[0][i] * m * m * h;
     }
@@ -317,8 +364,10 @@ void orc_init(const orc_globals *gl, orc_nodes *nd, orc_slot *slots, int nslots)
                 break;
             case ORC_CAHVA:
             case ORC_CAPUMP:
+            case ORC_CABUF:
                 orc_cahva_inf_tau(v, o);
                 sl->st[0][i] = o[0]; sl->st[1][i] = o[1]; sl->st[2][i] = gl->cai0;
+                if (sl->kind == ORC_CABUF) sl->st[3][i] = orc_cabuf_bound(gl, gl->cai0);
                 if (sl->ica) sl->ica[i] = 0.0;
                 break;
             case ORC_KMARKOV: {
@@ -376,7 +425,7 @@ void orc_cur(const orc_globals *gl, orc_nodes *nd, orc_slot *slots, int nslots) 
             int32_t ni = sl->node[i];
             double I0, g;
             orc_instance_current(gl, nd, sl, i, nd->v[ni], &I0, &g);
-            if (sl->kind == ORC_CAHVA || sl->kind == ORC_CAPUMP) {
+            if (sl->kind == ORC_CAHVA || sl->kind == ORC_CAPUMP || sl->kind == ORC_CABUF) {
                 if (sl->ica) sl->ica[i] = I0;
                 if (shared) nd->ica[ni] += I0;   /* the node's calcium current */
             }
@@ -506,6 +555,14 @@ void orc_state(const orc_globals *gl, orc_nodes *nd, orc_slot *slots, int nslots
                 sl->st[0][i] = cnexp(gl, sl->st[0][i], o[0], o[2], dt);
                 sl->st[1][i] = cnexp(gl, sl->st[1][i], o[1], o[3], dt);
                 if (!shared) orc_capump_step(gl, sl->ica[i], dt, &sl->st[2][i], gl->newton_iters);
+                break;
+            }
+            case ORC_CABUF: {
+                orc_cahva_inf_tau(v, o);
+                sl->st[0][i] = cnexp(gl, sl->st[0][i], o[0], o[2], dt);
+                sl->st[1][i] = cnexp(gl, sl->st[1][i], o[1], o[3], dt);
+                if (!shared)
+                    orc_cabuf_step(gl, sl->ica[i], dt, &sl->st[2][i], &sl->st[3][i], gl->newton_iters);
                 break;
             }
             case ORC_KMARKOV: {

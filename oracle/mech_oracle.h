@@ -47,15 +47,17 @@
 extern "C" {
 #endif
 
-enum { ORC_PAS = 0, ORC_HH = 1, ORC_IH = 2, ORC_CAHVA = 3, ORC_SYN = 4, ORC_KMARKOV = 5, ORC_CAPUMP = 6 };
+enum { ORC_PAS = 0, ORC_HH = 1, ORC_IH = 2, ORC_CAHVA = 3, ORC_SYN = 4, ORC_KMARKOV = 5, ORC_CAPUMP = 6,
+       ORC_CABUF = 7 };
 enum { ORC_V_EXTERNAL = 0, ORC_V_CLAMP = 1, ORC_V_ISOLATED = 2, ORC_V_CABLE = 3 };
 
 /* One mechanism type ("slot") and its instances, in the caller's order.
  *   st : STATE arrays     hh: m,h,n   ih: m   cahva: m,h,cai   syn: Aa,Ba,An,Bn
  *                         kmarkov: C1,C2,O   capump: m,h,cai
+ *                         cabuf: m,h,cai,cab
  *   par: RANGE parameters hh: gnabar,gkbar,gl,el   pas: g,e   ih: gbar
  *                         cahva: gbar   syn: weight (nS)   kmarkov: gbar
- *                         capump: gbar
+ *                         capump: gbar   cabuf: gbar
  *   ica: Ca-HVA calcium current written by cur and read by state (mA/cm2)
  *   gid: synapse event-stream id (NULL: the instance index is used)        */
 typedef struct {
@@ -97,6 +99,9 @@ typedef struct {
      * node's total, and one pool per node relaxes by the linear pool law
      * from that total (the instances' own pools are not used).              */
     int32_t shared_ca;
+    /* cabuf: total buffer (mM), binding rate (1/(mM ms)) and unbinding rate
+     * (1/ms) of the calcium buffer                                          */
+    double buf_total, buf_kon, buf_koff;
 } orc_globals;
 
 typedef struct {
@@ -134,6 +139,10 @@ void orc_kmarkov_step(double v, double celsius, double dt, double *x3);
  * cai0/(cai0+kp)), by `iters` Newton steps from c = cai; returns the
  * residual of the last iterate.                                           */
 double orc_capump_step(const orc_globals *gl, double ica, double dt, double *cai, int iters);
+/* one implicit Euler step of the cabuf pool (free cai, bound cab), `iters`
+ * Newton steps on the 2x2 system; returns the max-norm residual            */
+double orc_cabuf_step(const orc_globals *gl, double ica, double dt, double *cai, double *cab, int iters);
+double orc_cabuf_bound(const orc_globals *gl, double c);        /* mM        */
 double orc_mg_block(double v, double mg);
 double orc_syn_peak_factor(double tau_r, double tau_d, double *t_peak);
 double orc_nernst_ca(double cai, double cao, double celsius);     /* mV      */

@@ -20,13 +20,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "mech_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
-KIND = {"pas": 0, "hh": 1, "ih": 2, "cahva": 3, "syn": 4, "kmarkov": 5, "capump": 6}
+KIND = {"pas": 0, "hh": 1, "ih": 2, "cahva": 3, "syn": 4, "kmarkov": 5, "capump": 6, "cabuf": 7}
 VMODE = {"external": 0, "clamp": 1, "isolated": 2, "cable": 3}
 PARAMS = {"pas": ("g", "e"), "hh": ("gnabar", "gkbar", "gl", "el"), "ih": ("gbar",),
-          "cahva": ("gbar",), "syn": ("weight",), "kmarkov": ("gbar",), "capump": ("gbar",)}
+          "cahva": ("gbar",), "syn": ("weight",), "kmarkov": ("gbar",), "capump": ("gbar",), "cabuf": ("gbar",)}
 STATES = {"pas": (), "hh": ("m", "h", "n"), "ih": ("m",), "cahva": ("m", "h", "cai"),
           "syn": ("A_ampa", "B_ampa", "A_nmda", "B_nmda"), "kmarkov": ("C1", "C2", "O"),
-          "capump": ("m", "h", "cai")}
+          "capump": ("m", "h", "cai"), "cabuf": ("m", "h", "cai", "cab")}
 GLOBAL_FIELDS = ("celsius", "ena", "ek", "eh", "cao", "cai0", "tau_ca", "ca_gamma", "ca_depth",
                  "e_syn", "mg", "tau_r_ampa", "tau_d_ampa", "tau_r_nmda", "tau_d_nmda",
                  "event_rate_hz", "vthresh", "fd_dv")
@@ -48,7 +48,8 @@ class _Globals(C.Structure):
     _fields_ = ([(f, C.c_double) for f in GLOBAL_FIELDS] + [("event_seed", C.c_uint64)] +
                 [(f, C.c_int32) for f in FLAG_FIELDS] +
                 [("pump_vmax", C.c_double), ("pump_kp", C.c_double), ("newton_iters", C.c_int32),
-                 ("shared_ca", C.c_int32)])
+                 ("shared_ca", C.c_int32), ("buf_total", C.c_double), ("buf_kon", C.c_double),
+                 ("buf_koff", C.c_double)])
 
 
 class _Nodes(C.Structure):
@@ -97,6 +98,10 @@ def lib():
         L.orc_kmarkov_step.argtypes = [C.c_double, C.c_double, C.c_double, _dp]
         L.orc_capump_step.argtypes = [C.POINTER(_Globals), C.c_double, C.c_double, _dp, C.c_int]
         L.orc_capump_step.restype = C.c_double
+        L.orc_cabuf_step.argtypes = [C.POINTER(_Globals), C.c_double, C.c_double, _dp, _dp, C.c_int]
+        L.orc_cabuf_step.restype = C.c_double
+        L.orc_cabuf_bound.argtypes = [C.POINTER(_Globals), C.c_double]
+        L.orc_cabuf_bound.restype = C.c_double
         L.orc_instance_current.argtypes = [C.POINTER(_Globals), C.POINTER(_Nodes), C.POINTER(_Slot), C.c_int64,
                                            C.c_double, _dp, _dp]
         sig = [C.POINTER(_Globals), C.POINTER(_Nodes), C.POINTER(_Slot), C.c_int]
@@ -254,6 +259,9 @@ class Model:
         g.pump_kp = float(self.globals.get("pump_kp", 1e-3))
         g.newton_iters = int(self.globals.get("newton_iters", 4))
         g.shared_ca = int(self.globals.get("shared_ca", 0))
+        g.buf_total = float(self.globals.get("buf_total", 0.05))
+        g.buf_kon = float(self.globals.get("buf_kon", 100.0))
+        g.buf_koff = float(self.globals.get("buf_koff", 0.1))
         return g
 
     def set_global(self, name, value):
@@ -303,6 +311,15 @@ class Model:
         c = C.c_double(cai)
         r = lib().orc_capump_step(C.byref(self._g), ica, self.dt, C.byref(c), iters)
         return c.value, r
+
+    def cabuf_step(self, ica: float, cai: float, cab: float, iters: int, dt=None):
+        """One implicit Euler step of the cabuf pool; returns (cai, cab, residual)."""
+        c, b = C.c_double(cai), C.c_double(cab)
+        r = lib().orc_cabuf_step(C.byref(self._g), ica, self.dt if dt is None else dt, C.byref(c), C.byref(b), iters)
+        return c.value, b.value, r
+
+    def cabuf_bound(self, cai: float) -> float:
+        return lib().orc_cabuf_bound(C.byref(self._g), cai)
 
     def instance_current(self, s: int, i: int, v: float):
         cur, cond = C.c_double(), C.c_double()

@@ -20,7 +20,7 @@ from typing import Dict, List, Optional
 
 import numpy as np
 
-KINDS = ("pas", "hh", "ih", "cahva", "syn", "kmarkov", "capump")
+KINDS = ("pas", "hh", "ih", "cahva", "syn", "kmarkov", "capump", "cabuf")
 KIND_ID = {k: i for i, k in enumerate(KINDS)}
 
 # Variable names of every mechanism type (interface only).
@@ -32,6 +32,7 @@ PARAM_NAMES = {
     "syn": ("weight",),
     "kmarkov": ("gbar",),
     "capump": ("gbar",),
+    "cabuf": ("gbar",),
 }
 STATE_NAMES = {
     "pas": (),
@@ -41,6 +42,7 @@ STATE_NAMES = {
     "syn": ("A_ampa", "B_ampa", "A_nmda", "B_nmda"),
     "kmarkov": ("C1", "C2", "O"),
     "capump": ("m", "h", "cai"),
+    "cabuf": ("m", "h", "cai", "cab"),
 }
 PARAM_DEFAULTS = {
     "pas": {"g": 1e-3, "e": -70.0},
@@ -50,6 +52,7 @@ PARAM_DEFAULTS = {
     "syn": {"weight": 1.0},
     "kmarkov": {"gbar": 0.01},
     "capump": {"gbar": 5e-5},
+    "cabuf": {"gbar": 5e-5},
 }
 
 DEFAULT_GLOBALS = {
@@ -77,7 +80,10 @@ DEFAULT_GLOBALS = {
     "pump_vmax": 1e-4,           # capump: maximal pump rate (mM/ms)
     "pump_kp": 1e-3,             # capump: pump half-activation (mM)
     "newton_iters": 4,           # capump: Newton steps per implicit Euler step
-    "shared_ca": 0,              # 1: calcium is a per-node ion shared by the cahva/capump instances of a node
+    "shared_ca": 0,              # 1: calcium is a per-node ion shared by the calcium channels of a node
+    "buf_total": 0.05,           # cabuf: total calcium buffer (mM)
+    "buf_kon": 100.0,            # cabuf: binding rate (1/(mM ms)); with buf_koff a 1 uM dissociation constant
+    "buf_koff": 0.1,             # cabuf: unbinding rate (1/ms)
 }
 
 VMODES = ("external", "clamp", "isolated", "cable")

@@ -4,7 +4,7 @@
  * builds and runs it).  Every array is allocated at its exact size, so a read
  * or write one element past any of them is reported.
  *
- * Covered: all seven mechanism kinds with many-to-one node indices, the four
+ * Covered: all eight mechanism kinds with many-to-one node indices, the four
  * voltage modes (random branched trees for the cable mode), the calcium pool
  * per instance and per node, the closed-form conductance and Pade variants.
  * Exit status 0 when every result is finite, 1 otherwise (a sanitizer report
@@ -32,8 +32,9 @@ static double *dalloc(int64_t n, double lo, double hi) {
     return a;
 }
 
-static const int kStates[7] = {0, 3, 1, 3, 4, 3, 3};
-static const int kParams[7] = {2, 4, 1, 1, 1, 1, 1};
+#define NK 8
+static const int kStates[NK] = {0, 3, 1, 3, 4, 3, 3, 4};
+static const int kParams[NK] = {2, 4, 1, 1, 1, 1, 1, 1};
 
 static int finite_all(const double *a, int64_t n) {
     for (int64_t i = 0; i < n; ++i)
@@ -43,7 +44,7 @@ static int finite_all(const double *a, int64_t n) {
 
 static int run_case(int n_nodes, int vmode, int shared, int analytic, int pade, int64_t nsteps) {
     orc_globals gl = {6.3, 50.0, -77.0, -45.0, 2.0, 5e-5, 80.0, 0.05, 0.1, 0.0, 1.0, 0.2, 1.7, 0.29, 43.0,
-                      400.0, -20.0, 1e-3, 12345u, analytic, pade, 1e-4, 1e-3, 4, shared};
+                      400.0, -20.0, 1e-3, 12345u, analytic, pade, 1e-4, 1e-3, 4, shared, 0.05, 100.0, 0.1};
     orc_nodes nd;
     nd.n_nodes = n_nodes;
     nd.v = dalloc(n_nodes, -80.0, -50.0);
@@ -76,10 +77,10 @@ static int run_case(int n_nodes, int vmode, int shared, int analytic, int pade, 
     nd.cai = dalloc(n_nodes, 0.0, 0.0);
     nd.ica = dalloc(n_nodes, 0.0, 0.0);
 
-    orc_slot slots[7];
-    int32_t *nodes[7];
-    int64_t *gids[7];
-    for (int k = 0; k < 7; ++k) {
+    orc_slot slots[NK];
+    int32_t *nodes[NK];
+    int64_t *gids[NK];
+    for (int k = 0; k < NK; ++k) {
         orc_slot *s = &slots[k];
         s->kind = k;
         s->n = below(3 * n_nodes + 1);
@@ -101,20 +102,20 @@ static int run_case(int n_nodes, int vmode, int shared, int analytic, int pade, 
             s->st[j] = j < kStates[k] ? dalloc(s->n, 0.0, 0.0) : NULL;
             s->par[j] = par[j];
         }
-        s->ica = (k == ORC_CAHVA || k == ORC_CAPUMP) ? dalloc(s->n, 0.0, 0.0) : NULL;
+        s->ica = (k == ORC_CAHVA || k == ORC_CAPUMP || k == ORC_CABUF) ? dalloc(s->n, 0.0, 0.0) : NULL;
     }
 
-    orc_init(&gl, &nd, slots, 7);
-    int ok = orc_run(&gl, &nd, slots, 7, 0, nsteps, 0.025, vmode) == 0;
+    orc_init(&gl, &nd, slots, NK);
+    int ok = orc_run(&gl, &nd, slots, NK, 0, nsteps, 0.025, vmode) == 0;
     double I, G;
-    for (int k = 0; k < 7; ++k)
+    for (int k = 0; k < NK; ++k)
         if (slots[k].n > 0) orc_instance_current(&gl, &nd, &slots[k], slots[k].n - 1, -30.0, &I, &G);
     ok = ok && finite_all(nd.v, n_nodes) && finite_all(nd.rhs, n_nodes) && finite_all(nd.d, n_nodes) &&
          finite_all(nd.cai, n_nodes);
-    for (int k = 0; k < 7; ++k)
+    for (int k = 0; k < NK; ++k)
         for (int j = 0; j < kStates[k]; ++j) ok = ok && finite_all(slots[k].st[j], slots[k].n);
 
-    for (int k = 0; k < 7; ++k) {
+    for (int k = 0; k < NK; ++k) {
         for (int j = 0; j < 4; ++j) {
             free(slots[k].st[j]);
             free((void *)slots[k].par[j]);

@@ -759,3 +759,71 @@ def test_shared_calcium_capump_channel_feeds_the_linear_pool(oracle):
     sb = [i for i, sl in enumerate(wb.slots) if sl.kind == "cahva"][0]
     assert np.array_equal(a.v, b.v)
     assert np.array_equal(a.cai_node[wb.slots[sb].node], b.states[sb]["cai"])
+
+
+# ------------------- derivimplicit on a coupled 2x2 system: cabuf (F3) --
+def _cabuf_F(c, b, ica, btot=0.05, kon=100.0, koff=0.1, kappa=None, tau=80.0, c0r=5e-5):
+    bind = kon * c * (btot - b) - koff * b
+    return np.array([-kappa * ica - bind - (c - c0r) / tau, bind])
+
+
+def test_cabuf_newton_solves_the_coupled_implicit_equation(oracle):
+    """Free and buffer-bound calcium, implicit Euler: the Newton steps reach
+    the root of the 2x2 system; scipy's hybrid root finder on the same
+    equations, written here from the rates, agrees."""
+    from scipy.optimize import root
+    w = _single("cabuf", -65.0, 1)
+    M = oracle.Model(w)
+    kappa = oracle.ca_kappa(0.05, 0.1)
+    for ica, c, b in ((-2e-3, 5e-5, 2e-3), (-2e-2, 3e-3, 0.04), (0.0, 2e-3, 1e-3), (-5e-4, 1e-6, 0.0)):
+        gc, gb, res = M.cabuf_step(ica, c, b, 6)
+        assert res <= 1e-18
+        G = lambda x: x - np.array([c, b]) - 0.025 * _cabuf_F(x[0], x[1], ica, kappa=kappa)
+        ref = root(G, [c, b], method="hybr", tol=1e-16).x
+        assert abs(gc - ref[0]) <= 1e-13 * ref[0] and abs(gb - ref[1]) <= 1e-13 * max(ref[1], 1e-6)
+
+
+def test_cabuf_newton_converges_quadratically(oracle):
+    """Newton with the exact Jacobian squares the error each step; a wrong
+    Jacobian entry would leave linear convergence."""
+    w = _single("cabuf", -65.0, 1)
+    M = oracle.Model(w)
+    res = [M.cabuf_step(-5e-2, 1e-3, 1e-3, k, dt=1.0)[2] for k in (1, 2, 3)]
+    assert res[0] > 1e-8
+    assert res[1] <= 50.0 * res[0] ** 2 / 5e-3 and res[2] <= 50.0 * res[1] ** 2 / 5e-3 + 1e-18
+    assert res[2] < 1e-6 * res[0]
+
+
+def test_cabuf_without_buffer_is_linear_implicit_euler(oracle):
+    """btot = 0 and no bound calcium: the pool is linear, and implicit Euler
+    has the closed form c = (c_old + dt(-kappa ica + cai0/tau))/(1 + dt/tau)."""
+    w = _single("cabuf", -65.0, 1, buf_total=0.0)
+    M = oracle.Model(w)
+    kappa = oracle.ca_kappa(0.05, 0.1)
+    gc, gb, _ = M.cabuf_step(-3e-3, 1e-4, 0.0, 4)
+    ref = (1e-4 + 0.025 * (kappa * 3e-3 + 5e-5 / 80.0)) / (1.0 + 0.025 / 80.0)
+    assert gb == 0.0 and abs(gc - ref) <= 2e-16 * ref
+
+
+def test_cabuf_conserves_calcium_without_influx_or_extrusion(oracle):
+    """ica = 0 and no extrusion (tau_ca very large): binding only moves
+    calcium between free and bound, so c + b is kept, and the pool settles at
+    the binding equilibrium b/(btot - b) = kon c/koff."""
+    w = _single("cabuf", -65.0, 1, tau_ca=1e30)
+    M = oracle.Model(w)
+    c, b = 2e-3, 1e-3
+    total = c + b
+    for _ in range(400):
+        c, b, _ = M.cabuf_step(0.0, c, b, 4)
+        assert abs(c + b - total) <= 1e-15 * total
+    assert abs(b * 0.1 - 100.0 * c * (0.05 - b)) <= 1e-12 * 100.0 * c * 0.05
+    assert abs(M.cabuf_bound(c) - b) <= 1e-12 * b
+
+
+def test_cabuf_rest_is_a_fixed_point(oracle):
+    w = _single("cabuf", -65.0, 1)
+    M = oracle.Model(w)
+    b0 = M.cabuf_bound(5e-5)
+    assert abs(b0 - 0.05 * 5e-5 / (5e-5 + 1e-3)) <= 1e-17
+    gc, gb, res = M.cabuf_step(0.0, 5e-5, b0, 4)
+    assert abs(gc - 5e-5) <= 1e-20 and abs(gb - b0) <= 1e-18
