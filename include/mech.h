@@ -41,6 +41,12 @@
  *               implicit Euler equation is solved by Newton's method with the
  *               analytic derivative (derivimplicit, section 5.2)
  *                                                           params gbar; states m, h, cai
+ *   MECH_CABUF  density, Ca-HVA gates with free calcium cai and calcium
+ *               bound to a buffer, cab (binding kon cai (btot - cab) -
+ *               koff cab, cai relaxing to cai0 with tau_ca); the pool's two
+ *               coupled implicit Euler equations are solved by Newton's
+ *               method on the 2x2 system (derivimplicit, section 5.2)
+ *                                                           params gbar; states m, h, cai, cab
  *
  * Units: mV, ms, mA/cm2 and S/cm2 for density mechanisms, nA and uS for the
  * synapse (scaled by 100/area into the node vectors), um2, uF/cm2, mM, degC,
@@ -91,7 +97,10 @@ enum {
     MECH_ERR_NONFINITE = -6    /* a kernel produced a non-finite STATE          */
 };
 
-enum { MECH_PAS = 0, MECH_HH = 1, MECH_IH = 2, MECH_CAHVA = 3, MECH_SYN = 4, MECH_KMARKOV = 5, MECH_CAPUMP = 6 };
+enum {
+    MECH_PAS = 0, MECH_HH = 1, MECH_IH = 2, MECH_CAHVA = 3, MECH_SYN = 4, MECH_KMARKOV = 5, MECH_CAPUMP = 6,
+    MECH_CABUF = 7
+};
 enum { MECH_FP64 = 0, MECH_FP32_MIXED = 1 };
 /* voltage provision between the current and the state update of a step
  * (section 8, Table 3 "Other"):
@@ -196,7 +205,7 @@ int mech_bind_clamp(mech_ctx *ctx, const double *off, const double *amp, const d
 /* Set the RANGE parameter `name` of type slot `type_slot` from host memory:
  * n == 1 broadcasts one value, n == count gives one value per instance in the
  * caller's order.  Names: pas g,e; hh gnabar,gkbar,gl,el; ih gbar;
- * cahva gbar; syn weight; kmarkov gbar; capump gbar.                       */
+ * cahva gbar; syn weight; kmarkov gbar; capump gbar; cabuf gbar.          */
 int mech_set_params(mech_ctx *ctx, int type_slot, const char *name, const double *host_vals, int64_t n);
 
 /* Set a global: celsius, ena, ek, eh, cao, cai0, tau_ca, ca_gamma, ca_depth,
@@ -209,14 +218,16 @@ int mech_set_params(mech_ctx *ctx, int type_slot, const char *name, const double
  *                         (1,1) Pade approximant (1 - y/2)/(1 + y/2),
  *                         y = dt/tau (requires y < 2 to keep gates in
  *                         [0, 1]);
- * the pump of MECH_CAPUMP: pump_vmax (mM/ms), pump_kp (mM),
+ * the pump of MECH_CAPUMP: pump_vmax (mM/ms), pump_kp (mM); the buffer of
+ * MECH_CABUF: buf_total (mM), buf_kon (1/(mM ms)), buf_koff (1/ms);
  * newton_iters (1..16 Newton steps per implicit Euler step, default 4);
  * and shared_ca (0 or 1, default 0): calcium as a per-node ion, the USEION
- * dependency between mechanisms (section 3).  Every MECH_CAHVA and
- * MECH_CAPUMP instance then reads its node's cai and adds its calcium
+ * dependency between mechanisms (section 3).  Every MECH_CAHVA, MECH_CAPUMP
+ * and MECH_CABUF instance then reads its node's cai and adds its calcium
  * current to the node's total ica; one pool per node relaxes by the linear
  * pool law, cai_inf = cai0 - kappa tau_ca ica with time constant tau_ca,
- * from that total; the instances' own pools are left untouched.  Needs a
+ * from that total; the instances' own pools (cabuf's cab too) are left
+ * untouched.  Needs a
  * calcium type (MECH_ERR_STATE otherwise); set it before mech_init, which
  * sets every node's cai to cai0.  The node arrays are read with
  * mech_get_state(ctx, -1, "cai" or "ica", ...).  Changing a global drops
@@ -265,7 +276,7 @@ int mech_get_launch(const mech_ctx *ctx, int *block, int *tile_instances, int *t
  * besides the chosen shape.                                                */
 int mech_autotune(mech_ctx *ctx, double dt, int vmode, int nsteps, int reps, double *best_ms_per_step);
 
-/* Copy STATE `name` (or "ica" for Ca-HVA and capump) of type slot `type_slot` to /
+/* Copy STATE `name` (or "ica" for Ca-HVA, capump and cabuf) of type slot `type_slot` to /
  * from host doubles in the caller's instance order; n must equal count.
  * type_slot -1 names the per-node calcium ion instead: "cai" (mM) or "ica"
  * (mA/cm2, the last current update's total), n == n_nodes, present when a

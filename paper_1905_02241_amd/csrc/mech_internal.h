@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "mech.h"
+
 namespace mech {
 
 constexpr int kMaxSlots = 8;
@@ -18,6 +20,8 @@ constexpr int kMaxTileNodes = 2048;  // LDS: 32 B per node -> 64 KiB per block (
 
 // Step-phase flags of the fused kernel.
 enum : int { kDoState = 1, kDoCur = 2 };
+// Kinds that carry a calcium current and a pool (Ca-HVA gates).
+constexpr bool is_ca_kind(int kind) { return kind == MECH_CAHVA || kind == MECH_CAPUMP || kind == MECH_CABUF; }
 
 // One mechanism type as the kernels see it (internal, node-sorted order).
 // Storage types: S = state type (double or float); conductance PARAMETERs
@@ -56,6 +60,8 @@ struct GlobDev {
     double pump_vmax, pump_kp, pump_rest;   // pump_rest = vmax cai0/(cai0 + kp)
     int newton_iters;
     int shared_ca;             // calcium as a per-node ion (NodesDev::cai, ica)
+    double buf_total, buf_kon, buf_koff;   // cabuf's buffer (mM, 1/(mM ms), 1/ms)
+    double inv_tau_ca;                     // 1/tau_ca
 };
 
 struct NodesDev {
@@ -118,6 +124,7 @@ struct FusedArgs {
     int *err;
     GlobDev g;
     NodesDev nd;
+    int has_ext;               // a type only the extended instantiations handle (cabuf)
 };
 
 struct PlainArgs {

@@ -261,6 +261,36 @@ __device__ __forceinline__ void capump_pool(const GlobDev &g, float ica, float &
     cai = c;
 }
 
+// cabuf pool: free calcium c and buffer-bound calcium b, binding
+// kon c (btot - b) - koff b, relaxation of c to cai0 with tau_ca.  Implicit
+// Euler G(c, b) = (c - c_old - dt F_c, b - b_old - dt F_b) = 0 by a fixed
+// number of Newton steps from the old state; each step applies the inverse
+// of the 2x2 Jacobian I - dt dF/d(c, b) in closed form (adjugate over the
+// determinant, which is 1 + dt (x + y + 1/tau_ca) + dt^2 y/tau_ca > 1 with
+// x = kon (btot - b) >= 0 and y = kon c + koff > 0, so no pivot is needed).
+__device__ __forceinline__ double recip(double x) { return rcp_d(x); }
+__device__ __forceinline__ float recip(float x) { return 1.0f / x; }
+template <class T>
+__device__ __forceinline__ void cabuf_pool(const GlobDev &g, T ica, T &cai, T &cab) {
+    const T c0 = cai, b0 = cab, infl = -(T)g.kappa * ica, dt = (T)g.dt;
+    const T kon = (T)g.buf_kon, koff = (T)g.buf_koff, btot = (T)g.buf_total;
+    const T cai_rest = (T)g.cai0, itau = (T)g.inv_tau_ca;
+    T c = c0, b = b0;
+    for (int it = 0; it < g.newton_iters; ++it) {
+        const T x = kon * (btot - b), y = kon * c + koff;
+        const T bind = c * x - koff * b;
+        const T gc = c - c0 - dt * (infl - bind - (c - cai_rest) * itau);
+        const T gb = b - b0 - dt * bind;
+        // J = [[1 + dt (x + 1/tau), -dt y], [-dt x, 1 + dt y]]
+        const T j00 = T(1) + dt * (x + itau), j01 = -dt * y, j10 = -dt * x, j11 = T(1) + dt * y;
+        const T r = recip(j00 * j11 - j01 * j10);
+        c -= (j11 * gc - j01 * gb) * r;
+        b -= (j00 * gb - j10 * gc) * r;
+    }
+    cai = c;
+    cab = b;
+}
+
 // Synapse decay: A <- A e^{-dt/tau}; in FP32 A <- A - A (1 - e^{-dt/tau}),
 // which keeps the rounding of the factor from being amplified by tau/dt.
 __device__ __forceinline__ void syn_decay(double *x, const GlobDev &g) {
@@ -463,6 +493,32 @@ __device__ __forceinline__ void instance(const SlotDev &sl, int i, double v, con
                 st<NT>(CAI + i, cai);
             }
         }
+    } else if constexpr (KIND == MECH_CABUF) {
+        S *M = (S *)sl.st[0], *H = (S *)sl.st[1], *CAI = (S *)sl.st[2], *CAB = (S *)sl.st[3];
+        S *ICA = (S *)sl.ica;
+        S m = ld<NT>(M + i), h = ld<NT>(H + i), cai = ld<NT>(CAI + i);
+        if (PH & kDoState) {
+            ca_gates(v, g, m, h);
+            if (!FOLD) {
+                S cab = ld<NT>(CAB + i);
+                cabuf_pool<S>(g, ld<NT>(ICA + i), cai, cab);
+                flag |= bad(cab);
+                st<NT>(CAI + i, cai); st<NT>(CAB + i, cab);
+            }
+            flag |= bad(m) | bad(h) | bad(cai);
+            st<NT>(M + i, m); st<NT>(H + i, h);
+        }
+        if (PH & kDoCur) {
+            const S gbar = ld<NT>((const S *)sl.par[0] + i);
+            const S ica = (S)ca_cur<S>(v, m, h, cai, gbar, g, ci, cg);
+            st<NT>(ICA + i, ica);
+            if (FOLD) {
+                S cab = ld<NT>(CAB + i);
+                cabuf_pool<S>(g, ica, cai, cab);
+                flag |= bad(cai) | bad(cab);
+                st<NT>(CAI + i, cai); st<NT>(CAB + i, cab);
+            }
+        }
     } else if constexpr (KIND == MECH_SYN) {
         S x[4];
 #pragma unroll
@@ -486,9 +542,10 @@ __device__ __forceinline__ void instance(const SlotDev &sl, int i, double v, con
     }
 }
 
-// A cahva or capump instance under the shared calcium ion: its gates, and its
-// current at the node's cai (ica returned for the node's total); the pool
-// is the node's (ion_pool), not the instance's.
+// A cahva, capump or cabuf instance under the shared calcium ion: its gates,
+// and its current at the node's cai (ica returned for the node's total); the
+// pool is the node's (ion_pool), not the instance's, and a cabuf instance's
+// own free and bound calcium stay as they are.
 template <class S, int PH, bool NT = false>
 __device__ __forceinline__ void ca_shared(const SlotDev &sl, int i, double v, double cai, const GlobDev &g,
                                           double &ci, double &cg, double &ica, int &flag) {
@@ -544,7 +601,7 @@ __global__ __launch_bounds__(256) void k_plain_cur(PlainArgs a) {
     if (i < a.slot.n) {
         ni = a.slot.ni[i];
         const double v = a.nd.v[ni];
-        if ((KIND == MECH_CAHVA || KIND == MECH_CAPUMP) && a.g.shared_ca) {
+        if (is_ca_kind(KIND) && a.g.shared_ca) {
             double ica;
             ca_shared<S, kDoCur>(a.slot, i, v, a.nd.cai[ni], a.g, ci, cg, ica, flag);
             unsafeAtomicAdd(&a.nd.ica[ni], ica);
@@ -579,7 +636,7 @@ __global__ __launch_bounds__(256) void k_plain_state(PlainArgs a) {
     if (i < a.slot.n) {
         const double v = a.nd.v[a.slot.ni[i]];
         double ci, cg;
-        if ((KIND == MECH_CAHVA || KIND == MECH_CAPUMP) && a.g.shared_ca) {
+        if (is_ca_kind(KIND) && a.g.shared_ca) {
             double ica;
             ca_shared<S, kDoState>(a.slot, i, v, 0.0, a.g, ci, cg, ica, flag);
         } else {
@@ -619,10 +676,13 @@ __global__ __launch_bounds__(256) void k_init(PlainArgs a) {
         st[0][i] = (S)m; st[1][i] = (S)h; st[2][i] = (S)n;
     } else if constexpr (KIND == MECH_IH) {
         st[0][i] = (S)ih_inf(v);
-    } else if constexpr (KIND == MECH_CAHVA || KIND == MECH_CAPUMP) {
+    } else if constexpr (is_ca_kind(KIND)) {
         double m, h;
         ca_inf(v, m, h);
         st[0][i] = (S)m; st[1][i] = (S)h; st[2][i] = (S)a.g.cai0;
+        // cabuf: the bound calcium in equilibrium with cai0
+        if (KIND == MECH_CABUF)
+            st[3][i] = (S)(a.g.buf_total * a.g.buf_kon * a.g.cai0 / (a.g.buf_kon * a.g.cai0 + a.g.buf_koff));
         ((S *)a.slot.ica)[i] = (S)0;
     } else if constexpr (KIND == MECH_KMARKOV) {
         double m, h, n;
@@ -992,15 +1052,15 @@ hipError_t cable_allow_lds(size_t bytes) {
 // LDS per tile node: v, 100/area, rhs and d accumulators (4 doubles); under
 // the shared calcium ion also the node's cai and its calcium current
 // accumulator (6 doubles).
-template <class S, int KIND, int PH, bool NT, bool ION>
+template <class S, int KIND, int PH, bool NT, bool EXT>
 __device__ __forceinline__ void tile_slot(const SlotDev &sl, int lo, int hi, int nlo, const double *vl,
                                           const double *sc, double *ar, double *ad, const double *cl, double *ai,
-                                          const GlobDev &g, long long k, int &flag) {
+                                          const GlobDev &g, long long k, bool ion, int &flag) {
     for (int i = lo + (int)threadIdx.x; i < hi; i += (int)blockDim.x) {
         // an identity slot (instance i on node i) needs no index load
         const int j = (sl.identity ? i : ld<NT>(sl.ni + i)) - nlo;
         double ci, cg;
-        if constexpr (ION && (KIND == MECH_CAHVA || KIND == MECH_CAPUMP)) {
+        if (EXT && is_ca_kind(KIND) && ion) {
             double ica;
             ca_shared<S, PH, NT>(sl, i, vl[j], cl[j], g, ci, cg, ica, flag);
             if (PH & kDoCur) atomicAdd(&ai[j], ica);
@@ -1029,14 +1089,15 @@ __device__ __forceinline__ int tile_of(int b, int T, int xcd_order) {
     return x * q + min(x, r) + j;
 }
 
-// ION: the shared calcium ion (its own instantiations, so the others keep
-// their register budget).
-template <class S, int PH, int VM, bool NT, bool ION = false>
+// EXT: the extended instantiations, which add the buffered-calcium type and
+// the shared calcium ion (a run-time switch there).  They are kept apart so
+// that the default instantiations keep their register budget.
+template <class S, int PH, int VM, bool NT, bool EXT = false>
 __global__ __launch_bounds__(1024) void k_fused(FusedArgs a, int tn) {
     extern __shared__ double lds[];
     double *vl = lds, *sc = lds + tn, *ar = lds + 2 * tn, *ad = lds + 3 * tn;
     double *cl = lds + 4 * tn, *ai = lds + 5 * tn;
-    constexpr bool ion = ION;
+    const bool ion = EXT && a.g.shared_ca;
     const long long k = *a.kdev + a.kofs;
     int flag = 0;
     for (int b = blockIdx.x; b < a.n_tiles; b += gridDim.x) {
@@ -1050,7 +1111,7 @@ __global__ __launch_bounds__(1024) void k_fused(FusedArgs a, int tn) {
                 ar[j] = 0.0;
                 ad[j] = 0.0;
                 if (a.has_syn) sc[j] = 1e2 / a.nd.area[nlo + j];
-                if constexpr (ion) {
+                if (ion) {
                     cl[j] = a.nd.cai[nlo + j];
                     ai[j] = 0.0;
                 }
@@ -1062,14 +1123,17 @@ __global__ __launch_bounds__(1024) void k_fused(FusedArgs a, int tn) {
             const int lo = r0[1 + s], hi = r1[1 + s];
             switch (sl.kind) {
             case MECH_PAS:
-                if (PH & kDoCur) tile_slot<S, MECH_PAS, PH, NT, ION>(sl, lo, hi, nlo, vl, sc, ar, ad, cl, ai, a.g, k, flag);
+                if (PH & kDoCur) tile_slot<S, MECH_PAS, PH, NT, EXT>(sl, lo, hi, nlo, vl, sc, ar, ad, cl, ai, a.g, k, ion, flag);
                 break;
-            case MECH_HH: tile_slot<S, MECH_HH, PH, NT, ION>(sl, lo, hi, nlo, vl, sc, ar, ad, cl, ai, a.g, k, flag); break;
-            case MECH_IH: tile_slot<S, MECH_IH, PH, NT, ION>(sl, lo, hi, nlo, vl, sc, ar, ad, cl, ai, a.g, k, flag); break;
-            case MECH_CAHVA: tile_slot<S, MECH_CAHVA, PH, NT, ION>(sl, lo, hi, nlo, vl, sc, ar, ad, cl, ai, a.g, k, flag); break;
-            case MECH_SYN: tile_slot<S, MECH_SYN, PH, NT, ION>(sl, lo, hi, nlo, vl, sc, ar, ad, cl, ai, a.g, k, flag); break;
-            case MECH_KMARKOV: tile_slot<S, MECH_KMARKOV, PH, NT, ION>(sl, lo, hi, nlo, vl, sc, ar, ad, cl, ai, a.g, k, flag); break;
-            case MECH_CAPUMP: tile_slot<S, MECH_CAPUMP, PH, NT, ION>(sl, lo, hi, nlo, vl, sc, ar, ad, cl, ai, a.g, k, flag); break;
+            case MECH_HH: tile_slot<S, MECH_HH, PH, NT, EXT>(sl, lo, hi, nlo, vl, sc, ar, ad, cl, ai, a.g, k, ion, flag); break;
+            case MECH_IH: tile_slot<S, MECH_IH, PH, NT, EXT>(sl, lo, hi, nlo, vl, sc, ar, ad, cl, ai, a.g, k, ion, flag); break;
+            case MECH_CAHVA: tile_slot<S, MECH_CAHVA, PH, NT, EXT>(sl, lo, hi, nlo, vl, sc, ar, ad, cl, ai, a.g, k, ion, flag); break;
+            case MECH_SYN: tile_slot<S, MECH_SYN, PH, NT, EXT>(sl, lo, hi, nlo, vl, sc, ar, ad, cl, ai, a.g, k, ion, flag); break;
+            case MECH_KMARKOV: tile_slot<S, MECH_KMARKOV, PH, NT, EXT>(sl, lo, hi, nlo, vl, sc, ar, ad, cl, ai, a.g, k, ion, flag); break;
+            case MECH_CAPUMP: tile_slot<S, MECH_CAPUMP, PH, NT, EXT>(sl, lo, hi, nlo, vl, sc, ar, ad, cl, ai, a.g, k, ion, flag); break;
+            case MECH_CABUF:
+                if constexpr (EXT) tile_slot<S, MECH_CABUF, PH, NT, EXT>(sl, lo, hi, nlo, vl, sc, ar, ad, cl, ai, a.g, k, ion, flag);
+                break;
             default: break;
             }
         }
@@ -1082,7 +1146,7 @@ __global__ __launch_bounds__(1024) void k_fused(FusedArgs a, int tn) {
                 a.nd.d[n] = dd;
                 if (VM == MECH_V_ISOLATED) a.nd.v[n] = isolated_v(a.nd, a.g, n, vl[j], r, dd);
                 if (VM == MECH_V_CLAMP) a.nd.v[n] = clamp_v(a.nd, n, (double)(k + 1) * a.g.dt);
-                if constexpr (ion) {
+                if (ion) {
                     // the node's pool advances with this step's calcium current,
                     // as a cahva instance's own pool does in this pass
                     double c = cl[j];
@@ -1188,6 +1252,7 @@ static hipError_t init_t(const PlainArgs &a, hipStream_t s) {
     case MECH_SYN: k_init<S, MECH_SYN><<<gr, 256, 0, s>>>(a); break;
     case MECH_KMARKOV: k_init<S, MECH_KMARKOV><<<gr, 256, 0, s>>>(a); break;
     case MECH_CAPUMP: k_init<S, MECH_CAPUMP><<<gr, 256, 0, s>>>(a); break;
+    case MECH_CABUF: k_init<S, MECH_CABUF><<<gr, 256, 0, s>>>(a); break;
     default: break;
     }
     return hipGetLastError();
@@ -1208,6 +1273,7 @@ static hipError_t cur_t(const PlainArgs &a, hipStream_t s) {
     case MECH_SYN: k_plain_cur<S, MECH_SYN><<<gr, 256, 0, s>>>(a); break;
     case MECH_KMARKOV: k_plain_cur<S, MECH_KMARKOV><<<gr, 256, 0, s>>>(a); break;
     case MECH_CAPUMP: k_plain_cur<S, MECH_CAPUMP><<<gr, 256, 0, s>>>(a); break;
+    case MECH_CABUF: k_plain_cur<S, MECH_CABUF><<<gr, 256, 0, s>>>(a); break;
     default: break;
     }
     return hipGetLastError();
@@ -1227,6 +1293,7 @@ static hipError_t state_t(const PlainArgs &a, hipStream_t s) {
     case MECH_SYN: k_plain_state<S, MECH_SYN><<<gr, 256, 0, s>>>(a); break;
     case MECH_KMARKOV: k_plain_state<S, MECH_KMARKOV><<<gr, 256, 0, s>>>(a); break;
     case MECH_CAPUMP: k_plain_state<S, MECH_CAPUMP><<<gr, 256, 0, s>>>(a); break;
+    case MECH_CABUF: k_plain_state<S, MECH_CABUF><<<gr, 256, 0, s>>>(a); break;
     default: break;  // pas has no STATE
     }
     return hipGetLastError();
@@ -1236,31 +1303,31 @@ hipError_t launch_plain_state(bool fp32, const PlainArgs &a, hipStream_t s) {
     return fp32 ? state_t<float>(a, s) : state_t<double>(a, s);
 }
 
-template <class S, int PH, bool NT, bool ION>
+template <class S, int PH, bool NT, bool EXT>
 static hipError_t fused_vm(int vmode, const FusedArgs &a, int grid, int block, size_t lds, int tn,
                            hipStream_t s) {
     switch (vmode) {
-    case MECH_V_CLAMP: k_fused<S, PH, MECH_V_CLAMP, NT, ION><<<grid, block, lds, s>>>(a, tn); break;
-    case MECH_V_ISOLATED: k_fused<S, PH, MECH_V_ISOLATED, NT, ION><<<grid, block, lds, s>>>(a, tn); break;
-    default: k_fused<S, PH, MECH_V_EXTERNAL, NT, ION><<<grid, block, lds, s>>>(a, tn); break;
+    case MECH_V_CLAMP: k_fused<S, PH, MECH_V_CLAMP, NT, EXT><<<grid, block, lds, s>>>(a, tn); break;
+    case MECH_V_ISOLATED: k_fused<S, PH, MECH_V_ISOLATED, NT, EXT><<<grid, block, lds, s>>>(a, tn); break;
+    default: k_fused<S, PH, MECH_V_EXTERNAL, NT, EXT><<<grid, block, lds, s>>>(a, tn); break;
     }
     return hipGetLastError();
 }
-template <class S, bool NT, bool ION = false>
+template <class S, bool NT, bool EXT = false>
 static hipError_t fused_t(int phases, int vmode, const FusedArgs &a, int grid, int block, size_t lds, int tn,
                           hipStream_t s) {
     switch (phases) {
-    case kDoCur: return fused_vm<S, kDoCur, NT, ION>(vmode, a, grid, block, lds, tn, s);
+    case kDoCur: return fused_vm<S, kDoCur, NT, EXT>(vmode, a, grid, block, lds, tn, s);
     case kDoState:
-        k_fused<S, kDoState, MECH_V_EXTERNAL, NT, ION><<<grid, block, lds, s>>>(a, tn);
+        k_fused<S, kDoState, MECH_V_EXTERNAL, NT, EXT><<<grid, block, lds, s>>>(a, tn);
         return hipGetLastError();
-    default: return fused_vm<S, kDoCur | kDoState, NT, ION>(vmode, a, grid, block, lds, tn, s);
+    default: return fused_vm<S, kDoCur | kDoState, NT, EXT>(vmode, a, grid, block, lds, tn, s);
     }
 }
 size_t fused_lds_bytes(int tile_nodes, bool ion) { return (ion ? 6 : 4) * sizeof(double) * (size_t)tile_nodes; }
 
-// Lets every fused instantiation of the shared calcium ion take up to
-// `bytes` of dynamic LDS.
+// Lets every extended fused instantiation (those that run the shared
+// calcium ion) take up to `bytes` of dynamic LDS.
 hipError_t fused_allow_lds(size_t bytes) {
     const int b = (int)bytes;
     const void *fns[] = {
@@ -1295,8 +1362,9 @@ hipError_t launch_fused(bool fp32, int phases, int vmode, const FusedArgs &a, in
                         hipStream_t s) {
     if (a.n_tiles == 0 || grid == 0) return hipSuccess;
     const size_t lds_bytes = fused_lds_bytes(tn, a.g.shared_ca != 0);
-    // the shared calcium ion has temporal-hint instantiations only
-    if (a.g.shared_ca)
+    // the extended set (shared calcium ion, cabuf) has temporal-hint
+    // instantiations only
+    if (a.g.shared_ca || a.has_ext)
         return fp32 ? fused_t<float, false, true>(phases, vmode, a, grid, block, lds_bytes, tn, s)
                     : fused_t<double, false, true>(phases, vmode, a, grid, block, lds_bytes, tn, s);
     if (a.nontemporal)

@@ -38,7 +38,7 @@ struct KindDesc {
     double defaults[kMaxParams];
 };
 
-const KindDesc kKinds[7] = {
+const KindDesc kKinds[8] = {
     {"pas", false, 0, {}, 2, {{"g", false}, {"e", false}}, {1e-3, -70.0}},
     {"hh", false, 3, {"m", "h", "n"}, 4,
      {{"gnabar", false}, {"gkbar", false}, {"gl", false}, {"el", false}}, {0.12, 0.036, 0.0003, -54.3}},
@@ -47,6 +47,7 @@ const KindDesc kKinds[7] = {
     {"syn", true, 4, {"A_ampa", "B_ampa", "A_nmda", "B_nmda"}, 1, {{"weight", true}}, {1.0}},
     {"kmarkov", false, 3, {"C1", "C2", "O"}, 1, {{"gbar", false}}, {0.01}},
     {"capump", false, 3, {"m", "h", "cai"}, 1, {{"gbar", false}}, {5e-5}},
+    {"cabuf", false, 4, {"m", "h", "cai", "cab"}, 1, {{"gbar", false}}, {5e-5}},
 };
 
 struct Globals {
@@ -59,6 +60,7 @@ struct Globals {
     int analytic_conductance = 0;   // closed-form di/dv instead of the finite difference
     int pade_cnexp = 0;             // (1,1) Pade approximant of the cnexp exponential
     double pump_vmax = 1e-4, pump_kp = 1e-3;
+    double buf_total = 0.05, buf_kon = 100.0, buf_koff = 0.1;
     int newton_iters = 4;
     int shared_ca = 0;              // calcium as a per-node ion
 };
@@ -311,7 +313,7 @@ void compute_layout(int64_t n_nodes, std::vector<SlotHost> &slots, int prec, Lay
             s.off_par[j] = off;
             off = align_up(off + (K.param[j].is_double ? 8 : ss) * (size_t)s.np);
         }
-        s.has_ica = s.kind == MECH_CAHVA || s.kind == MECH_CAPUMP;
+        s.has_ica = is_ca_kind(s.kind);
         if (s.has_ica) { s.off_ica = off; off = align_up(off + ss * (size_t)s.np); }
     }
     L.inst_end = off;
@@ -319,7 +321,7 @@ void compute_layout(int64_t n_nodes, std::vector<SlotHost> &slots, int prec, Lay
     L.off_err = off; off = align_up(off + 4);
     L.off_kdev = off; off = align_up(off + 8);
     L.has_ion = false;
-    for (auto &s : slots) L.has_ion |= s.kind == MECH_CAHVA || s.kind == MECH_CAPUMP;
+    for (auto &s : slots) L.has_ion |= is_ca_kind(s.kind);
     if (L.has_ion) { L.off_ion = off; off = align_up(off + 16 * (size_t)std::max<int64_t>(n_nodes, 1)); }
     L.max_tile_rows = 2 * ((total_inst + kMinTileBudget - 1) / kMinTileBudget) +
                       (n_nodes + kMinTileNodes - 1) / kMinTileNodes + 2;
@@ -428,6 +430,10 @@ GlobDev make_glob(const mech_ctx *c, double dt) {
     g.pump_vmax = G.pump_vmax;
     g.pump_kp = G.pump_kp;
     g.pump_rest = G.pump_vmax * (G.cai0 / (G.cai0 + G.pump_kp));
+    g.buf_total = G.buf_total;
+    g.buf_kon = G.buf_kon;
+    g.buf_koff = G.buf_koff;
+    g.inv_tau_ca = 1.0 / G.tau_ca;
     g.newton_iters = G.newton_iters;
     g.shared_ca = G.shared_ca && c->nd.cai ? 1 : 0;
     g.seed = G.event_seed;
@@ -578,6 +584,7 @@ FusedArgs fused_args(mech_ctx *c, const GlobDev &g, int kofs) {
     for (int s = 0; s < (int)c->slots.size(); ++s) a.slot[s] = slot_dev(c, s);
     a.n_slots = (int)c->slots.size();
     a.has_syn = c->has_syn ? 1 : 0;
+    for (const auto &h : c->slots) a.has_ext |= h.kind == MECH_CABUF && h.n > 0 ? 1 : 0;
     a.tiles = (const int *)(c->buf + c->L.off_tiles);
     a.n_tiles = (int)c->n_tiles;
     a.row = 1 + (int)c->slots.size();
@@ -706,7 +713,7 @@ static int validate_types(int64_t n_nodes, const mech_type_desc *types, int n_ty
     if (n_types > 0 && !types) return fail(nullptr, MECH_ERR_INVAL, "null types");
     if (prec != MECH_FP64 && prec != MECH_FP32_MIXED) return fail(nullptr, MECH_ERR_INVAL, "bad precision %d", prec);
     for (int s = 0; s < n_types; ++s) {
-        if (types[s].kind < MECH_PAS || types[s].kind > MECH_CAPUMP)
+        if (types[s].kind < MECH_PAS || types[s].kind > MECH_CABUF)
             return fail(nullptr, MECH_ERR_INVAL, "type %d: bad kind %d", s, types[s].kind);
         if (types[s].count < 0 || types[s].count >= (int64_t(1) << 31))
             return fail(nullptr, MECH_ERR_INVAL, "type %d: bad count", s);
@@ -998,7 +1005,8 @@ int mech_set_global(mech_ctx *c, const char *name, double value) {
         {"cai0", &G.cai0}, {"tau_ca", &G.tau_ca}, {"ca_gamma", &G.ca_gamma}, {"ca_depth", &G.ca_depth},
         {"e_syn", &G.e_syn}, {"mg", &G.mg}, {"tau_r_ampa", &G.tau_r_ampa}, {"tau_d_ampa", &G.tau_d_ampa},
         {"tau_r_nmda", &G.tau_r_nmda}, {"tau_d_nmda", &G.tau_d_nmda}, {"event_rate_hz", &G.event_rate_hz},
-        {"vthresh", &G.vthresh}, {"fd_dv", &G.fd_dv}, {"pump_vmax", &G.pump_vmax}, {"pump_kp", &G.pump_kp}};
+        {"vthresh", &G.vthresh}, {"fd_dv", &G.fd_dv}, {"pump_vmax", &G.pump_vmax}, {"pump_kp", &G.pump_kp},
+        {"buf_total", &G.buf_total}, {"buf_kon", &G.buf_kon}, {"buf_koff", &G.buf_koff}};
     if (!strcmp(name, "newton_iters")) {
         if (!(value >= 1.0 && value <= 16.0) || value != std::floor(value))
             return fail(c, MECH_ERR_INVAL, "newton_iters must be an integer in [1, 16]");
@@ -1016,7 +1024,7 @@ int mech_set_global(mech_ctx *c, const char *name, double value) {
     if (!strcmp(name, "shared_ca")) {
         if (value != 0.0 && value != 1.0) return fail(c, MECH_ERR_INVAL, "shared_ca must be 0 or 1");
         if (value != 0.0 && !c->nd.cai)
-            return fail(c, MECH_ERR_STATE, "shared_ca needs a cahva or capump type");
+            return fail(c, MECH_ERR_STATE, "shared_ca needs a cahva, capump or cabuf type");
         if (value != 0.0 && !c->ion_lds) {
             // the fused pass then keeps two more doubles per tile node in LDS
             HIPCHK(c, fused_allow_lds(fused_lds_bytes(kMaxTileNodes, true)));

@@ -18,14 +18,14 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libmech.so")
 
 OK, ERR_INVAL, ERR_RANGE, ERR_NOMEM, ERR_STATE, ERR_HIP, ERR_NONFINITE = 0, -1, -2, -3, -4, -5, -6
-KIND = {"pas": 0, "hh": 1, "ih": 2, "cahva": 3, "syn": 4, "kmarkov": 5, "capump": 6}
+KIND = {"pas": 0, "hh": 1, "ih": 2, "cahva": 3, "syn": 4, "kmarkov": 5, "capump": 6, "cabuf": 7}
 PREC = {"fp64": 0, "fp32": 1}
 VMODE = {"external": 0, "clamp": 1, "isolated": 2, "cable": 3}
 PATH = {"plain": 0, "batched": 1}
 GLOBAL_NAMES = ("celsius", "ena", "ek", "eh", "cao", "cai0", "tau_ca", "ca_gamma", "ca_depth", "e_syn",
                 "mg", "tau_r_ampa", "tau_d_ampa", "tau_r_nmda", "tau_d_nmda", "event_rate_hz", "event_seed",
                 "vthresh", "fd_dv", "analytic_conductance", "pade_cnexp", "pump_vmax", "pump_kp",
-                "newton_iters", "shared_ca")
+                "buf_total", "buf_kon", "buf_koff", "newton_iters", "shared_ca")
 
 # Exported symbols of include/mech.h (checked by the CPU tests).
 SYMBOLS = ("mech_required_bytes", "mech_alloc", "mech_bind_nodes", "mech_bind_clamp", "mech_cable_required_bytes",
@@ -275,7 +275,8 @@ class Mechanisms:
 
 STATE_NAMES = {"pas": (), "hh": ("m", "h", "n"), "ih": ("m",), "cahva": ("m", "h", "cai"),
                "syn": ("A_ampa", "B_ampa", "A_nmda", "B_nmda"), "kmarkov": ("C1", "C2", "O"),
-               "capump": ("m", "h", "cai")}
+               "capump": ("m", "h", "cai"), "cabuf": ("m", "h", "cai", "cab")}
+CA_KINDS = ("cahva", "capump", "cabuf")
 
 
 PROBE_OPS = {"copy": 0, "read": 1, "write": 2, "triad": 3}
@@ -373,7 +374,7 @@ def states_of(m: Mechanisms) -> List[Dict[str, np.ndarray]]:
     out = []
     for i, k in enumerate(m.kinds):
         d = {name: m.get_state(i, name) for name in STATE_NAMES[k]}
-        if k in ("cahva", "capump"):
+        if k in CA_KINDS:
             d["ica"] = m.get_state(i, "ica")
         out.append(d)
     return out

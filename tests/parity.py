@@ -10,7 +10,7 @@ Tolerances, each derived from the arithmetic it bounds:
                  the rhs bar over 1e-3 cm/dt + d >= 0.04 S/cm2 injects about
                  1e-9 mV per step, which the membrane's leak contracts
   FP32  gates and synapse states (nS)   |gpu - ref| <= 1e-5
-        cai                             |gpu - ref| <= 1e-4 |ref|
+        cai, cab (free and bound calcium) |gpu - ref| <= 1e-4 |ref|
         rhs, d   |gpu - ref| <= 2e-3 S_n
   node index handling and event decisions: exact (spike counts bit-exact in
   FP64).
@@ -77,7 +77,7 @@ def compare_states(got, M, prec, keep=None, label=""):
             g = got["states"][s][name]
             if keep is not None:
                 g = g[keep[s]]
-            if name == "cai":
+            if name in ("cai", "cab"):
                 tol = CAI_REL[prec] * np.abs(ref)
             else:
                 tol = rel * np.abs(ref) + ab + 1e-300

@@ -85,7 +85,7 @@ int main() {
             const int64_t count = (int64_t)(rng() % (3 * n_nodes));
             idx[s].resize((size_t)count);
             for (auto &x : idx[s]) x = (int32_t)(rng() % n_nodes);
-            types[s].kind = (int32_t)(rng() % 7);
+            types[s].kind = (int32_t)(rng() % 8);
             types[s].count = count;
             types[s].node_index = idx[s].data();
         }

@@ -86,6 +86,24 @@ def test_required_bytes_layout(lib):
     assert fp64 % 256 == 0 and fp64 > inst64
 
 
+def test_required_bytes_cabuf_layout(lib):
+    """The buffered-calcium type: index, four STATEs (m, h, cai, cab), gbar
+    and its calcium current per padded instance, and the per-node ion region
+    (cai, ica) that every calcium type brings."""
+    out = C.c_size_t()
+    d, keep = _descs([("cabuf", np.arange(1000))])
+    assert lib.mech_required_bytes(1000, d, 1, 0, C.byref(out)) == 0
+    fp64 = out.value
+    assert lib.mech_required_bytes(1000, d, 1, 1, C.byref(out)) == 0
+    fp32 = out.value
+    inst64 = 1024 * (4 + 4 * 8 + 8 + 8)
+    inst32 = 1024 * (4 + 4 * 4 + 4 + 4)
+    assert fp64 - fp32 == inst64 - inst32
+    assert fp64 > inst64 + 16 * 1000
+    d, keep = _descs([(8, np.arange(4))])
+    assert lib.mech_required_bytes(4, d, 1, 0, C.byref(out)) == mech.ERR_INVAL
+
+
 def test_validation_codes(lib):
     out = C.c_size_t()
     d, keep = _descs([(9, np.arange(4))])

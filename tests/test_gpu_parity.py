@@ -382,6 +382,46 @@ def test_implicit_kinds_isolated_fp64(path):
     compare_nodes(got, M, "fp64", label="implicit isolated")
 
 
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("prec", PRECS)
+def test_buffered_calcium_clamp(path, prec):
+    """cabuf (free and bound calcium, Newton on the 2x2 implicit Euler
+    system) beside capump and the other types, shuffled many-to-one index,
+    a strong clamp that drives calcium in well above rest."""
+    w = W.make_tiny(43, kinds=("pas", "hh", "cabuf", "capump", "syn"), per_node=2, nsteps=120)
+    w.clamp_amp[:] = 55.0
+    for s in w.slots:
+        if s.kind in ("cabuf", "capump"):
+            s.params["gbar"][:] *= 20.0
+    got, m = run_gpu(w, 120, path, prec)
+    M = run_oracle(w, 120)
+    cb = next(i for i, s in enumerate(w.slots) if s.kind == "cabuf")
+    cai0 = w.globals["cai0"]
+    assert np.max(M.states[cb]["cai"]) > 2.0 * cai0
+    # the buffer has taken up calcium beyond its rest value somewhere
+    b0 = M.cabuf_bound(cai0)
+    assert np.max(M.states[cb]["cab"]) > 1.05 * b0
+    ws = compare_states(got, M, prec, label="cabuf")
+    compare_nodes(got, M, prec, label="cabuf")
+    log(f"cabuf {path} {prec}: cai ratio {ws[f'{cb}:cabuf.cai'][0]:.3g}, cab ratio {ws[f'{cb}:cabuf.cab'][0]:.3g}")
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_buffered_calcium_isolated_fp64(path):
+    w = W.make_tiny(44, kinds=("pas", "hh", "cabuf", "syn"), n_nodes=40, syn_per_node=6.0,
+                    vmode="isolated", event_rate_hz=300.0, nsteps=500)
+    w.area[:] = np.linspace(100.0, 400.0, w.n_nodes)
+    w.slots[-1].params["weight"][:] *= 6.0
+    w.slots[2].params["gbar"][:] *= 20.0
+    w.globals["newton_iters"] = 3
+    got, m = run_gpu(w, 500, path, "fp64")
+    M = run_oracle(w, 500)
+    assert M.spikes.sum() > 0
+    assert np.array_equal(got["spikes"], M.spikes)
+    compare_states(got, M, "fp64", label="cabuf isolated")
+    compare_nodes(got, M, "fp64", label="cabuf isolated")
+
+
 # ------------------------------- per-node calcium ion, USEION (F4) --
 def compare_ion(m, M, prec, label):
     """Node cai against the oracle's at the calcium bar; node ica, a sum of
@@ -390,7 +430,7 @@ def compare_ion(m, M, prec, label):
     from tests.parity import CAI_REL
     A = np.zeros(M.n_nodes)
     for s, sl in enumerate(M.w.slots):
-        if sl.kind in ("cahva", "capump"):
+        if sl.kind in mech.CA_KINDS:
             np.add.at(A, np.asarray(sl.node), np.abs(M.ica[s]))
     cai, ica = m.ion("cai"), m.ion("ica")
     rc = float(np.max(np.abs(cai - M.cai_node) / (CAI_REL[prec] * np.abs(M.cai_node))))
@@ -434,6 +474,27 @@ def test_shared_calcium_isolated_fp64(path):
     compare_states(got, M, "fp64", label="shared ca isolated")
     compare_nodes(got, M, "fp64", label="shared ca isolated")
     compare_ion(m, M, "fp64", f"shared ca isolated {path}")
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("prec", PRECS)
+def test_shared_calcium_with_buffer_type(path, prec):
+    """Under the shared ion a cabuf instance reads its node's cai and adds
+    its current to the node's total like the other calcium types; its own
+    free and bound calcium stay at their initial values."""
+    w = W.make_tiny(95, kinds=("pas", "cahva", "cabuf", "syn"), per_node=2, nsteps=100)
+    for s in w.slots:
+        if s.kind in ("cahva", "cabuf"):
+            s.params["gbar"][:] *= 20.0
+    w.globals["shared_ca"] = 1
+    got, m = run_gpu(w, 100, path, prec)
+    M = run_oracle(w, 100)
+    assert np.max(M.cai_node) > 2.0 * w.globals["cai0"]
+    compare_states(got, M, prec, label="shared ca cabuf")
+    compare_nodes(got, M, prec, label="shared ca cabuf")
+    compare_ion(m, M, prec, f"shared ca cabuf {path} {prec}")
+    cb = next(i for i, s in enumerate(w.slots) if s.kind == "cabuf")
+    assert np.all(M.states[cb]["cai"] == w.globals["cai0"])
 
 
 def test_shared_calcium_ion_arrays_checkpoint():
@@ -556,6 +617,21 @@ def test_cable_with_shared_calcium_fp64(path):
     compare_states(got, M, "fp64", label="cable shared ca")
     compare_nodes(got, M, "fp64", label="cable shared ca")
     compare_ion(m, M, "fp64", f"cable shared ca {path}")
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_cable_with_buffered_calcium_fp64(path):
+    """The tree solve with cabuf instances at every compartment, each with
+    its own free and bound calcium (no shared ion)."""
+    w = W.make_cells(57, n_cells=4, lo=60, hi=300, kinds=("pas", "hh", "cabuf", "syn"), nsteps=300)
+    for s in w.slots:
+        if s.kind == "cabuf":
+            s.params["gbar"][:] *= 20.0
+    got, m = run_gpu(w, 300, path, "fp64", unit_nodes=64)
+    M = run_oracle(w, 300)
+    assert np.array_equal(got["spikes"], M.spikes)
+    compare_states(got, M, "fp64", label="cable cabuf")
+    compare_nodes(got, M, "fp64", label="cable cabuf")
 
 
 def test_cable_single_nodes_equal_isolated():
