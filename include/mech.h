@@ -121,8 +121,18 @@ enum { MECH_V_EXTERNAL = 0, MECH_V_CLAMP = 1, MECH_V_ISOLATED = 2, MECH_V_CABLE 
  *        eagerly (the paper's per-mechanism kernel structure);
  * BATCHED: per step one fused launch over a table of node tiles that runs
  *        state(k-1), events(k) and cur(k) of every type and provides the
- *        next voltage, with chunks of steps replayed from a HIP graph.      */
-enum { MECH_PATH_PLAIN = 0, MECH_PATH_BATCHED = 1 };
+ *        next voltage, with chunks of steps replayed from a HIP graph;
+ * RESIDENT: time-fused.  The BATCHED path's tiles, but each workgroup keeps
+ *        its tile (node data and every instance array) in LDS for up to
+ *        mech_set_resident_steps() steps and writes STATEs back once, so
+ *        STATEs do not cross HBM every step.  Same per-step arithmetic and
+ *        results as BATCHED up to the rounding order of rhs/d.  CLAMP and
+ *        ISOLATED modes only (MECH_ERR_INVAL otherwise); every tile must fit
+ *        the device's LDS per workgroup (160 KiB on gfx950; MECH_ERR_STATE
+ *        otherwise: lower tile_instances / tile_nodes with
+ *        mech_set_launch).  Between launches rhs/d are not written, only
+ *        after the last step, which is what mech_step returns.              */
+enum { MECH_PATH_PLAIN = 0, MECH_PATH_BATCHED = 1, MECH_PATH_RESIDENT = 2 };
 
 typedef struct mech_ctx mech_ctx;
 
@@ -268,6 +278,10 @@ int mech_set_launch(mech_ctx *ctx, int block, int tile_instances, int tile_nodes
                     int flags);
 int mech_get_launch(const mech_ctx *ctx, int *block, int *tile_instances, int *tile_nodes,
                     int *blocks_per_cu, int *flags);
+
+/* Steps per launch of the RESIDENT path (1..4096, default 32): STATEs
+ * cross HBM once per launch.                                              */
+int mech_set_resident_steps(mech_ctx *ctx, int steps_per_launch);
 
 /* Time every candidate launch shape of the BATCHED path on `nsteps` steps
  * (HIP events, median of `reps`), keep the fastest, and return its ms per

@@ -127,6 +127,45 @@ struct FusedArgs {
     int has_ext;               // a type only the extended instantiations handle (cabuf)
 };
 
+// Time-fused path: each workgroup stages one tile (its nodes and every
+// instance on them) in LDS, advances it over `nsub` steps there, and writes
+// it back once.  Per-slot shapes come from the kind table on the host.
+struct ResArgs {
+    long long k0;              // step of the launch's first current update
+    int nsub;                  // current updates (steps) in this launch
+    int first_state;           // state update of step k0-1 before the first current update
+    int last_state;            // state update at v_{k0+nsub} after the last one
+    int ss;                    // bytes of a stored STATE (8 FP64, 4 FP32-mixed)
+    int n_state[kMaxSlots], n_param[kMaxSlots];
+    int param_double[kMaxSlots];   // bit j: PARAMETER j is stored in FP64 in both precisions
+    int has_ica[kMaxSlots], has_gid[kMaxSlots];
+};
+
+__host__ __device__ inline size_t res_round8(size_t b) { return (b + 7) & ~(size_t)7; }
+
+// LDS bytes of one slot's instance arrays in a tile of n of its instances:
+// STATEs, PARAMETERs, ica, the tile-local node index, the event stream id.
+__host__ __device__ inline size_t res_slot_bytes(const ResArgs &r, int s, int n) {
+    const size_t nn = (size_t)n;
+    size_t b = 0;
+    for (int j = 0; j < r.n_state[s]; ++j) b += res_round8(nn * r.ss);
+    for (int j = 0; j < r.n_param[s]; ++j) b += res_round8(nn * (((r.param_double[s] >> j) & 1) ? 8 : r.ss));
+    if (r.has_ica[s]) b += res_round8(nn * r.ss);
+    b += res_round8(nn * 4);
+    if (r.has_gid[s]) b += res_round8(nn * 4);
+    return b;
+}
+
+// LDS doubles per tile node: v, rhs and d accumulators, 100/area (point
+// processes), cm (isolated) or the four clamp waveform parameters, and the
+// shared calcium ion's cai and ica accumulator; then an int spike counter.
+__host__ __device__ inline int res_node_doubles(int vmode, bool has_syn, bool ion) {
+    return 3 + (has_syn ? 1 : 0) + (vmode == MECH_V_CLAMP ? 4 : 1) + (ion ? 2 : 0);
+}
+__host__ __device__ inline size_t res_node_bytes(int nn, int vmode, bool has_syn, bool ion) {
+    return 8 * (size_t)nn * res_node_doubles(vmode, has_syn, ion) + res_round8(4 * (size_t)nn);
+}
+
 struct PlainArgs {
     SlotDev slot;
     long long k;
@@ -154,6 +193,9 @@ hipError_t launch_fused(bool fp32, int phases, int vmode, const FusedArgs &a, in
                         hipStream_t s);
 size_t fused_lds_bytes(int tile_nodes, bool ion);
 hipError_t fused_allow_lds(size_t bytes);
+hipError_t launch_resident(bool fp32, int vmode, const FusedArgs &a, const ResArgs &r, int grid, int block,
+                           size_t lds_bytes, hipStream_t s);
+hipError_t resident_allow_lds(size_t bytes);
 hipError_t launch_ion_pool(const NodesDev &nd, const GlobDev &g, int *err, hipStream_t s);
 hipError_t launch_ion_init(const NodesDev &nd, const GlobDev &g, hipStream_t s);
 

@@ -1052,30 +1052,37 @@ hipError_t cable_allow_lds(size_t bytes) {
 // LDS per tile node: v, 100/area, rhs and d accumulators (4 doubles); under
 // the shared calcium ion also the node's cai and its calcium current
 // accumulator (6 doubles).
+// Instance i of a slot within a tile whose nodes start at nlo.
+template <class S, int KIND, int PH, bool NT, bool EXT>
+__device__ __forceinline__ void tile_one(const SlotDev &sl, int i, int nlo, const double *vl, const double *sc,
+                                         double *ar, double *ad, const double *cl, double *ai, const GlobDev &g,
+                                         long long k, bool ion, int &flag) {
+    // an identity slot (instance i on node i) needs no index load
+    const int j = (sl.identity ? i : ld<NT>(sl.ni + i)) - nlo;
+    double ci, cg;
+    if (EXT && is_ca_kind(KIND) && ion) {
+        double ica;
+        ca_shared<S, PH, NT>(sl, i, vl[j], cl[j], g, ci, cg, ica, flag);
+        if (PH & kDoCur) atomicAdd(&ai[j], ica);
+    } else {
+        instance<S, KIND, PH, NT, true>(sl, i, vl[j], g, k, ci, cg, flag);
+    }
+    if (PH & kDoCur) {
+        if (KIND == MECH_SYN) {
+            ci *= sc[j];
+            cg *= sc[j];
+        }
+        atomicAdd(&ar[j], -ci);
+        atomicAdd(&ad[j], cg);
+    }
+}
+
 template <class S, int KIND, int PH, bool NT, bool EXT>
 __device__ __forceinline__ void tile_slot(const SlotDev &sl, int lo, int hi, int nlo, const double *vl,
                                           const double *sc, double *ar, double *ad, const double *cl, double *ai,
                                           const GlobDev &g, long long k, bool ion, int &flag) {
-    for (int i = lo + (int)threadIdx.x; i < hi; i += (int)blockDim.x) {
-        // an identity slot (instance i on node i) needs no index load
-        const int j = (sl.identity ? i : ld<NT>(sl.ni + i)) - nlo;
-        double ci, cg;
-        if (EXT && is_ca_kind(KIND) && ion) {
-            double ica;
-            ca_shared<S, PH, NT>(sl, i, vl[j], cl[j], g, ci, cg, ica, flag);
-            if (PH & kDoCur) atomicAdd(&ai[j], ica);
-        } else {
-            instance<S, KIND, PH, NT, true>(sl, i, vl[j], g, k, ci, cg, flag);
-        }
-        if (PH & kDoCur) {
-            if (KIND == MECH_SYN) {
-                ci *= sc[j];
-                cg *= sc[j];
-            }
-            atomicAdd(&ar[j], -ci);
-            atomicAdd(&ad[j], cg);
-        }
-    }
+    for (int i = lo + (int)threadIdx.x; i < hi; i += (int)blockDim.x)
+        tile_one<S, KIND, PH, NT, EXT>(sl, i, nlo, vl, sc, ar, ad, cl, ai, g, k, ion, flag);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on
@@ -1157,6 +1164,240 @@ __global__ __launch_bounds__(1024) void k_fused(FusedArgs a, int tn) {
                 }
             }
         }
+        __syncthreads();
+    }
+    if (flag) atomicOr(a.err, 1);
+}
+
+// ---------------------------------------------------- time-fused path --
+// One workgroup per tile, as in k_fused, but the tile stays in LDS for
+// `nsub` steps: its nodes' v, accumulators and voltage-mode data, and every
+// instance array of its instances.  Each step runs the same per-instance
+// code (tile_slot and instance, on a slot descriptor that points into LDS),
+// then a flush provides v_{k+1}; STATEs go back to memory once, at the end.
+// Only modes in which the kernel provides v itself (clamp, isolated) can
+// run this way.  The arithmetic of each step is that of k_fused.
+
+// Slot s's arrays for n instances at p, in the order of res_slot_bytes:
+// STATEs, PARAMETERs, ica, the tile-local node index, the event stream id.
+template <class S>
+__device__ __forceinline__ SlotDev res_carve(const ResArgs &r, int s, int kind, int n, char *p) {
+    SlotDev l{};
+    l.kind = kind;
+    l.n = n;
+    l.identity = 0;
+#pragma unroll
+    for (int j = 0; j < kMaxStates; ++j)
+        if (j < r.n_state[s]) {
+            l.st[j] = p;
+            p += res_round8((size_t)n * sizeof(S));
+        }
+#pragma unroll
+    for (int j = 0; j < kMaxParams; ++j)
+        if (j < r.n_param[s]) {
+            l.par[j] = p;
+            p += res_round8((size_t)n * (((r.param_double[s] >> j) & 1) ? 8 : sizeof(S)));
+        }
+    if (r.has_ica[s]) {
+        l.ica = p;
+        p += res_round8((size_t)n * sizeof(S));
+    }
+    l.ni = (const int *)p;
+    p += res_round8((size_t)n * 4);
+    l.gid = r.has_gid[s] ? (const int *)p : nullptr;
+    return l;
+}
+
+// Stage a slot's run [lo, lo + n) of the tile into LDS (IN) or write its
+// STATEs and ica back (!IN).
+template <class S, bool IN>
+__device__ __forceinline__ void res_copy(const SlotDev &g, const SlotDev &l, const ResArgs &r, int s, int lo, int n,
+                                         int nlo) {
+    for (int i = (int)threadIdx.x; i < n; i += (int)blockDim.x) {
+        const int gi = lo + i;
+#pragma unroll
+        for (int j = 0; j < kMaxStates; ++j)
+            if (j < r.n_state[s]) {
+                S *a = (S *)g.st[j] + gi, *b = (S *)l.st[j] + i;
+                if (IN) *b = *a;
+                else *a = *b;
+            }
+        if (r.has_ica[s]) {
+            S *a = (S *)g.ica + gi, *b = (S *)l.ica + i;
+            if (IN) *b = *a;
+            else *a = *b;
+        }
+        if (IN) {
+#pragma unroll
+            for (int j = 0; j < kMaxParams; ++j)
+                if (j < r.n_param[s]) {
+                    if ((r.param_double[s] >> j) & 1) ((double *)l.par[j])[i] = ((const double *)g.par[j])[gi];
+                    else ((S *)l.par[j])[i] = ((const S *)g.par[j])[gi];
+                }
+            ((int *)l.ni)[i] = (g.identity ? gi : g.ni[gi]) - nlo;
+            if (l.gid) ((int *)l.gid)[i] = g.gid ? g.gid[gi] : gi;
+        }
+    }
+}
+
+// One pass over every instance of the staged tile (phases PH at step k).
+// The slots' runs are laid end to end, each padded to a whole wave, and the
+// block's threads stride over that sequence: every thread gets an equal
+// share whatever the mix of types, and every wave works on one type.  A
+// wave finds its slot with scalar arithmetic from its first position.
+// (Walking the slots in an outer loop and keeping each slot's descriptor
+// live across its run instead spills about three times as many scalar
+// registers and measured 10-20 % slower.)
+template <class S, int PH, bool EXT>
+__device__ __forceinline__ void res_pass(const FusedArgs &a, const ResArgs &r, const int *r0, const int *r1, char *inst,
+                                         const double *vl, const double *sc, double *ar, double *ad, const double *cl,
+                                         double *ai, long long k, bool ion, int &flag) {
+    int total = 0;
+    for (int s = 0; s < a.n_slots; ++s) total += (r1[1 + s] - r0[1 + s] + 63) & ~63;
+    const int lane = (int)(threadIdx.x & 63);
+    for (int g0 = (int)threadIdx.x - lane; g0 < total; g0 += (int)blockDim.x) {
+        // the wave's first position, as a scalar
+        const int gw = __builtin_amdgcn_readfirstlane(g0);
+        int s = 0, base = 0, n = r1[1] - r0[1];
+        char *p = inst;
+        while (gw >= base + ((n + 63) & ~63)) {
+            base += (n + 63) & ~63;
+            p += res_slot_bytes(r, s, n);
+            ++s;
+            n = r1[1 + s] - r0[1 + s];
+        }
+        const int i = gw - base + lane;
+        if (i >= n) continue;
+        const int kind = a.slot[s].kind;
+        const SlotDev l = res_carve<S>(r, s, kind, n, p);
+        switch (kind) {
+        case MECH_PAS:
+            if (PH & kDoCur) tile_one<S, MECH_PAS, PH, false, EXT>(l, i, 0, vl, sc, ar, ad, cl, ai, a.g, k, ion, flag);
+            break;
+        case MECH_HH: tile_one<S, MECH_HH, PH, false, EXT>(l, i, 0, vl, sc, ar, ad, cl, ai, a.g, k, ion, flag); break;
+        case MECH_IH: tile_one<S, MECH_IH, PH, false, EXT>(l, i, 0, vl, sc, ar, ad, cl, ai, a.g, k, ion, flag); break;
+        case MECH_CAHVA: tile_one<S, MECH_CAHVA, PH, false, EXT>(l, i, 0, vl, sc, ar, ad, cl, ai, a.g, k, ion, flag); break;
+        case MECH_SYN: tile_one<S, MECH_SYN, PH, false, EXT>(l, i, 0, vl, sc, ar, ad, cl, ai, a.g, k, ion, flag); break;
+        case MECH_KMARKOV: tile_one<S, MECH_KMARKOV, PH, false, EXT>(l, i, 0, vl, sc, ar, ad, cl, ai, a.g, k, ion, flag); break;
+        case MECH_CAPUMP: tile_one<S, MECH_CAPUMP, PH, false, EXT>(l, i, 0, vl, sc, ar, ad, cl, ai, a.g, k, ion, flag); break;
+        case MECH_CABUF:
+            if constexpr (EXT) tile_one<S, MECH_CABUF, PH, false, EXT>(l, i, 0, vl, sc, ar, ad, cl, ai, a.g, k, ion, flag);
+            break;
+        default: break;
+        }
+    }
+}
+
+template <class S, int VM, bool EXT>
+__global__ __launch_bounds__(1024) void k_resident(FusedArgs a, ResArgs r) {
+    extern __shared__ double lds[];
+    const bool ion = EXT && a.g.shared_ca;
+    const bool syn = a.has_syn != 0;
+    int flag = 0;
+    for (int b = blockIdx.x; b < a.n_tiles; b += gridDim.x) {
+        const int t = tile_of(b, a.n_tiles, a.xcd_order);
+        const int *r0 = a.tiles + (size_t)t * a.row;
+        const int *r1 = r0 + a.row;
+        const int nlo = r0[0], nn = r1[0] - nlo;
+        // node region (res_node_bytes), then the slots' instance arrays
+        double *vl = lds, *ar = lds + nn, *ad = lds + 2 * nn, *q = lds + 3 * nn;
+        double *sc = q;
+        if (syn) q += nn;
+        double *md = q;   // cm (isolated) or the clamp waveform, 4 per node
+        q += (VM == MECH_V_CLAMP ? 4 : 1) * nn;
+        double *cl = q, *ai = q + nn;
+        if (ion) q += 2 * nn;
+        int *spk = (int *)q;
+        char *inst = (char *)q + res_round8(4 * (size_t)nn);
+        for (int j = threadIdx.x; j < nn; j += blockDim.x) {
+            const int n = nlo + j;
+            vl[j] = a.nd.v[n];
+            ar[j] = 0.0;
+            ad[j] = 0.0;
+            if (syn) sc[j] = 1e2 / a.nd.area[n];
+            if (VM == MECH_V_CLAMP) {
+                md[4 * j] = a.nd.c_off[n];
+                md[4 * j + 1] = a.nd.c_amp[n];
+                md[4 * j + 2] = a.nd.c_freq[n];
+                md[4 * j + 3] = a.nd.c_phase[n];
+            } else {
+                md[j] = a.nd.cm[n];
+            }
+            if (ion) {
+                cl[j] = a.nd.cai[n];
+                ai[j] = 0.0;
+            }
+            spk[j] = 0;
+        }
+        {
+            char *p = inst;
+            for (int s = 0; s < a.n_slots; ++s) {
+                const int n = r1[1 + s] - r0[1 + s];
+                const SlotDev l = res_carve<S>(r, s, a.slot[s].kind, n, p);
+                res_copy<S, true>(a.slot[s], l, r, s, r0[1 + s], n, nlo);
+                p += res_slot_bytes(r, s, n);
+            }
+        }
+        __syncthreads();
+        for (int sub = 0; sub < r.nsub; ++sub) {
+            const long long k = r.k0 + sub;
+            if (sub == 0 && !r.first_state)
+                res_pass<S, kDoCur, EXT>(a, r, r0, r1, inst, vl, sc, ar, ad, cl, ai, k, ion, flag);
+            else
+                res_pass<S, kDoCur | kDoState, EXT>(a, r, r0, r1, inst, vl, sc, ar, ad, cl, ai, k, ion, flag);
+            __syncthreads();
+            // flush: the same voltage provision as k_fused's, from LDS
+            const bool last = sub + 1 == r.nsub;
+            for (int j = threadIdx.x; j < nn; j += blockDim.x) {
+                const int n = nlo + j;
+                const double rr = ar[j], dd = ad[j], v0 = vl[j];
+                double v1;
+                if (VM == MECH_V_ISOLATED) {
+                    v1 = v0 + rr / (1e-3 * md[j] / a.g.dt + dd);
+                    if (v0 < a.g.vthresh && v1 >= a.g.vthresh) spk[j] += 1;
+                } else {
+                    const double t1 = (double)(k + 1) * a.g.dt;
+                    v1 = md[4 * j] + md[4 * j + 1] * sin(2.0 * 3.14159265358979323846 * md[4 * j + 2] * t1 * 1e-3 +
+                                                         md[4 * j + 3]);
+                }
+                vl[j] = v1;
+                ar[j] = 0.0;
+                ad[j] = 0.0;
+                if (ion) {
+                    double c = cl[j];
+                    ion_pool(a.g, ai[j], c);
+                    flag |= bad(c);
+                    cl[j] = c;
+                }
+                if (last) {
+                    a.nd.rhs[n] = rr;
+                    a.nd.d[n] = dd;
+                    a.nd.v[n] = v1;
+                    if (ion) {
+                        a.nd.cai[n] = cl[j];
+                        a.nd.ica[n] = ai[j];
+                    }
+                }
+                if (ion) ai[j] = 0.0;
+            }
+            __syncthreads();
+        }
+        if (r.last_state) {
+            res_pass<S, kDoState, EXT>(a, r, r0, r1, inst, vl, sc, ar, ad, cl, ai, r.k0 + r.nsub, ion, flag);
+            __syncthreads();
+        }
+        {
+            char *p = inst;
+            for (int s = 0; s < a.n_slots; ++s) {
+                const int n = r1[1 + s] - r0[1 + s];
+                const SlotDev l = res_carve<S>(r, s, a.slot[s].kind, n, p);
+                res_copy<S, false>(a.slot[s], l, r, s, r0[1 + s], n, nlo);
+                p += res_slot_bytes(r, s, n);
+            }
+        }
+        if (VM == MECH_V_ISOLATED)
+            for (int j = threadIdx.x; j < nn; j += blockDim.x)
+                if (spk[j]) a.nd.spikes[nlo + j] += spk[j];
         __syncthreads();
     }
     if (flag) atomicOr(a.err, 1);
@@ -1341,6 +1582,39 @@ hipError_t fused_allow_lds(size_t bytes) {
         (const void *)k_fused<S, kDoCur | kDoState, MECH_V_ISOLATED, false, true>
         MECH_FUSED_FNS(double), MECH_FUSED_FNS(float)
 #undef MECH_FUSED_FNS
+    };
+    for (const void *f : fns) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <class S, bool EXT>
+static hipError_t resident_t(int vmode, const FusedArgs &a, const ResArgs &r, int grid, int block, size_t lds,
+                             hipStream_t s) {
+    if (vmode == MECH_V_CLAMP) k_resident<S, MECH_V_CLAMP, EXT><<<grid, block, lds, s>>>(a, r);
+    else k_resident<S, MECH_V_ISOLATED, EXT><<<grid, block, lds, s>>>(a, r);
+    return hipGetLastError();
+}
+hipError_t launch_resident(bool fp32, int vmode, const FusedArgs &a, const ResArgs &r, int grid, int block,
+                           size_t lds_bytes, hipStream_t s) {
+    if (a.n_tiles == 0 || grid == 0 || r.nsub <= 0) return hipSuccess;
+    if (vmode != MECH_V_CLAMP && vmode != MECH_V_ISOLATED) return hipErrorInvalidValue;
+    if (a.g.shared_ca || a.has_ext)
+        return fp32 ? resident_t<float, true>(vmode, a, r, grid, block, lds_bytes, s)
+                    : resident_t<double, true>(vmode, a, r, grid, block, lds_bytes, s);
+    return fp32 ? resident_t<float, false>(vmode, a, r, grid, block, lds_bytes, s)
+                : resident_t<double, false>(vmode, a, r, grid, block, lds_bytes, s);
+}
+hipError_t resident_allow_lds(size_t bytes) {
+    const int b = (int)bytes;
+    const void *fns[] = {
+#define MECH_RES_FNS(S)                                                                                            \
+    (const void *)k_resident<S, MECH_V_CLAMP, false>, (const void *)k_resident<S, MECH_V_ISOLATED, false>,        \
+        (const void *)k_resident<S, MECH_V_CLAMP, true>, (const void *)k_resident<S, MECH_V_ISOLATED, true>
+        MECH_RES_FNS(double), MECH_RES_FNS(float)
+#undef MECH_RES_FNS
     };
     for (const void *f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b);

@@ -350,7 +350,11 @@ struct mech_ctx {
     // fused-path launch shape and tile table
     int block = 256, tile_budget = 2048, tile_nodes = 1024, blocks_per_cu = 0, launch_flags = MECH_LAUNCH_XCD_ORDER;
     int64_t n_tiles = 0, max_tile_nodes = 0;
+    std::vector<int32_t> tile_rows;   // host copy of the tile table
     int n_cu = 256;
+    // time-fused path: steps per launch, and the dynamic LDS its kernels may take
+    int res_steps = 32;
+    size_t res_lds_allowed = 0;
     // graphs of kGraphSteps fused steps, keyed by (vmode, dt)
     std::map<std::pair<int, uint64_t>, hipGraphExec_t> graphs;
     std::string err;
@@ -500,6 +504,7 @@ int build_tiles(mech_ctx *c) {
     HIPCHK(c, hipMemcpyAsync(c->buf + c->L.off_tiles, rows.data(), rows.size() * 4, hipMemcpyHostToDevice,
                              c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->tile_rows = std::move(rows);
     clear_graphs(c);
     return MECH_OK;
 }
@@ -685,6 +690,75 @@ int step_batched(mech_ctx *c, int64_t nsteps, int64_t k0, double dt, int vmode, 
     }
     // closing state update at v_{k0+nsteps}
     return launch_fused_phase(c, kDoState, MECH_V_EXTERNAL, g, 0, c->stream);
+}
+
+// ------------------------------------------------------ time-fused path --
+ResArgs res_args(const mech_ctx *c) {
+    ResArgs r{};
+    r.ss = c->fp32 ? 4 : 8;
+    for (int s = 0; s < (int)c->slots.size(); ++s) {
+        const SlotHost &h = c->slots[s];
+        const KindDesc &K = kKinds[h.kind];
+        r.n_state[s] = K.n_state;
+        r.n_param[s] = K.n_param;
+        for (int j = 0; j < K.n_param; ++j)
+            if (K.param[j].is_double || !c->fp32) r.param_double[s] |= 1 << j;
+        r.has_ica[s] = h.has_ica ? 1 : 0;
+        r.has_gid[s] = K.point_process ? 1 : 0;
+    }
+    return r;
+}
+
+// Dynamic LDS of the largest tile of the current table.
+size_t res_lds_need(const mech_ctx *c, const ResArgs &r, int vmode, bool ion) {
+    const int ns = (int)c->slots.size(), row = 1 + ns;
+    size_t need = 0;
+    for (int64_t t = 0; t < c->n_tiles; ++t) {
+        const int32_t *r0 = c->tile_rows.data() + (size_t)t * row, *r1 = r0 + row;
+        size_t b = res_node_bytes(r1[0] - r0[0], vmode, c->has_syn, ion);
+        for (int s = 0; s < ns; ++s) b += res_slot_bytes(r, s, r1[1 + s] - r0[1 + s]);
+        need = std::max(need, b);
+    }
+    return need;
+}
+
+size_t device_lds_bytes() {
+    int dev = 0, bytes = 65536;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int b = 0;
+        if (hipDeviceGetAttribute(&b, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && b > 0)
+            bytes = b;
+    }
+    return (size_t)bytes;
+}
+
+int step_resident(mech_ctx *c, int64_t nsteps, int64_t k0, double dt, int vmode) {
+    if (vmode != MECH_V_CLAMP && vmode != MECH_V_ISOLATED)
+        return fail(c, MECH_ERR_INVAL, "the time-fused path provides v itself: clamp or isolated mode only");
+    const GlobDev g = make_glob(c, dt);
+    ResArgs r = res_args(c);
+    const size_t need = res_lds_need(c, r, vmode, g.shared_ca != 0), cap = device_lds_bytes();
+    if (need > cap)
+        return fail(c, MECH_ERR_STATE,
+                    "a tile needs %zu B of LDS on the time-fused path, the device allows %zu: lower "
+                    "tile_instances or tile_nodes (mech_set_launch)",
+                    need, cap);
+    if (need > c->res_lds_allowed) {
+        HIPCHK(c, resident_allow_lds(cap));
+        c->res_lds_allowed = cap;
+    }
+    if (vmode == MECH_V_CLAMP) HIPCHK(c, launch_vclamp(c->nd, (double)k0 * dt, c->stream));
+    const FusedArgs a = fused_args(c, g, 0);
+    for (int64_t done = 0; done < nsteps;) {
+        const int n = (int)std::min<int64_t>(c->res_steps, nsteps - done);
+        r.k0 = k0 + done;
+        r.nsub = n;
+        r.first_state = done > 0 ? 1 : 0;
+        r.last_state = done + n == nsteps ? 1 : 0;
+        HIPCHK(c, launch_resident(c->fp32, vmode, a, r, fused_grid(c), c->block, need, c->stream));
+        done += n;
+    }
+    return MECH_OK;
 }
 
 }  // namespace
@@ -1091,7 +1165,16 @@ int mech_step(mech_ctx *c, int64_t nsteps, int64_t k0, double dt, int vmode, int
     if (nsteps == 0) return MECH_OK;
     if (path == MECH_PATH_PLAIN) return step_plain(c, nsteps, k0, dt, vmode);
     if (path == MECH_PATH_BATCHED) return step_batched(c, nsteps, k0, dt, vmode, true);
+    if (path == MECH_PATH_RESIDENT) return step_resident(c, nsteps, k0, dt, vmode);
     return fail(c, MECH_ERR_INVAL, "bad path %d", path);
+}
+
+int mech_set_resident_steps(mech_ctx *c, int steps_per_launch) {
+    if (!c) return fail(nullptr, MECH_ERR_INVAL, "null ctx");
+    if (steps_per_launch < 1 || steps_per_launch > 4096)
+        return fail(c, MECH_ERR_INVAL, "steps_per_launch must be in [1, 4096]");
+    c->res_steps = steps_per_launch;
+    return MECH_OK;
 }
 
 int mech_set_launch(mech_ctx *c, int block, int tile_instances, int tile_nodes, int blocks_per_cu, int flags) {

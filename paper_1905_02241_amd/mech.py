@@ -21,7 +21,7 @@ OK, ERR_INVAL, ERR_RANGE, ERR_NOMEM, ERR_STATE, ERR_HIP, ERR_NONFINITE = 0, -1, 
 KIND = {"pas": 0, "hh": 1, "ih": 2, "cahva": 3, "syn": 4, "kmarkov": 5, "capump": 6, "cabuf": 7}
 PREC = {"fp64": 0, "fp32": 1}
 VMODE = {"external": 0, "clamp": 1, "isolated": 2, "cable": 3}
-PATH = {"plain": 0, "batched": 1}
+PATH = {"plain": 0, "batched": 1, "resident": 2}
 GLOBAL_NAMES = ("celsius", "ena", "ek", "eh", "cao", "cai0", "tau_ca", "ca_gamma", "ca_depth", "e_syn",
                 "mg", "tau_r_ampa", "tau_d_ampa", "tau_r_nmda", "tau_d_nmda", "event_rate_hz", "event_seed",
                 "vthresh", "fd_dv", "analytic_conductance", "pade_cnexp", "pump_vmax", "pump_kp",
@@ -32,7 +32,7 @@ SYMBOLS = ("mech_required_bytes", "mech_alloc", "mech_bind_nodes", "mech_bind_cl
            "mech_cable_plan",
            "mech_bind_cable", "mech_set_params",
            "mech_set_global", "mech_init", "mech_cur", "mech_state", "mech_step", "mech_set_launch",
-           "mech_get_launch", "mech_autotune", "mech_get_state", "mech_set_state", "mech_spike_counts",
+           "mech_get_launch", "mech_set_resident_steps", "mech_autotune", "mech_get_state", "mech_set_state", "mech_spike_counts",
            "mech_sync", "mech_info", "mech_probe_stream", "mech_last_error", "mech_strerror", "mech_free")
 LAUNCH_XCD_ORDER = 1
 LAUNCH_NONTEMPORAL = 2
@@ -81,6 +81,7 @@ def load_library(path: str = LIB_PATH):
         "mech_step": [vp, C.c_int64, C.c_int64, C.c_double, C.c_int, C.c_int],
         "mech_set_launch": [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int],
         "mech_get_launch": [vp, ip, ip, ip, ip, ip],
+        "mech_set_resident_steps": [vp, C.c_int],
         "mech_autotune": [vp, C.c_double, C.c_int, C.c_int, C.c_int, dp],
         "mech_get_state": [vp, C.c_int, C.c_char_p, dp, C.c_int64],
         "mech_set_state": [vp, C.c_int, C.c_char_p, dp, C.c_int64],
@@ -224,6 +225,9 @@ class Mechanisms:
     def set_launch(self, block: int, tile_instances: int, tile_nodes: int, blocks_per_cu: int = 0,
                    flags: int = LAUNCH_XCD_ORDER):
         self._check(self.L.mech_set_launch(self.ctx, block, tile_instances, tile_nodes, blocks_per_cu, flags))
+
+    def set_resident_steps(self, steps_per_launch: int):
+        self._check(self.L.mech_set_resident_steps(self.ctx, steps_per_launch))
 
     def get_launch(self):
         v = [C.c_int32() for _ in range(5)]

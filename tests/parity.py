@@ -37,11 +37,14 @@ def log(msg: str):
     sys.stdout.flush()
 
 
-def run_gpu(w, nsteps, path="batched", prec="fp64", k0=0, launch=None, vmode=None, unit_nodes=0):
+def run_gpu(w, nsteps, path="batched", prec="fp64", k0=0, launch=None, vmode=None, unit_nodes=0,
+            resident_steps=None):
     from paper_1905_02241_amd import mech
     m = mech.from_workload(w, prec, unit_nodes=unit_nodes)
     if launch is not None:
         m.set_launch(*launch)
+    if resident_steps is not None:
+        m.set_resident_steps(resident_steps)
     m.step(nsteps, k0, w.dt, vmode or w.vmode, path)
     m.sync()
     out = {"states": mech.states_of(m), **m.nodes(), "spikes": m.spike_counts()}

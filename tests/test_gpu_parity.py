@@ -276,10 +276,10 @@ def test_config1_fp32_within_1e5():
     log(f"c1 fp32: max abs err {max(v[1] for v in ws.values()):.3g}")
 
 
-def _sampled(cfg, nsteps, prec, path, n_sample, seed=99):
+def _sampled(cfg, nsteps, prec, path, n_sample, seed=99, launch=None, resident_steps=None):
     w = W.make_config(cfg)
     with Timer() as tg:
-        got, m = run_gpu(w, nsteps, path, prec)
+        got, m = run_gpu(w, nsteps, path, prec, launch=launch, resident_steps=resident_steps)
     rng = np.random.default_rng(seed)
     nodes = np.sort(rng.choice(w.n_nodes, size=n_sample, replace=False))
     sub, keep = W.subset(w, nodes)
@@ -320,6 +320,103 @@ def test_config5_fp64_sampled_spikes():
     got, M, nodes = _sampled(5, 2000, "fp64", "batched", 1500)
     assert np.array_equal(got["spikes"][nodes], M.spikes)
     log(f"c5 spikes on sample: {int(M.spikes.sum())}")
+
+
+# ------------------------------------------------- time-fused path --
+# Tiles stay in LDS for several steps (mech_set_resident_steps); the chunk
+# lengths below leave a ragged last launch.  Launch shapes keep each tile
+# within the LDS of one workgroup.
+RES_SHAPE = (256, 1024, 512, 0, mech.LAUNCH_XCD_ORDER)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_resident_all_kinds_clamp(prec):
+    """Every mechanism type, two instances per node for the density types,
+    shuffled index, small tiles, 80 steps in launches of 7."""
+    w = W.make_tiny(61, kinds=W.KINDS, per_node=2, nsteps=80)
+    got, m = run_gpu(w, 80, "resident", prec, launch=(128, 128, 64, 0, 1), resident_steps=7)
+    M = run_oracle(w, 80)
+    ws = compare_states(got, M, prec, label="resident")
+    wn = compare_nodes(got, M, prec, label="resident")
+    log(f"resident clamp {prec}: worst state ratio {max(v[0] for v in ws.values()):.3g}, nodes {wn}")
+
+
+@pytest.mark.parametrize("steps", [1, 64, 1000])
+def test_resident_isolated_fp64_spikes(steps):
+    """Free voltage: states, v and spike counts exact against the oracle for
+    one step per launch, ragged chunks, and the whole run in one launch."""
+    w = W.make_tiny(62, kinds=("pas", "hh", "cahva", "syn"), n_nodes=40, syn_per_node=6.0,
+                    vmode="isolated", event_rate_hz=300.0, nsteps=600)
+    w.area[:] = np.linspace(100.0, 400.0, w.n_nodes)
+    w.slots[-1].params["weight"][:] *= 6.0
+    got, m = run_gpu(w, 600, "resident", "fp64", launch=(128, 128, 64, 0, 1), resident_steps=steps)
+    M = run_oracle(w, 600)
+    assert M.spikes.sum() > 0
+    assert np.array_equal(got["spikes"], M.spikes)
+    compare_states(got, M, "fp64", label="resident isolated")
+    compare_nodes(got, M, "fp64", label="resident isolated")
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_resident_shared_calcium(prec):
+    """The extended instantiations: cabuf and the per-node calcium ion kept
+    in LDS across steps."""
+    w = W.make_tiny(63, kinds=("pas", "hh", "cahva", "capump", "cabuf", "syn"), per_node=2, nsteps=100)
+    for s in w.slots:
+        if s.kind in mech.CA_KINDS:
+            s.params["gbar"][:] *= 20.0
+    w.globals["shared_ca"] = 1
+    got, m = run_gpu(w, 100, "resident", prec, launch=(128, 256, 64, 0, 1), resident_steps=16)
+    M = run_oracle(w, 100)
+    assert np.max(M.cai_node) > 2.0 * w.globals["cai0"]
+    compare_states(got, M, prec, label="resident shared ca")
+    compare_nodes(got, M, prec, label="resident shared ca")
+    compare_ion(m, M, prec, f"resident shared ca {prec}")
+
+
+def test_resident_equals_batched_medium():
+    """A workload of many tiles with a ragged last tile: the time-fused path
+    against the per-step fused path on the same tiles."""
+    w = W.make_config(2, scale=0.01)
+    a, _ = run_gpu(w, 300, "batched", "fp64", launch=RES_SHAPE)
+    b, mb = run_gpu(w, 300, "resident", "fp64", launch=RES_SHAPE, resident_steps=32)
+    log(f"resident vs batched: {mb.info()['n_tiles']} tiles")
+    for sa, sb in zip(a["states"], b["states"]):
+        for name in sa:
+            assert np.allclose(sb[name], sa[name], rtol=1e-12, atol=1e-300), name
+    assert np.allclose(b["v"], a["v"], rtol=1e-13, atol=0)
+    for key in ("rhs", "d"):
+        assert np.allclose(b[key], a[key], rtol=1e-10, atol=1e-14), key
+
+
+def test_resident_rejects():
+    """Modes whose v comes from elsewhere, tiles beyond the LDS of a
+    workgroup and out-of-range chunk lengths are errors, raised before any
+    launch."""
+    w = W.make_tiny(64, kinds=("pas", "hh"), per_node=2, nsteps=10)
+    m = mech.from_workload(w, "fp64")
+    for vmode in ("external", "cable"):
+        with pytest.raises(mech.MechError):
+            m.step(5, 0, w.dt, vmode, "resident")
+    for bad_steps in (0, 4097):
+        with pytest.raises(mech.MechError):
+            m.set_resident_steps(bad_steps)
+    big = W.make_config(2, scale=0.01)
+    mb = mech.from_workload(big, "fp64")
+    mb.set_launch(1024, 4096, 2048, 0, 1)
+    with pytest.raises(mech.MechError, match="LDS"):
+        mb.step(5, 0, big.dt, "clamp", "resident")
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_config2_resident_sampled(prec):
+    _sampled(2, 4000, prec, "resident", 1500, launch=RES_SHAPE, resident_steps=64)
+
+
+def test_config5_resident_fp64_sampled_spikes():
+    got, M, nodes = _sampled(5, 2000, "fp64", "resident", 1500, launch=RES_SHAPE, resident_steps=64)
+    assert np.array_equal(got["spikes"][nodes], M.spikes)
+    log(f"c5 resident spikes on sample: {int(M.spikes.sum())}")
 
 
 # ------------------------------------------ section 5.2 variants (F1, F2) --
