@@ -297,6 +297,9 @@ def main():
     res = {}
     for v in args.variants.split(","):
         prec, path = v.split("-")
+        if path == "resident" and w.vmode not in ("clamp", "isolated"):
+            log(f"{v}: skipped, the time-fused path runs in clamp and isolated modes only")
+            continue
         launch = tuple(int(x) for x in args.launch.split(",")) if args.launch else None
         shape = tuple(int(x) for x in args.resident_launch.split(",")) if args.resident_launch else RESIDENT_SHAPE[prec]
         resident = (shape, args.resident_steps)
