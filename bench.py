@@ -97,10 +97,25 @@ def time_variant(w, prec, path, steps, warmup, autotune, torch, mech, launch=Non
     log(f"{prec}-{path}: context ready in {time.perf_counter() - t0:.1f}s ({m.nbytes / 1e9:.2f} GB)")
     tuned = None
     if path == "resident":
-        shape, nsub = resident
-        m.set_launch(*shape)
+        from paper_1905_02241_amd import tuning
+        shape, nsub, given = resident
         m.set_resident_steps(nsub)
-        tuned = {"launch": m.get_launch(), "steps_per_launch": nsub, "source": "--resident-launch"}
+        cached = tuning.lookup(w, prec, step_path="resident")
+        if given:
+            m.set_launch(*shape)
+            tuned = {"launch": m.get_launch(), "source": "--resident-launch"}
+        elif cached is not None and not autotune:
+            m.set_launch(*cached)
+            tuned = {"launch": m.get_launch(), "source": "tuning cache"}
+        elif autotune:
+            ms = m.autotune(w.dt, w.vmode, nsteps=nsub, reps=3, path="resident")
+            tuned = {"launch": m.get_launch(), "source": "autotuned", "ms_per_step": ms}
+            if save_tuning:
+                tuning.record(w, prec, m.get_launch(), ms, path=save_tuning, step_path="resident")
+        else:
+            m.set_launch(*shape)
+            tuned = {"launch": m.get_launch(), "source": "default"}
+        tuned["steps_per_launch"] = nsub
         log(f"{prec}-{path}: launch {tuned}")
     if path == "batched":
         from paper_1905_02241_amd import tuning
@@ -302,7 +317,7 @@ def main():
             continue
         launch = tuple(int(x) for x in args.launch.split(",")) if args.launch else None
         shape = tuple(int(x) for x in args.resident_launch.split(",")) if args.resident_launch else RESIDENT_SHAPE[prec]
-        resident = (shape, args.resident_steps)
+        resident = (shape, args.resident_steps, args.resident_launch is not None)
         res[v] = time_variant(w, prec, path, args.steps, args.warmup, args.autotune, torch, mech, launch,
                               args.save_tuning, resident)
 

@@ -290,6 +290,12 @@ int mech_set_resident_steps(mech_ctx *ctx, int steps_per_launch);
  * besides the chosen shape.                                                */
 int mech_autotune(mech_ctx *ctx, double dt, int vmode, int nsteps, int reps, double *best_ms_per_step);
 
+/* The same for the RESIDENT path: launch shapes whose tiles fit the LDS of a
+ * workgroup, each timed over `nsteps` steps (at most the steps per launch
+ * set by mech_set_resident_steps per launch).  CLAMP and ISOLATED modes
+ * only.                                                                    */
+int mech_autotune_resident(mech_ctx *ctx, double dt, int vmode, int nsteps, int reps, double *best_ms_per_step);
+
 /* Copy STATE `name` (or "ica" for Ca-HVA, capump and cabuf) of type slot `type_slot` to /
  * from host doubles in the caller's instance order; n must equal count.
  * type_slot -1 names the per-node calcium ion instead: "cai" (mM) or "ica"

@@ -1214,11 +1214,15 @@ int mech_info(const mech_ctx *c, int64_t *n_tiles, int64_t *max_tile_nodes) {
     return MECH_OK;
 }
 
-int mech_autotune(mech_ctx *c, double dt, int vmode, int nsteps, int reps, double *best_ms) {
+// Time candidate launch shapes of the batched (or time-fused) path and keep
+// the fastest; everything a step writes is saved before and restored after.
+static int autotune_impl(mech_ctx *c, double dt, int vmode, int nsteps, int reps, double *best_ms, bool resident) {
     if (!c) return fail(nullptr, MECH_ERR_INVAL, "null ctx");
     int rc = check_ready(c, vmode);
     if (rc) return rc;
     if (!(dt > 0.0) || nsteps < 1 || reps < 1) return fail(c, MECH_ERR_INVAL, "need dt > 0, nsteps >= 1, reps >= 1");
+    if (resident && vmode != MECH_V_CLAMP && vmode != MECH_V_ISOLATED)
+        return fail(c, MECH_ERR_INVAL, "the time-fused path provides v itself: clamp or isolated mode only");
     // save everything a step writes
     const size_t nb = 8 * (size_t)c->n_nodes, ion = c->nd.cai ? 2 * nb : 0;
     const size_t save_bytes = c->L.inst_end + 3 * nb + 4 * (size_t)c->n_nodes + ion;
@@ -1246,40 +1250,58 @@ int mech_autotune(mech_ctx *c, double dt, int vmode, int nsteps, int reps, doubl
     hipEvent_t e0 = nullptr, e1 = nullptr;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
-    const int blocks_c[] = {128, 256, 512};
-    const int ipt_c[] = {1, 2, 4, 8};
-    const int bpc_c[] = {0, 8};
-    // the non-temporal flag measured slower on every shape tried; it stays
-    // available through mech_set_launch but is not searched
-    const int flag_c[] = {0, MECH_LAUNCH_XCD_ORDER};
-    for (int b : blocks_c)
-        for (int ipt : ipt_c)
-            for (int bpc : bpc_c)
-            for (int fl : flag_c) {
-                if (rc) break;
-                const int budget = b * ipt;
-                const int tn = std::min(kMaxTileNodes, std::max(kMinTileNodes, budget));
-                rc = mech_set_launch(c, b, budget, tn, bpc, fl);
-                if (rc) break;
-                rc = step_batched(c, 1, 0, dt, vmode, false);  // warm-up
-                std::vector<double> ts;
-                for (int r = 0; r < reps && rc == MECH_OK; ++r) {
-                    (void)hipEventRecord(e0, c->stream);
-                    rc = step_batched(c, nsteps, 1, dt, vmode, false);
-                    (void)hipEventRecord(e1, c->stream);
-                    (void)hipEventSynchronize(e1);
-                    float ms = 0;
-                    (void)hipEventElapsedTime(&ms, e0, e1);
-                    ts.push_back(ms / nsteps);
+    struct Shape { int block, budget, nodes, bpc, flags; };
+    std::vector<Shape> cand;
+    if (!resident) {
+        // the non-temporal flag measured slower on every shape tried; it
+        // stays available through mech_set_launch but is not searched
+        for (int b : {128, 256, 512})
+            for (int ipt : {1, 2, 4, 8})
+                for (int bpc : {0, 8})
+                    for (int fl : {0, (int)MECH_LAUNCH_XCD_ORDER}) {
+                        const int budget = b * ipt;
+                        cand.push_back({b, budget, std::min(kMaxTileNodes, std::max(kMinTileNodes, budget)), bpc, fl});
+                    }
+    } else {
+        // a tile stays on one CU for many steps, so its LDS (and how many
+        // tiles share a CU) matters more than the stream order
+        for (int b : {64, 128, 256, 512})
+            for (int ipt : {1, 2, 4})
+                for (int half : {0, 1}) {
+                    const int budget = std::max(b * ipt, kMinTileBudget);
+                    const int nodes = std::min(kMaxTileNodes, std::max(kMinTileNodes, half ? budget / 2 : budget));
+                    cand.push_back({b, budget, nodes, 0, (int)MECH_LAUNCH_XCD_ORDER});
                 }
-                if (rc) break;
-                std::sort(ts.begin(), ts.end());
-                const double med = ts[ts.size() / 2];
-                if (med < best_t) {
-                    best_t = med;
-                    best[0] = b; best[1] = budget; best[2] = tn; best[3] = bpc; best[4] = fl;
-                }
-            }
+    }
+    const int ion_on = c->gl.shared_ca && c->nd.cai;
+    const size_t cap = device_lds_bytes();
+    for (const Shape &sh : cand) {
+        if (rc) break;
+        rc = mech_set_launch(c, sh.block, sh.budget, sh.nodes, sh.bpc, sh.flags);
+        if (rc) break;
+        if (resident && res_lds_need(c, res_args(c), vmode, ion_on) > cap) continue;
+        auto run = [&](int n, int64_t k0) {
+            return resident ? step_resident(c, n, k0, dt, vmode) : step_batched(c, n, k0, dt, vmode, false);
+        };
+        rc = run(1, 0);  // warm-up
+        std::vector<double> ts;
+        for (int r = 0; r < reps && rc == MECH_OK; ++r) {
+            (void)hipEventRecord(e0, c->stream);
+            rc = run(nsteps, 1);
+            (void)hipEventRecord(e1, c->stream);
+            (void)hipEventSynchronize(e1);
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            ts.push_back(ms / nsteps);
+        }
+        if (rc) break;
+        std::sort(ts.begin(), ts.end());
+        const double med = ts[ts.size() / 2];
+        if (med < best_t) {
+            best_t = med;
+            best[0] = sh.block; best[1] = sh.budget; best[2] = sh.nodes; best[3] = sh.bpc; best[4] = sh.flags;
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     int rc2 = mech_set_launch(c, best[0], best[1], best[2], best[3], best[4]);
@@ -1288,8 +1310,17 @@ int mech_autotune(mech_ctx *c, double dt, int vmode, int nsteps, int reps, doubl
     if (rc) return rc;
     if (rc2) return rc2;
     if (e != hipSuccess) return fail(c, MECH_ERR_HIP, "autotune restore: %s", hipGetErrorString(e));
+    if (best_t > 1e299) return fail(c, MECH_ERR_STATE, "no candidate launch shape fits the LDS of a workgroup");
     if (best_ms) *best_ms = best_t;
     return MECH_OK;
+}
+
+int mech_autotune(mech_ctx *c, double dt, int vmode, int nsteps, int reps, double *best_ms) {
+    return autotune_impl(c, dt, vmode, nsteps, reps, best_ms, false);
+}
+
+int mech_autotune_resident(mech_ctx *c, double dt, int vmode, int nsteps, int reps, double *best_ms) {
+    return autotune_impl(c, dt, vmode, nsteps, reps, best_ms, true);
 }
 
 // slot -1: the per-node calcium ion ("cai", "ica"), n_nodes doubles.

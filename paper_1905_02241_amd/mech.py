@@ -32,7 +32,7 @@ SYMBOLS = ("mech_required_bytes", "mech_alloc", "mech_bind_nodes", "mech_bind_cl
            "mech_cable_plan",
            "mech_bind_cable", "mech_set_params",
            "mech_set_global", "mech_init", "mech_cur", "mech_state", "mech_step", "mech_set_launch",
-           "mech_get_launch", "mech_set_resident_steps", "mech_autotune", "mech_get_state", "mech_set_state", "mech_spike_counts",
+           "mech_get_launch", "mech_set_resident_steps", "mech_autotune", "mech_autotune_resident", "mech_get_state", "mech_set_state", "mech_spike_counts",
            "mech_sync", "mech_info", "mech_probe_stream", "mech_last_error", "mech_strerror", "mech_free")
 LAUNCH_XCD_ORDER = 1
 LAUNCH_NONTEMPORAL = 2
@@ -83,6 +83,7 @@ def load_library(path: str = LIB_PATH):
         "mech_get_launch": [vp, ip, ip, ip, ip, ip],
         "mech_set_resident_steps": [vp, C.c_int],
         "mech_autotune": [vp, C.c_double, C.c_int, C.c_int, C.c_int, dp],
+        "mech_autotune_resident": [vp, C.c_double, C.c_int, C.c_int, C.c_int, dp],
         "mech_get_state": [vp, C.c_int, C.c_char_p, dp, C.c_int64],
         "mech_set_state": [vp, C.c_int, C.c_char_p, dp, C.c_int64],
         "mech_spike_counts": [vp, ip, C.c_int64],
@@ -239,9 +240,10 @@ class Mechanisms:
         self._check(self.L.mech_info(self.ctx, C.byref(a), C.byref(b)))
         return {"n_tiles": a.value, "max_tile_nodes": b.value}
 
-    def autotune(self, dt: float, vmode: str, nsteps: int = 10, reps: int = 3) -> float:
+    def autotune(self, dt: float, vmode: str, nsteps: int = 10, reps: int = 3, path: str = "batched") -> float:
         ms = C.c_double(0.0)
-        self._check(self.L.mech_autotune(self.ctx, dt, VMODE[vmode], nsteps, reps, C.byref(ms)))
+        fn = self.L.mech_autotune_resident if path == "resident" else self.L.mech_autotune
+        self._check(fn(self.ctx, dt, VMODE[vmode], nsteps, reps, C.byref(ms)))
         return ms.value
 
     def sync(self):

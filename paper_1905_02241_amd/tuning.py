@@ -1,5 +1,6 @@
-"""Autotuner cache: launch shapes of the batched path chosen by
-mech_autotune, keyed by (GPU architecture, workload signature, precision).
+"""Autotuner cache: launch shapes chosen by mech_autotune (batched path) and
+mech_autotune_resident (time-fused path), keyed by (GPU architecture,
+workload signature, precision[-resident]).
 
 The cache is a JSON file; entries are written by ``record`` and read by
 ``lookup``.  A shape is (block, tile_instances, tile_nodes, blocks_per_cu,
@@ -32,15 +33,19 @@ def _load(path: str) -> dict:
     return {}
 
 
-def lookup(w, prec: str, path: str = CACHE) -> Optional[Tuple[int, ...]]:
-    e = _load(path).get(arch(), {}).get(signature(w), {}).get(prec)
+def _key(prec: str, step_path: str) -> str:
+    return prec if step_path == "batched" else f"{prec}-{step_path}"
+
+
+def lookup(w, prec: str, path: str = CACHE, step_path: str = "batched") -> Optional[Tuple[int, ...]]:
+    e = _load(path).get(arch(), {}).get(signature(w), {}).get(_key(prec, step_path))
     return tuple(e["launch"]) if e else None
 
 
-def record(w, prec: str, launch, ms_per_step: float, path: str = CACHE) -> None:
+def record(w, prec: str, launch, ms_per_step: float, path: str = CACHE, step_path: str = "batched") -> None:
     d = _load(path)
-    d.setdefault(arch(), {}).setdefault(signature(w), {})[prec] = {"launch": list(launch),
-                                                                  "ms_per_step": ms_per_step}
+    d.setdefault(arch(), {}).setdefault(signature(w), {})[_key(prec, step_path)] = {
+        "launch": list(launch), "ms_per_step": ms_per_step}
     tmp = path + ".tmp"
     with open(tmp, "w") as f:
         json.dump(d, f, indent=1, sort_keys=True)

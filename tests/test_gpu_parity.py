@@ -389,6 +389,28 @@ def test_resident_equals_batched_medium():
         assert np.allclose(b[key], a[key], rtol=1e-10, atol=1e-14), key
 
 
+def test_resident_autotune_keeps_results():
+    """mech_autotune_resident leaves every state as it found it and picks a
+    shape whose results match the oracle."""
+    w = W.make_tiny(65, n_nodes=3000, per_node=1, nsteps=40)
+    m = mech.from_workload(w, "fp64")
+    before = mech.states_of(m)
+    v_before = m.nodes()["v"]
+    ms = m.autotune(w.dt, "clamp", nsteps=8, reps=2, path="resident")
+    after = mech.states_of(m)
+    assert ms > 0
+    for s in range(len(w.slots)):
+        for name in before[s]:
+            assert np.array_equal(before[s][name], after[s][name])
+    assert np.array_equal(v_before, m.nodes()["v"])
+    log(f"resident autotune: {m.get_launch()} at {ms:.4f} ms/step")
+    got, _ = run_gpu(w, 40, "resident", "fp64", launch=m.get_launch(), resident_steps=16)
+    M = run_oracle(w, 40)
+    compare_states(got, M, "fp64", label="resident autotuned")
+    with pytest.raises(mech.MechError):
+        m.autotune(w.dt, "external", nsteps=4, reps=1, path="resident")
+
+
 def test_resident_rejects():
     """Modes whose v comes from elsewhere, tiles beyond the LDS of a
     workgroup and out-of-range chunk lengths are errors, raised before any
