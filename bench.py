@@ -38,7 +38,7 @@ BYTES_PER_INSTANCE = {
 # Launch shapes of the time-fused path on the default workload (measured
 # over block 256/512/1024 and tiles of 512-2048 instances): each tile must
 # fit the LDS of a workgroup, and smaller tiles let more of them share a CU.
-RESIDENT_SHAPE = {"fp64": (256, 512, 256, 0, 1), "fp32": (512, 2048, 1024, 0, 1)}
+RESIDENT_SHAPE = {"fp64": (256, 512, 512, 0, 1), "fp32": (512, 2048, 1024, 0, 1)}
 
 
 def is_identity(slot, n_nodes) -> bool:
@@ -274,7 +274,7 @@ def main():
                     help="fixed batched launch shape 'block,tile_instances,tile_nodes,blocks_per_cu' (no autotune)")
     ap.add_argument("--resident-launch", default=None,
                     help="launch shape of the time-fused path 'block,tile_instances,tile_nodes,blocks_per_cu,flags' "
-                         "(default per precision: FP64 256,512,256,0,1; FP32 512,2048,1024,0,1)")
+                         "(default: the tuning cache, else FP64 256,512,512,0,1 and FP32 512,2048,1024,0,1)")
     ap.add_argument("--resident-steps", type=int, default=64, help="steps per launch of the time-fused path")
     args = ap.parse_args()
 

@@ -129,41 +129,59 @@ struct FusedArgs {
 
 // Time-fused path: each workgroup stages one tile (its nodes and every
 // instance on them) in LDS, advances it over `nsub` steps there, and writes
-// it back once.  Per-slot shapes come from the kind table on the host.
+// it back once.
 struct ResArgs {
     long long k0;              // step of the launch's first current update
     int nsub;                  // current updates (steps) in this launch
     int first_state;           // state update of step k0-1 before the first current update
     int last_state;            // state update at v_{k0+nsub} after the last one
-    int ss;                    // bytes of a stored STATE (8 FP64, 4 FP32-mixed)
-    int n_state[kMaxSlots], n_param[kMaxSlots];
-    int param_double[kMaxSlots];   // bit j: PARAMETER j is stored in FP64 in both precisions
-    int has_ica[kMaxSlots], has_gid[kMaxSlots];
 };
+
+// The arrays of a mechanism kind as the time-fused path stages them: STATEs,
+// PARAMETERs (bit j of param_double: stored in FP64 in both precisions),
+// the calcium current, the event stream id.  A compile-time copy of the
+// kind table's shapes, checked against it on the host before every launch.
+struct KindShape {
+    int n_state, n_param, param_double, has_ica, has_gid;
+};
+__host__ __device__ constexpr KindShape kind_shape(int kind) {
+    return kind == MECH_PAS       ? KindShape{0, 2, 0, 0, 0}
+           : kind == MECH_HH      ? KindShape{3, 4, 0, 0, 0}
+           : kind == MECH_IH      ? KindShape{1, 1, 0, 0, 0}
+           : kind == MECH_CAHVA   ? KindShape{3, 1, 0, 1, 0}
+           : kind == MECH_SYN     ? KindShape{4, 1, 1, 0, 1}
+           : kind == MECH_KMARKOV ? KindShape{3, 1, 0, 0, 0}
+           : kind == MECH_CAPUMP  ? KindShape{3, 1, 0, 1, 0}
+           : kind == MECH_CABUF   ? KindShape{4, 1, 0, 1, 0}
+                                  : KindShape{0, 0, 0, 0, 0};
+}
 
 __host__ __device__ inline size_t res_round8(size_t b) { return (b + 7) & ~(size_t)7; }
 
-// LDS bytes of one slot's instance arrays in a tile of n of its instances:
-// STATEs, PARAMETERs, ica, the tile-local node index, the event stream id.
-__host__ __device__ inline size_t res_slot_bytes(const ResArgs &r, int s, int n) {
+// LDS bytes of one slot's instance arrays in a tile of n of its instances
+// (ss: bytes of a stored STATE): STATEs, PARAMETERs, ica, the tile-local
+// node index, the event stream id.
+__host__ __device__ inline size_t res_slot_bytes(int kind, int n, int ss) {
+    const KindShape k = kind_shape(kind);
     const size_t nn = (size_t)n;
     size_t b = 0;
-    for (int j = 0; j < r.n_state[s]; ++j) b += res_round8(nn * r.ss);
-    for (int j = 0; j < r.n_param[s]; ++j) b += res_round8(nn * (((r.param_double[s] >> j) & 1) ? 8 : r.ss));
-    if (r.has_ica[s]) b += res_round8(nn * r.ss);
+    for (int j = 0; j < k.n_state; ++j) b += res_round8(nn * ss);
+    for (int j = 0; j < k.n_param; ++j) b += res_round8(nn * (((k.param_double >> j) & 1) ? 8 : ss));
+    if (k.has_ica) b += res_round8(nn * ss);
     b += res_round8(nn * 4);
-    if (r.has_gid[s]) b += res_round8(nn * 4);
+    if (k.has_gid) b += res_round8(nn * 4);
     return b;
 }
 
 // LDS doubles per tile node: v, rhs and d accumulators, 100/area (point
 // processes), cm (isolated) or the four clamp waveform parameters, and the
-// shared calcium ion's cai and ica accumulator; then an int spike counter.
+// shared calcium ion's cai and ica accumulator; then an int spike counter
+// per node and a 16-byte aligned table of 16 bytes per slot.
 __host__ __device__ inline int res_node_doubles(int vmode, bool has_syn, bool ion) {
     return 3 + (has_syn ? 1 : 0) + (vmode == MECH_V_CLAMP ? 4 : 1) + (ion ? 2 : 0);
 }
 __host__ __device__ inline size_t res_node_bytes(int nn, int vmode, bool has_syn, bool ion) {
-    return 8 * (size_t)nn * res_node_doubles(vmode, has_syn, ion) + res_round8(4 * (size_t)nn);
+    return 8 * (size_t)nn * res_node_doubles(vmode, has_syn, ion) + res_round8(4 * (size_t)nn) + 8 + 16 * kMaxSlots;
 }
 
 struct PlainArgs {

@@ -693,30 +693,29 @@ int step_batched(mech_ctx *c, int64_t nsteps, int64_t k0, double dt, int vmode, 
 }
 
 // ------------------------------------------------------ time-fused path --
-ResArgs res_args(const mech_ctx *c) {
-    ResArgs r{};
-    r.ss = c->fp32 ? 4 : 8;
-    for (int s = 0; s < (int)c->slots.size(); ++s) {
-        const SlotHost &h = c->slots[s];
+// The time-fused kernels stage each kind by its compile-time shape; check
+// that shape against the kind table the buffer layout was carved from.
+int res_check_shapes(mech_ctx *c) {
+    for (const SlotHost &h : c->slots) {
         const KindDesc &K = kKinds[h.kind];
-        r.n_state[s] = K.n_state;
-        r.n_param[s] = K.n_param;
-        for (int j = 0; j < K.n_param; ++j)
-            if (K.param[j].is_double || !c->fp32) r.param_double[s] |= 1 << j;
-        r.has_ica[s] = h.has_ica ? 1 : 0;
-        r.has_gid[s] = K.point_process ? 1 : 0;
+        const KindShape ks = kind_shape(h.kind);
+        int dbl = 0;
+        for (int j = 0; j < K.n_param; ++j) dbl |= K.param[j].is_double ? 1 << j : 0;
+        if (ks.n_state != K.n_state || ks.n_param != K.n_param || ks.param_double != dbl ||
+            ks.has_ica != (h.has_ica ? 1 : 0) || ks.has_gid != (K.point_process ? 1 : 0))
+            return fail(c, MECH_ERR_STATE, "internal: staged shape of kind %s differs from the kind table", K.name);
     }
-    return r;
+    return MECH_OK;
 }
 
 // Dynamic LDS of the largest tile of the current table.
-size_t res_lds_need(const mech_ctx *c, const ResArgs &r, int vmode, bool ion) {
-    const int ns = (int)c->slots.size(), row = 1 + ns;
+size_t res_lds_need(const mech_ctx *c, int vmode, bool ion) {
+    const int ns = (int)c->slots.size(), row = 1 + ns, ss = c->fp32 ? 4 : 8;
     size_t need = 0;
     for (int64_t t = 0; t < c->n_tiles; ++t) {
         const int32_t *r0 = c->tile_rows.data() + (size_t)t * row, *r1 = r0 + row;
         size_t b = res_node_bytes(r1[0] - r0[0], vmode, c->has_syn, ion);
-        for (int s = 0; s < ns; ++s) b += res_slot_bytes(r, s, r1[1 + s] - r0[1 + s]);
+        for (int s = 0; s < ns; ++s) b += res_slot_bytes(c->slots[s].kind, r1[1 + s] - r0[1 + s], ss);
         need = std::max(need, b);
     }
     return need;
@@ -735,9 +734,11 @@ size_t device_lds_bytes() {
 int step_resident(mech_ctx *c, int64_t nsteps, int64_t k0, double dt, int vmode) {
     if (vmode != MECH_V_CLAMP && vmode != MECH_V_ISOLATED)
         return fail(c, MECH_ERR_INVAL, "the time-fused path provides v itself: clamp or isolated mode only");
+    int rc = res_check_shapes(c);
+    if (rc) return rc;
     const GlobDev g = make_glob(c, dt);
-    ResArgs r = res_args(c);
-    const size_t need = res_lds_need(c, r, vmode, g.shared_ca != 0), cap = device_lds_bytes();
+    ResArgs r{};
+    const size_t need = res_lds_need(c, vmode, g.shared_ca != 0), cap = device_lds_bytes();
     if (need > cap)
         return fail(c, MECH_ERR_STATE,
                     "a tile needs %zu B of LDS on the time-fused path, the device allows %zu: lower "
@@ -1279,7 +1280,7 @@ static int autotune_impl(mech_ctx *c, double dt, int vmode, int nsteps, int reps
         if (rc) break;
         rc = mech_set_launch(c, sh.block, sh.budget, sh.nodes, sh.bpc, sh.flags);
         if (rc) break;
-        if (resident && res_lds_need(c, res_args(c), vmode, ion_on) > cap) continue;
+        if (resident && res_lds_need(c, vmode, ion_on) > cap) continue;
         auto run = [&](int n, int64_t k0) {
             return resident ? step_resident(c, n, k0, dt, vmode) : step_batched(c, n, k0, dt, vmode, false);
         };
