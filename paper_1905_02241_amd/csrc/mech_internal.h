@@ -174,14 +174,15 @@ __host__ __device__ inline size_t res_slot_bytes(int kind, int n, int ss) {
 }
 
 // LDS doubles per tile node: v, rhs and d accumulators, 100/area (point
-// processes), cm (isolated) or the four clamp waveform parameters, and the
+// processes), 1e-3 cm/dt (isolated) or the four clamp waveform parameters, and the
 // shared calcium ion's cai and ica accumulator; then an int spike counter
-// per node and a 16-byte aligned table of 16 bytes per slot.
+// per node and a 16-byte aligned table: 16 bytes per slot and 32 bytes of
+// run ends.
 __host__ __device__ inline int res_node_doubles(int vmode, bool has_syn, bool ion) {
     return 3 + (has_syn ? 1 : 0) + (vmode == MECH_V_CLAMP ? 4 : 1) + (ion ? 2 : 0);
 }
 __host__ __device__ inline size_t res_node_bytes(int nn, int vmode, bool has_syn, bool ion) {
-    return 8 * (size_t)nn * res_node_doubles(vmode, has_syn, ion) + res_round8(4 * (size_t)nn) + 8 + 16 * kMaxSlots;
+    return 8 * (size_t)nn * res_node_doubles(vmode, has_syn, ion) + res_round8(4 * (size_t)nn) + 8 + 16 * (kMaxSlots + 2);
 }
 
 struct PlainArgs {

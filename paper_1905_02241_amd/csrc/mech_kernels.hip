@@ -1246,33 +1246,28 @@ __device__ __forceinline__ void res_copy(const SlotDev &g, const SlotDev &l, int
 // The slots' runs are laid end to end, each padded to a whole wave, and the
 // block's threads stride over that sequence: every thread gets an equal
 // share whatever the mix of types, and every wave works on one type.  A wave
-// finds its run by comparing its first position with the runs' ends (scalar
-// registers) and reads the run's start, LDS offset, count and kind from a
-// table the tile keeps in LDS.  Measured against the alternatives on the
-// 100 M-instance workload: rescanning the slots per wave from the tile table
-// in memory was 13 % (FP64) and 50 % (FP32) slower; keeping the whole table
-// in scalar registers spilled them and was 21 % / 31 % slower; walking the
-// slots in an outer loop with each slot's descriptor live across its run
-// was slower still.
+// finds its run by comparing its first position with the runs' ends and
+// reads the run's start, LDS offset, count and kind from a table the tile
+// keeps in LDS (ends included: scalar registers are the scarce resource
+// here, and every value kept in them across the loop is spilled and
+// reloaded with VALU instructions).  Measured against the alternatives on
+// the 100 M-instance workload, FP64 / FP32 ms per step: this 1.08 / 0.53;
+// the ends in scalar registers 1.26 / 0.62; rescanning the slots per wave
+// from the tile table in memory 1.42 / 0.93; the whole table in scalar
+// registers 1.52 / 0.81.
 template <class S, int PH, bool EXT>
 __device__ __forceinline__ void res_pass(const FusedArgs &a, const int *r0, const int *r1, const int4 *tab, char *inst,
                                          const double *vl, const double *sc, double *ar, double *ad, const double *cl,
                                          double *ai, long long k, bool ion, int &flag) {
-    int end[kMaxSlots];
-    int total = 0;
-#pragma unroll
-    for (int q = 0; q < kMaxSlots; ++q) {
-        const bool on = q < a.n_slots;
-        total += on ? (r1[1 + q] - r0[1 + q] + 63) & ~63 : 0;
-        end[q] = on ? total : 0x7fffffff;
-    }
+    const int4 *ends = tab + kMaxSlots;
+    const int total = __builtin_amdgcn_readfirstlane(ends[1].w);
     const int lane = (int)(threadIdx.x & 63);
     for (int g0 = (int)threadIdx.x - lane; g0 < total; g0 += (int)blockDim.x) {
         const int gw = __builtin_amdgcn_readfirstlane(g0);
-        int s = 0;
-#pragma unroll
-        for (int q = 0; q < kMaxSlots - 1; ++q) s += gw >= end[q] ? 1 : 0;
-        const int4 t = tab[s];
+        const int4 e0 = ends[0], e1 = ends[1];
+        const int s = (gw >= e0.x) + (gw >= e0.y) + (gw >= e0.z) + (gw >= e0.w) + (gw >= e1.x) + (gw >= e1.y) +
+                      (gw >= e1.z);
+        const int4 t = tab[__builtin_amdgcn_readfirstlane(s)];
         const int base = __builtin_amdgcn_readfirstlane(t.x), o = __builtin_amdgcn_readfirstlane(t.y);
         const int n = __builtin_amdgcn_readfirstlane(t.z), kind = __builtin_amdgcn_readfirstlane(t.w);
         const int i = gw - base + lane;
@@ -1318,23 +1313,29 @@ __global__ __launch_bounds__(1024) void k_resident(FusedArgs a, ResArgs r) {
         double *vl = lds, *ar = lds + nn, *ad = lds + 2 * nn, *q = lds + 3 * nn;
         double *sc = q;
         if (syn) q += nn;
-        double *md = q;   // cm (isolated) or the clamp waveform, 4 per node
+        double *md = q;   // 1e-3 cm/dt (isolated) or the clamp waveform, 4 per node
         q += (VM == MECH_V_CLAMP ? 4 : 1) * nn;
         double *cl = q, *ai = q + nn;
         if (ion) q += 2 * nn;
         int *spk = (int *)q;
         const size_t toff = (((char *)q - (char *)lds) + res_round8(4 * (size_t)nn) + 15) & ~(size_t)15;
         int4 *tab = (int4 *)((char *)lds + toff);
-        char *inst = (char *)(tab + kMaxSlots);
+        char *inst = (char *)(tab + kMaxSlots + 2);
         // per slot: start of its run, LDS offset of its arrays, count, kind
         if (threadIdx.x == 0) {
             int pos = 0, bytes = 0;
-            for (int s = 0; s < a.n_slots; ++s) {
-                const int n = r1[1 + s] - r0[1 + s], kind = a.slot[s].kind;
+            int e[2 * 4];
+            for (int s = 0; s < kMaxSlots; ++s) {
+                const bool on = s < a.n_slots;
+                const int n = on ? r1[1 + s] - r0[1 + s] : 0, kind = on ? a.slot[s].kind : -1;
                 tab[s] = make_int4(pos, bytes, n, kind);
                 pos += (n + 63) & ~63;
-                bytes += (int)res_slot_bytes(kind, n, sizeof(S));
+                bytes += on ? (int)res_slot_bytes(kind, n, sizeof(S)) : 0;
+                e[s] = on ? pos : 0x7fffffff;
             }
+            // run ends of slots 0..6, then the total (the last run's end)
+            tab[kMaxSlots] = make_int4(e[0], e[1], e[2], e[3]);
+            tab[kMaxSlots + 1] = make_int4(e[4], e[5], e[6], pos);
         }
         for (int j = threadIdx.x; j < nn; j += blockDim.x) {
             const int n = nlo + j;
@@ -1348,7 +1349,7 @@ __global__ __launch_bounds__(1024) void k_resident(FusedArgs a, ResArgs r) {
                 md[4 * j + 2] = a.nd.c_freq[n];
                 md[4 * j + 3] = a.nd.c_phase[n];
             } else {
-                md[j] = a.nd.cm[n];
+                md[j] = 1e-3 * a.nd.cm[n] / a.g.dt;
             }
             if (ion) {
                 cl[j] = a.nd.cai[n];
@@ -1380,7 +1381,7 @@ __global__ __launch_bounds__(1024) void k_resident(FusedArgs a, ResArgs r) {
                 const double rr = ar[j], dd = ad[j], v0 = vl[j];
                 double v1;
                 if (VM == MECH_V_ISOLATED) {
-                    v1 = v0 + rr / (1e-3 * md[j] / a.g.dt + dd);
+                    v1 = v0 + rr / (md[j] + dd);
                     if (v0 < a.g.vthresh && v1 >= a.g.vthresh) spk[j] += 1;
                 } else {
                     const double t1 = (double)(k + 1) * a.g.dt;
