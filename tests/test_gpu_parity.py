@@ -185,9 +185,14 @@ def test_empty_and_degenerate_inputs():
     m.step(5, 0, 0.025, "external", "plain")
     got = m.nodes()
     assert np.count_nonzero(got["rhs"]) <= 2
+    m.step(0, 0, 0.025, "isolated", "resident")
+    m.step(5, 5, 0.025, "isolated", "resident")
+    got = m.nodes()
+    assert np.count_nonzero(got["rhs"]) <= 2
     m2 = mech.Mechanisms(4, [])
     m2.init()
     m2.step(3, 0, 0.025, "isolated", "batched")
+    m2.step(3, 3, 0.025, "isolated", "resident")
     m2.sync()
 
 
@@ -455,6 +460,19 @@ def test_variants_parity(variant, path, prec):
     M = run_oracle(w, 60)
     compare_states(got, M, prec, label=variant)
     compare_nodes(got, M, prec, label=variant)
+
+
+@pytest.mark.parametrize("variant", ["analytic_conductance", "pade_cnexp"])
+@pytest.mark.parametrize("prec", PRECS)
+def test_variants_resident(variant, prec):
+    """The section 5.2 variants on the time-fused path: every type, clamp,
+    launches of 9 steps."""
+    w = W.make_tiny(33, kinds=W.KINDS, per_node=2, nsteps=60)
+    w.globals[variant] = 1
+    got, m = run_gpu(w, 60, "resident", prec, launch=(128, 128, 64, 0, 1), resident_steps=9)
+    M = run_oracle(w, 60)
+    compare_states(got, M, prec, label=f"resident {variant}")
+    compare_nodes(got, M, prec, label=f"resident {variant}")
 
 
 @pytest.mark.parametrize("path", PATHS)
