@@ -440,6 +440,36 @@ def test_config2_resident_sampled(prec):
     _sampled(2, 4000, prec, "resident", 1500, launch=RES_SHAPE, resident_steps=64)
 
 
+@pytest.mark.parametrize("prec", PRECS)
+def test_config3_resident_sampled(prec):
+    """Synapses only, unsorted random index (sorted at alloc), 5 M instances."""
+    _sampled(3, 2000, prec, "resident", 300, launch=(128, 256, 128, 0, 1), resident_steps=64)
+
+
+def test_config4_resident_sampled():
+    _sampled(4, 2000, "fp64", "resident", 800, launch=RES_SHAPE, resident_steps=128)
+
+
+def test_config5_resident_fp32_reports():
+    """FP32-mixed in free-voltage mode on the time-fused path.  The voltage
+    feeds the FP32 state error back (the per-state bar holds under a clamp,
+    test_config2_resident_sampled), so this checks spike counts and reports
+    the state and voltage errors, as the per-step path's isolated FP32 test
+    does."""
+    w = W.make_config(5)
+    got, m = run_gpu(w, 1000, "resident", "fp32", launch=(512, 2048, 2048, 0, 1), resident_steps=64)
+    nodes = np.sort(np.random.default_rng(98).choice(w.n_nodes, size=1000, replace=False))
+    sub, keep = W.subset(w, nodes)
+    M = run_oracle(sub, 1000)
+    match = float(np.mean(got["spikes"][nodes] == M.spikes))
+    dv = float(np.max(np.abs(got["v"][nodes] - M.v)))
+    errs = {f"{sl.kind}.{name}": float(np.max(np.abs(got["states"][s][name][keep[s]] - ref)))
+            for s, sl in enumerate(M.w.slots) for name, ref in M.states[s].items() if ref.size}
+    log(f"c5 resident fp32: spike match {match:.4f} ({int(M.spikes.sum())} oracle spikes), max |dv| {dv:.3g} mV, "
+        f"state errors {errs}")
+    assert match >= 0.99
+
+
 def test_config5_resident_fp64_sampled_spikes():
     got, M, nodes = _sampled(5, 2000, "fp64", "resident", 1500, launch=RES_SHAPE, resident_steps=64)
     assert np.array_equal(got["spikes"][nodes], M.spikes)
