@@ -250,6 +250,44 @@ def precision_report(w, steps: int, sample: int, torch, mech):
     return out
 
 
+def variant_accuracy(w, settings, steps: int, sample: int):
+    """How far a section 5.2 variant (closed-form conductance, Pade cnexp)
+    moves the results: the oracle with the variant's globals against the
+    oracle without them, per state, on a node sample."""
+    import copy
+    import numpy as np
+    from oracle import oracle as O
+    sub, keep, nodes = node_sample(w, sample, 11)
+    runs = []
+    for on in (False, True):
+        s = copy.deepcopy(sub)
+        for k, v in settings.items():
+            s.globals[k] = v if on else 0
+        M = O.Model(s)
+        M.init()
+        M.run(0, steps)
+        runs.append(M)
+    exact, var = runs
+    out = {"steps": steps, "sample_nodes": int(nodes.shape[0]), "vmode": w.vmode}
+    for s, sl in enumerate(sub.slots):
+        for name, ref in exact.states[s].items():
+            if ref.size == 0:
+                continue
+            d = np.abs(var.states[s][name] - ref)
+            out[f"{sl.kind}.{name}"] = {"max_abs": float(d.max()),
+                                        "max_rel": float((d / np.maximum(np.abs(ref), 1e-300)).max())}
+    out["v"] = {"max_abs": float(np.max(np.abs(var.v - exact.v)))}
+    for key in ("rhs", "d"):
+        a, b = getattr(exact, key), getattr(var, key)
+        # relative to the largest magnitude on the sample: rhs crosses zero
+        out[key] = {"max_abs": float(np.max(np.abs(b - a))),
+                    "rel_to_max": float(np.max(np.abs(b - a)) / max(float(np.max(np.abs(a))), 1e-300))}
+    if w.vmode in ("isolated", "cable"):
+        out["spikes"] = {"match_rate": float(np.mean(var.spikes == exact.spikes)),
+                         "exact_total": int(exact.spikes.sum()), "variant_total": int(var.spikes.sum())}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -276,7 +314,26 @@ def main():
                     help="launch shape of the time-fused path 'block,tile_instances,tile_nodes,blocks_per_cu,flags' "
                          "(default: the tuning cache, else FP64 256,512,512,0,1 and FP32 512,2048,1024,0,1)")
     ap.add_argument("--resident-steps", type=int, default=64, help="steps per launch of the time-fused path")
+    ap.add_argument("--set", action="append", default=[], metavar="NAME=VALUE",
+                    help="set a global of the workload (e.g. pade_cnexp=1, analytic_conductance=1); repeatable")
+    ap.add_argument("--variant-accuracy", type=int, default=0, metavar="NODES",
+                    help="instead of timing: the oracle with the --set globals against the oracle without them, "
+                         "per state, on a node sample (CPU only)")
     args = ap.parse_args()
+
+    settings = {}
+    for kv in args.set:
+        k, _, v = kv.partition("=")
+        settings[k.strip()] = float(v)
+
+    if args.variant_accuracy:
+        from paper_1905_02241_amd import workloads as W
+        w = W.make_config(args.config, scale=args.scale)
+        if args.vmode:
+            w.vmode = args.vmode
+        rep = variant_accuracy(w, settings, args.steps, args.variant_accuracy)
+        print(json.dumps({"variant_accuracy": rep, "workload": w.name, "set": settings}), flush=True)
+        return
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the mechanism path has no "
@@ -301,8 +358,10 @@ def main():
             print(f"workload {w.name} has no clamp waveform", file=sys.stderr)
             sys.exit(2)
         w.vmode = args.vmode
+    for k, v in settings.items():
+        w.globals[k] = v
     log(f"workload {w.name}: {w.n_nodes} nodes, {w.instance_counts()}, vmode {w.vmode}, "
-        f"built in {time.perf_counter() - t0:.1f}s")
+        f"built in {time.perf_counter() - t0:.1f}s" + (f", globals set {settings}" if settings else ""))
 
     if args.precision_report:
         rep = precision_report(w, args.steps, args.precision_report, torch, mech)
@@ -344,7 +403,8 @@ def main():
         "dtype": "f64" if prec == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": w.name, "n_nodes": w.n_nodes, "instances": w.instance_counts(),
-                   "dt_ms": w.dt, "vmode": w.vmode, "path": head_key, "parallelism": "single GPU"},
+                   "dt_ms": w.dt, "vmode": w.vmode, "path": head_key, "parallelism": "single GPU",
+                   **({"globals_set": settings} if settings else {})},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(w, prec),
                      "kernel": f"k_fused (state+cur, {w.vmode})",
