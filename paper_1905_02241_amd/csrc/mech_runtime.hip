@@ -355,6 +355,9 @@ struct mech_ctx {
     // time-fused path: steps per launch, and the dynamic LDS its kernels may take
     int res_steps = 32;
     size_t res_lds_allowed = 0;
+    // largest tile's LDS on that path per (voltage mode, shared ion), for the
+    // current tile table (cleared when the table is rebuilt)
+    std::map<std::pair<int, int>, size_t> res_lds_cache;
     // graphs of kGraphSteps fused steps, keyed by (vmode, dt)
     std::map<std::pair<int, uint64_t>, hipGraphExec_t> graphs;
     std::string err;
@@ -505,6 +508,7 @@ int build_tiles(mech_ctx *c) {
                              c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->tile_rows = std::move(rows);
+    c->res_lds_cache.clear();
     clear_graphs(c);
     return MECH_OK;
 }
@@ -709,7 +713,10 @@ int res_check_shapes(mech_ctx *c) {
 }
 
 // Dynamic LDS of the largest tile of the current table.
-size_t res_lds_need(const mech_ctx *c, int vmode, bool ion) {
+size_t res_lds_need(mech_ctx *c, int vmode, bool ion) {
+    const auto key = std::make_pair(vmode, ion ? 1 : 0);
+    const auto hit = c->res_lds_cache.find(key);
+    if (hit != c->res_lds_cache.end()) return hit->second;
     const int ns = (int)c->slots.size(), row = 1 + ns, ss = c->fp32 ? 4 : 8;
     size_t need = 0;
     for (int64_t t = 0; t < c->n_tiles; ++t) {
@@ -718,6 +725,7 @@ size_t res_lds_need(const mech_ctx *c, int vmode, bool ion) {
         for (int s = 0; s < ns; ++s) b += res_slot_bytes(c->slots[s].kind, r1[1 + s] - r0[1 + s], ss);
         need = std::max(need, b);
     }
+    c->res_lds_cache[key] = need;
     return need;
 }
 

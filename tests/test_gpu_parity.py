@@ -346,6 +346,18 @@ def test_resident_all_kinds_clamp(prec):
     log(f"resident clamp {prec}: worst state ratio {max(v[0] for v in ws.values()):.3g}, nodes {wn}")
 
 
+@pytest.mark.parametrize("bpc", [1, 3])
+def test_resident_persistent_grid(bpc):
+    """A grid of a few workgroups per CU, each taking tile after tile (and
+    the plain tile order): the same results as the oracle."""
+    w = W.make_tiny(66, kinds=W.KINDS, n_nodes=8000, per_node=1, nsteps=50)
+    got, m = run_gpu(w, 50, "resident", "fp64", launch=(64, 64, 64, bpc, 0), resident_steps=20)
+    assert m.info()["n_tiles"] > 256 * bpc
+    M = run_oracle(w, 50)
+    compare_states(got, M, "fp64", label=f"resident persistent {bpc}")
+    compare_nodes(got, M, "fp64", label=f"resident persistent {bpc}")
+
+
 @pytest.mark.parametrize("steps", [1, 64, 1000])
 def test_resident_isolated_fp64_spikes(steps):
     """Free voltage: states, v and spike counts exact against the oracle for
