@@ -90,12 +90,16 @@ def log(msg):
 
 
 def time_variant(w, prec, path, steps, warmup, autotune, torch, mech, launch=None, save_tuning=None,
-                 resident=None):
+                 resident=None, plain_atomic=False):
     t0 = time.perf_counter()
     m = mech.from_workload(w, prec)
     torch.cuda.synchronize()
     log(f"{prec}-{path}: context ready in {time.perf_counter() - t0:.1f}s ({m.nbytes / 1e9:.2f} GB)")
     tuned = None
+    if path == "plain" and plain_atomic:
+        b, t, n, bpc, fl = m.get_launch()
+        m.set_launch(b, t, n, bpc, fl | mech.LAUNCH_PLAIN_ATOMIC)
+        tuned = {"scatter": "one FP64 atomic per instance"}
     if path == "resident":
         from paper_1905_02241_amd import tuning
         shape, nsub, given = resident
@@ -314,6 +318,9 @@ def main():
                     help="launch shape of the time-fused path 'block,tile_instances,tile_nodes,blocks_per_cu,flags' "
                          "(default: the tuning cache, else FP64 256,512,512,0,1 and FP32 512,2048,1024,0,1)")
     ap.add_argument("--resident-steps", type=int, default=64, help="steps per launch of the time-fused path")
+    ap.add_argument("--plain-scatter", default="segmented", choices=("segmented", "atomic"),
+                    help="scatter of the plain path's current update: the wave-segmented per-node sum (default) "
+                         "or one FP64 atomic per instance")
     ap.add_argument("--set", action="append", default=[], metavar="NAME=VALUE",
                     help="set a global of the workload (e.g. pade_cnexp=1, analytic_conductance=1); repeatable")
     ap.add_argument("--variant-accuracy", type=int, default=0, metavar="NODES",
@@ -378,7 +385,7 @@ def main():
         shape = tuple(int(x) for x in args.resident_launch.split(",")) if args.resident_launch else RESIDENT_SHAPE[prec]
         resident = (shape, args.resident_steps, args.resident_launch is not None)
         res[v] = time_variant(w, prec, path, args.steps, args.warmup, args.autotune, torch, mech, launch,
-                              args.save_tuning, resident)
+                              args.save_tuning, resident, args.plain_scatter == "atomic")
 
     probe = None
     if not args.no_probe:

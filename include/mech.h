@@ -270,10 +270,12 @@ int mech_step(mech_ctx *ctx, int64_t nsteps, int64_t k0, double dt, int vmode, i
  * and flags (MECH_LAUNCH_XCD_ORDER: consecutive tiles on the same XCD, so
  * the cache lines two neighbouring tiles share stay in one L2;
  * MECH_LAUNCH_NONTEMPORAL: instance arrays streamed with the non-temporal
- * hint, as they are touched once per step).  Rebuilds
+ * hint, as they are touched once per step; MECH_LAUNCH_PLAIN_ATOMIC: the
+ * PLAIN path's current update scatters one FP64 atomic per instance instead
+ * of the wave-segmented per-node sum, for comparison).  Rebuilds
  * the tile table.  Results do not depend on the shape except for the
  * rounding order of rhs/d.                                                 */
-enum { MECH_LAUNCH_XCD_ORDER = 1, MECH_LAUNCH_NONTEMPORAL = 2 };
+enum { MECH_LAUNCH_XCD_ORDER = 1, MECH_LAUNCH_NONTEMPORAL = 2, MECH_LAUNCH_PLAIN_ATOMIC = 4 };
 int mech_set_launch(mech_ctx *ctx, int block, int tile_instances, int tile_nodes, int blocks_per_cu,
                     int flags);
 int mech_get_launch(const mech_ctx *ctx, int *block, int *tile_instances, int *tile_nodes,

@@ -192,6 +192,7 @@ struct PlainArgs {
     int *err;
     GlobDev g;
     NodesDev nd;
+    int atomic_scatter;        // one FP64 atomic per instance instead of the wave-segmented sum
 };
 
 // Launchers (defined in mech_kernels.hip).  All return hipGetLastError().

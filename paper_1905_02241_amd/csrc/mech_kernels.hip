@@ -621,6 +621,12 @@ __global__ __launch_bounds__(256) void k_plain_cur(PlainArgs a) {
             a.nd.rhs[ni] -= ci;
             a.nd.d[ni] += cg;
         }
+    } else if (a.atomic_scatter) {
+        // one FP64 atomic per instance (the comparison point of the sum below)
+        if (ni >= 0) {
+            unsafeAtomicAdd(&a.nd.rhs[ni], -ci);
+            unsafeAtomicAdd(&a.nd.d[ni], cg);
+        }
     } else if (segmented_sum(ni, ci, cg)) {
         // node-sorted instances: one FP64 atomic per node run in the wave
         unsafeAtomicAdd(&a.nd.rhs[ni], -ci);

@@ -576,6 +576,7 @@ int launch_plain_phase(mech_ctx *c, bool cur, int64_t k, const GlobDev &g, int a
     a.err = (int *)(c->buf + c->L.off_err);
     a.g = g;
     a.nd = c->nd;
+    a.atomic_scatter = (c->launch_flags & MECH_LAUNCH_PLAIN_ATOMIC) ? 1 : 0;
     if (cur && !accumulate) HIPCHK(c, launch_fill(c->nd.rhs, c->nd.d, (int)c->n_nodes, c->stream));
     if (cur && !accumulate && g.shared_ca) HIPCHK(c, launch_fill(c->nd.ica, c->nd.ica, (int)c->n_nodes, c->stream));
     for (int s = 0; s < (int)c->slots.size(); ++s) {
@@ -1188,7 +1189,7 @@ int mech_set_resident_steps(mech_ctx *c, int steps_per_launch) {
 
 int mech_set_launch(mech_ctx *c, int block, int tile_instances, int tile_nodes, int blocks_per_cu, int flags) {
     if (!c) return fail(nullptr, MECH_ERR_INVAL, "null ctx");
-    if (flags & ~(MECH_LAUNCH_XCD_ORDER | MECH_LAUNCH_NONTEMPORAL))
+    if (flags & ~(MECH_LAUNCH_XCD_ORDER | MECH_LAUNCH_NONTEMPORAL | MECH_LAUNCH_PLAIN_ATOMIC))
         return fail(c, MECH_ERR_INVAL, "unknown launch flags 0x%x", flags);
     if (block < 64 || block > 1024 || block % 64)
         return fail(c, MECH_ERR_INVAL, "block must be a multiple of 64 in [64, 1024]");

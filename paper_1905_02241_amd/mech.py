@@ -36,6 +36,7 @@ SYMBOLS = ("mech_required_bytes", "mech_alloc", "mech_bind_nodes", "mech_bind_cl
            "mech_sync", "mech_info", "mech_probe_stream", "mech_last_error", "mech_strerror", "mech_free")
 LAUNCH_XCD_ORDER = 1
 LAUNCH_NONTEMPORAL = 2
+LAUNCH_PLAIN_ATOMIC = 4
 
 
 class MechError(RuntimeError):

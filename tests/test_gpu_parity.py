@@ -102,6 +102,21 @@ def test_accumulate_adds_to_existing_rhs():
     assert a["rhs"].shape == (w.n_nodes,)
 
 
+def test_plain_atomic_scatter():
+    """The plain path's per-instance FP64 atomics (the comparison point of
+    the wave-segmented sum) on many synapses per node: rhs/d at the bar."""
+    w = W.make_tiny(71, kinds=("pas", "hh", "syn"), n_nodes=200, per_node=2, syn_per_node=12.0, nsteps=40)
+    m = mech.from_workload(w, "fp64")
+    b, t, n, bpc, fl = m.get_launch()
+    m.set_launch(b, t, n, bpc, fl | mech.LAUNCH_PLAIN_ATOMIC)
+    m.step(40, 0, w.dt, w.vmode, "plain")
+    m.sync()
+    got = {"states": mech.states_of(m), **m.nodes()}
+    M = run_oracle(w, 40)
+    compare_states(got, M, "fp64", label="plain atomic")
+    compare_nodes(got, M, "fp64", label="plain atomic")
+
+
 @pytest.mark.parametrize("path", PATHS)
 def test_node_index_bit_exact(path):
     """Dyadic conductances, reversals, voltages and dv make every product and
