@@ -4,7 +4,8 @@
     python -m paper_1905_02241_amd.build --asm    # also write the gfx950 assembly
 
 Flags: -O3, FP64 hardware atomics (-munsafe-fp-atomics), packed FP32
-instructions disabled (-target-feature -packed-fp32-ops), C++17.
+instructions disabled (-target-feature -packed-fp32-ops), C++17; linked
+against the roctx library for the entry points' trace ranges.
 """
 from __future__ import annotations
 
@@ -27,7 +28,7 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-    "-Wl,-rpath,/opt/rocm/lib",
+    "-Wl,-rpath,/opt/rocm/lib", "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx",
 ]
 
 

@@ -8,6 +8,8 @@
 #include "mech.h"
 #include "mech_internal.h"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
@@ -386,6 +388,15 @@ int fail(mech_ctx *c, int code, const char *fmt, ...) {
     } while (0)
 
 constexpr int kGraphSteps = 64;
+
+// A roctx range over an entry point's host work; rocprofv3 --marker-trace
+// attributes the kernels it enqueues to the range.
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
 
 void clear_graphs(mech_ctx *c) {
     for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
@@ -1137,6 +1148,7 @@ int mech_set_global(mech_ctx *c, const char *name, double value) {
 int mech_init(mech_ctx *c) {
     if (!c) return fail(nullptr, MECH_ERR_INVAL, "null ctx");
     if (!c->nodes_bound) return fail(c, MECH_ERR_STATE, "node vectors not bound (mech_bind_nodes)");
+    TraceRange range("mech_init");
     PlainArgs a{};
     a.err = (int *)(c->buf + c->L.off_err);
     a.g = make_glob(c, 0.025);
@@ -1155,6 +1167,7 @@ int mech_cur(mech_ctx *c, int64_t k, double dt, int accumulate) {
     int rc = check_ready(c, MECH_V_EXTERNAL);
     if (rc) return rc;
     if (!(dt > 0.0) || k < 0) return fail(c, MECH_ERR_INVAL, "need dt > 0 and k >= 0");
+    TraceRange range("mech_cur");
     return launch_plain_phase(c, true, k, make_glob(c, dt), accumulate);
 }
 
@@ -1163,6 +1176,7 @@ int mech_state(mech_ctx *c, double dt) {
     int rc = check_ready(c, MECH_V_EXTERNAL);
     if (rc) return rc;
     if (!(dt > 0.0)) return fail(c, MECH_ERR_INVAL, "need dt > 0");
+    TraceRange range("mech_state");
     return launch_plain_phase(c, false, 0, make_glob(c, dt), 0);
 }
 
@@ -1173,6 +1187,8 @@ int mech_step(mech_ctx *c, int64_t nsteps, int64_t k0, double dt, int vmode, int
     if (!(dt > 0.0) || k0 < 0 || nsteps < 0 || k0 + nsteps >= (int64_t(1) << 32))
         return fail(c, MECH_ERR_INVAL, "need dt > 0, k0 >= 0, nsteps >= 0, k0 + nsteps < 2^32");
     if (nsteps == 0) return MECH_OK;
+    static const char *const kRange[] = {"mech_step plain", "mech_step batched", "mech_step resident"};
+    TraceRange range(path >= 0 && path <= MECH_PATH_RESIDENT ? kRange[path] : "mech_step");
     if (path == MECH_PATH_PLAIN) return step_plain(c, nsteps, k0, dt, vmode);
     if (path == MECH_PATH_BATCHED) return step_batched(c, nsteps, k0, dt, vmode, true);
     if (path == MECH_PATH_RESIDENT) return step_resident(c, nsteps, k0, dt, vmode);
@@ -1228,6 +1244,7 @@ int mech_info(const mech_ctx *c, int64_t *n_tiles, int64_t *max_tile_nodes) {
 // the fastest; everything a step writes is saved before and restored after.
 static int autotune_impl(mech_ctx *c, double dt, int vmode, int nsteps, int reps, double *best_ms, bool resident) {
     if (!c) return fail(nullptr, MECH_ERR_INVAL, "null ctx");
+    TraceRange range(resident ? "mech_autotune_resident" : "mech_autotune");
     int rc = check_ready(c, vmode);
     if (rc) return rc;
     if (!(dt > 0.0) || nsteps < 1 || reps < 1) return fail(c, MECH_ERR_INVAL, "need dt > 0, nsteps >= 1, reps >= 1");

@@ -53,7 +53,8 @@ def test_library_host_code_under_address_and_undefined_sanitizers(tmp_path):
            "-Xarch_host", "-fno-omit-frame-pointer",
            "-I", os.path.join(ROOT, "include"), "-I", csrc,
            os.path.join(ROOT, "tests", "sanitize_host.cpp"), os.path.join(csrc, "mech_kernels.hip"),
-           os.path.join(csrc, "mech_runtime.hip"), "-o", exe]
+           os.path.join(csrc, "mech_runtime.hip"), "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx",
+           "-Wl,-rpath,/opt/rocm/lib", "-o", exe]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-3000:]
     # leak checking is off: the HIP runtime keeps its own allocations to exit
