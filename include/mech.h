@@ -281,7 +281,7 @@ int mech_set_launch(mech_ctx *ctx, int block, int tile_instances, int tile_nodes
 int mech_get_launch(const mech_ctx *ctx, int *block, int *tile_instances, int *tile_nodes,
                     int *blocks_per_cu, int *flags);
 
-/* Steps per launch of the RESIDENT path (1..4096, default 32): STATEs
+/* Steps per launch of the RESIDENT path (1..4096, default 64): STATEs
  * cross HBM once per launch.                                              */
 int mech_set_resident_steps(mech_ctx *ctx, int steps_per_launch);
 

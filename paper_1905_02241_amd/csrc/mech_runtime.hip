@@ -355,7 +355,7 @@ struct mech_ctx {
     std::vector<int32_t> tile_rows;   // host copy of the tile table
     int n_cu = 256;
     // time-fused path: steps per launch, and the dynamic LDS its kernels may take
-    int res_steps = 32;
+    int res_steps = 64;
     size_t res_lds_allowed = 0;
     // largest tile's LDS on that path per (voltage mode, shared ion), for the
     // current tile table (cleared when the table is rebuilt)

@@ -175,6 +175,27 @@ def test_launch_shapes_give_identical_states_under_clamp(prec):
                 assert np.array_equal(a, base["states"][s][name]), (shape, s, name)
 
 
+@pytest.mark.parametrize("prec", PRECS)
+def test_resident_states_bit_identical_under_clamp(prec):
+    """Under a clamp the states do not depend on rhs/d: the time-fused path,
+    at any shape and chunk length, gives the per-step fused path's states
+    (the same per-instance code).  FP64: bit-identical.  FP32: within a few
+    float ulps, since the compiler may contract a multiply-add of the FP32
+    rate code differently in the two kernels."""
+    w = W.make_tiny(8, kinds=W.KINDS, per_node=2, n_nodes=700, nsteps=40)
+    base, _ = run_gpu(w, 40, "batched", prec, launch=(256, 2048, 1024, 0))
+    for shape, steps in [((64, 64, 64, 0, 1), 1), ((128, 512, 256, 0, 1), 7), ((256, 1024, 512, 2, 0), 40)]:
+        got, m = run_gpu(w, 40, "resident", prec, launch=shape, resident_steps=steps)
+        for s in range(len(w.slots)):
+            for name, a in got["states"][s].items():
+                b = base["states"][s][name]
+                if prec == "fp64":
+                    assert np.array_equal(a, b), (shape, steps, s, name)
+                else:
+                    ulps = np.abs(a - b) / np.maximum(np.abs(b) * 2.0 ** -23, 1e-30)
+                    assert float(ulps.max()) <= 4.0, (shape, steps, s, name, float(ulps.max()))
+
+
 @pytest.mark.parametrize("path", PATHS)
 def test_medium_several_tiles_ragged(path):
     """5000 nodes, many small tiles and a ragged tail, all types."""
