@@ -4,6 +4,7 @@ device call) rejects bad input with the documented codes."""
 import ctypes as C
 import os
 import re
+import subprocess
 
 import numpy as np
 import pytest
@@ -131,3 +132,36 @@ def test_validation_codes(lib):
     assert lib.mech_step(None, 1, 0, 0.025, 1, 1) == mech.ERR_INVAL
     assert lib.mech_sync(None) == mech.ERR_INVAL
     lib.mech_free(None)
+
+
+def test_staged_kind_shapes_match_the_kind_tables(lib, tmp_path):
+    """The time-fused kernels stage each kind by a compile-time shape
+    (mech_internal.h).  It must match the binding's variable tables and the
+    library's buffer layout (mech_required_bytes in both precisions)."""
+    from paper_1905_02241_amd import workloads as W
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    csrc = os.path.join(ROOT, "paper_1905_02241_amd", "csrc")
+    exe = str(tmp_path / "kind_shapes")
+    r = subprocess.run([hipcc, "-O1", "-std=c++17", "-I", os.path.join(ROOT, "include"), "-I", csrc,
+                        os.path.join(ROOT, "tests", "kind_shapes.cpp"), "-o", exe], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-2000:]
+    out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split("\n")
+    shapes = {int(f[0]): tuple(int(x) for x in f[1:]) for f in (l.split() for l in out if l.strip())}
+    assert sorted(shapes) == list(range(len(W.KINDS)))
+    for kind, kid in mech.KIND.items():
+        n_state, n_param, dbl, ica, gid = shapes[kid]
+        assert n_state == len(mech.STATE_NAMES[kind]), kind
+        assert n_param == len(W.PARAM_NAMES[kind]), kind
+        assert ica == (kind in mech.CA_KINDS), kind
+        assert gid == (kind == "syn"), kind
+        # bytes per 64 padded instances in each precision, from the library
+        d, keep = _descs([(kind, np.arange(64))])
+        out64, out32 = C.c_size_t(), C.c_size_t()
+        assert lib.mech_required_bytes(64, d, 1, 0, C.byref(out64)) == 0
+        assert lib.mech_required_bytes(64, d, 1, 1, C.byref(out32)) == 0
+        n_dbl = bin(dbl).count("1")
+        per8 = n_state + n_param + ica          # 8-byte values per instance in FP64
+        per4 = n_state + (n_param - n_dbl) + ica  # values that shrink to 4 bytes in FP32
+        assert out64.value - out32.value == 64 * 4 * per4, (kind, per8, per4)
