@@ -1,20 +1,25 @@
 // mech_kernels.hip -- CDNA4 (gfx950) kernels of the mechanism library.
 //
 // Current update (BREAKPOINT, paper section 3) and state update (DERIVATIVE +
-// SOLVE cnexp, sections 3 and 5.2) of five mechanism types over SoA instance
-// arrays, in two launch structures:
+// SOLVE cnexp, sparse and derivimplicit; sections 3 and 5.2) of eight
+// mechanism types over SoA instance arrays, in three launch structures:
 //
-//   plain   one kernel per mechanism type and phase, a thread per instance,
-//           node vectors reached through the node index, many-to-one
-//           reductions by FP64 global atomics (the paper's per-mechanism
-//           kernel structure; section 8 notes the cost of its atomic
-//           reductions);
-//   fused   one kernel per timestep over a table of node tiles: each block
-//           stages its nodes' v in LDS, runs state(k-1), events(k) and cur(k)
-//           of every instance in the tile (coalesced SoA streams, a thread per
-//           instance), reduces into LDS accumulators, then writes rhs/d and
-//           provides v_{k+1} for its own nodes.  No global atomics.
+//   plain     one kernel per mechanism type and phase, a thread per
+//             instance, node vectors reached through the node index,
+//             many-to-one reductions by FP64 global atomics (the paper's
+//             per-mechanism kernel structure; section 8 notes the cost of
+//             its atomic reductions);
+//   fused     one kernel per timestep over a table of node tiles: each block
+//             stages its nodes' v in LDS, runs state(k-1), events(k) and
+//             cur(k) of every instance in the tile (coalesced SoA streams, a
+//             thread per instance), reduces into LDS accumulators, then
+//             writes rhs/d and provides v_{k+1} for its own nodes.  No
+//             global atomics;
+//   resident  the fused kernel's tiles kept in LDS for many steps (clamp and
+//             isolated modes), so STATEs cross HBM once per launch.
 //
+// Cable mode adds the tree solve (k_cable) between the current update and
+// the voltage.
 // The work is elementwise and exponential/division heavy (section 6 calls the
 // state kernels compute bound and the current kernels bandwidth bound); there
 // is no dense contraction, so no MFMA.  Precision: FP64 throughout, or FP32
