@@ -2,9 +2,10 @@
 //
 // Responsibilities: argument validation, stable node sort of every mechanism
 // type, carving of the caller's device buffer into 256-byte aligned SoA
-// arrays, the tile table of the fused path, the per-step launch sequences of
-// the plain and batched paths (the latter replayed from HIP graphs), the
-// launch-shape autotuner and host copies of STATEs in the caller's order.
+// arrays, the tile table of the fused path, the launch sequences of the
+// plain, batched (replayed from HIP graphs) and time-fused paths, the cut of
+// cell trees into units for the cable solve, the launch-shape autotuners,
+// host copies of STATEs in the caller's order, and roctx trace ranges.
 #include "mech.h"
 #include "mech_internal.h"
 
