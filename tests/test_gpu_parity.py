@@ -464,6 +464,39 @@ def test_resident_autotune_keeps_results():
         m.autotune(w.dt, "external", nsteps=4, reps=1, path="resident")
 
 
+@pytest.mark.parametrize("prec", PRECS)
+def test_resident_split_calls_and_resume(prec):
+    """Under a clamp: 80 steps in one call, in two calls (30 + 50), and as 30
+    steps, a checkpoint of every state into a fresh context, then 50 more,
+    all give bit-identical states on the time-fused path."""
+    w = W.make_tiny(67, kinds=W.KINDS, per_node=2, nsteps=80)
+    shape = (128, 256, 128, 0, 1)
+    full, _ = run_gpu(w, 80, "resident", prec, launch=shape, resident_steps=16)
+    a = mech.from_workload(w, prec)
+    a.set_launch(*shape)
+    a.set_resident_steps(16)
+    a.step(30, 0, w.dt, "clamp", "resident")
+    saved = mech.states_of(a)
+    a.step(50, 30, w.dt, "clamp", "resident")
+    a.sync()
+    split = mech.states_of(a)
+    b = mech.from_workload(w, prec)
+    b.set_launch(*shape)
+    b.set_resident_steps(16)
+    for s_, st in enumerate(saved):
+        for name, vals in st.items():
+            b.set_state(s_, name, vals)
+    b.step(50, 30, w.dt, "clamp", "resident")
+    b.sync()
+    resumed = mech.states_of(b)
+    for s_ in range(len(w.slots)):
+        for name, ref in full["states"][s_].items():
+            if name == "ica":
+                continue
+            assert np.array_equal(split[s_][name], ref), ("split", s_, name)
+            assert np.array_equal(resumed[s_][name], ref), ("resumed", s_, name)
+
+
 def test_resident_rejects():
     """Modes whose v comes from elsewhere, tiles beyond the LDS of a
     workgroup and out-of-range chunk lengths are errors, raised before any
