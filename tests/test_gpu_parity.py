@@ -898,7 +898,7 @@ def test_cable_single_nodes_equal_isolated():
 
 
 def test_config4_cable_whole_cell_sample():
-    """C4's 64 branched cells in cable mode at full size; the oracle runs
+    """The 64 branched cells (274 k compartments) in cable mode at full size; the oracle runs
     three whole cells (a cell is the unit the tree solve couples)."""
     w = W.make_config(4)
     w.vmode = "cable"
