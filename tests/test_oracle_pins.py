@@ -67,6 +67,56 @@ def test_hh_removable_singularities(oracle):
         assert abs(oracle.hh_rates(-55.0 + dx)[4] - 0.1 * ser) < 2e-16
 
 
+def _closed(name):
+    return {r[0]: (float(r[1]), float(r[2])) for r in _golden("hh_syn_ca_closed_forms.txt")}[name]
+
+
+def test_hh_time_constants_at_rest(oracle):
+    got = oracle.hh_inf_tau(-65.0, 6.3)[3:]
+    for name, g in zip(("tau_m_rest", "tau_h_rest", "tau_n_rest"), got):
+        val, tol = _closed(name)
+        assert abs(g - val) <= tol, name
+
+
+def test_hh_gates_after_clamp_step_to_minus20(oracle):
+    # away from -65 mV: beta_m, alpha_h and beta_n leave exp(0), so their
+    # exponent scales (18, 20, 80 mV) and signs decide these values
+    w = _single("hh", -20.0, 1000)
+    M = oracle.Model(w)
+    M.init()
+    M.run(0, 1000)
+    for k in "mhn":
+        val, tol = _closed(f"{k}_clamp_minus20_1000")
+        assert abs(M.states[0][k][0] - val) <= tol, k
+
+
+def test_hh_net_current_at_rest(oracle):
+    w = _single("hh", -65.0, 1)
+    M = oracle.Model(w)
+    M.init(-65.0)
+    val, tol = _closed("i_hh_net_rest")
+    assert abs(M.instance_current(0, 0, -65.0)[0] - val) <= tol
+
+
+def test_mg_block_values(oracle):
+    for v, name in ((-65.0, "mg_block_minus65"), (-20.0, "mg_block_minus20"), (0.0, "mg_block_0")):
+        val, tol = _closed(name)
+        assert abs(oracle.mg_block(v, 1.0) - val) <= tol, name
+
+
+def test_synapse_peak_factor_values(oracle):
+    for (tr, td), rec in (((0.2, 1.7), "ampa"), ((0.29, 43.0), "nmda")):
+        f, tp = oracle.syn_peak_factor(tr, td)
+        for got, name in ((f, f"f_{rec}"), (tp, f"tp_{rec}")):
+            val, tol = _closed(name)
+            assert abs(got - val) <= tol, name
+
+
+def test_calcium_reversal_at_rest_concentration(oracle):
+    val, tol = _closed("eca_cai0")
+    assert abs(oracle.nernst_ca(5e-5, 2.0, 6.3) - val) <= tol
+
+
 def test_q10_scales_time_constants_only(oracle):
     a = oracle.hh_inf_tau(-50.0, 6.3)
     b = oracle.hh_inf_tau(-50.0, 16.3)  # q10 = 3 exactly one decade up
