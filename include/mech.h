@@ -54,10 +54,14 @@
  *
  * Precision (MECH_FP64 / MECH_FP32_MIXED): FP64 keeps every variable in
  * double, as the paper's generated code does (section 4.3).  FP32_MIXED
- * stores STATEs and conductance PARAMETERs in float and computes rates and
- * the state update in float with the hardware exponential; v, the reversal
- * potentials, the driving force, the Nernst potential, the Mg block, the
- * finite difference and the rhs/d reduction stay in double.
+ * stores STATEs and every RANGE PARAMETER read each step in float
+ * (conductances and per-instance reversal potentials such as pas e and hh
+ * el; a float reversal potential moves by at most about 5e-6 mV) and
+ * computes rates and the state update in float with the hardware
+ * exponential.  v, the global reversal potentials (ena, ek, eh, e_syn), the
+ * driving force v - e (formed in double from the stored e), the Nernst
+ * potential, the Mg block, the finite difference and the rhs/d reduction
+ * stay in double; synaptic weights, read only on an event, stay in double.
  *
  * Memory ownership: the caller allocates one device buffer of
  * mech_required_bytes() bytes and passes it to mech_alloc(); the library
@@ -317,14 +321,25 @@ int mech_sync(mech_ctx *ctx);
 int mech_info(const mech_ctx *ctx, int64_t *n_tiles, int64_t *max_tile_nodes);
 
 /* Measurement aid (not part of a timestep): stream `bytes` (a multiple of
- * 16; device pointers, 16-byte aligned) with a grid-stride kernel of
- * blocks_per_cu * n_CU blocks of 256 threads on `hip_stream`, each thread
- * keeping `unroll` (1, 2, 4, 8) independent 16-byte accesses in flight:
- * op 0 copies src to dst, op 1 reads src (dst receives at most 16 bytes),
- * op 2 writes dst, op 3 reads src[0, bytes) and src[bytes, 2 bytes) and
- * writes their xor to dst (two reads per write).  The streaming HBM ceiling the mechanism kernels are
- * compared with.  Asynchronous.                                            */
-int mech_probe_stream(int op, int unroll, int blocks_per_cu, void *dst, const void *src, size_t bytes,
+ * 16; device pointers, 16-byte aligned) with blocks_per_cu * n_CU blocks of
+ * 256 threads on `hip_stream`, each thread keeping `unroll` (1, 2, 4, 8)
+ * independent accesses in flight:
+ *   op 0 copies src to dst;
+ *   op 1 reads src (dst receives at most 16 bytes);
+ *   op 2 writes dst;
+ *   op 3 reads src[0, bytes) and src[bytes, 2 bytes) and writes their xor
+ *        to dst (two reads per write, the STREAM-triad mix);
+ *   op 4 reads src[0, bytes) in the even workgroups and writes dst[0, bytes)
+ *        in the odd ones (read and write streams from different waves).
+ * `flags` (bitwise or of MECH_PROBE_*): non-temporal hint on the loads or
+ * on the stores, 8-byte instead of 16-byte accesses, and one contiguous
+ * chunk per workgroup instead of the grid-stride mapping.  The streaming HBM
+ * ceilings the mechanism kernels are compared with.  Asynchronous.         */
+#define MECH_PROBE_NT_LOAD 1
+#define MECH_PROBE_NT_STORE 2
+#define MECH_PROBE_8B 4
+#define MECH_PROBE_CHUNKED 8
+int mech_probe_stream(int op, int unroll, int blocks_per_cu, int flags, void *dst, const void *src, size_t bytes,
                       void *hip_stream);
 
 const char *mech_last_error(const mech_ctx *ctx);

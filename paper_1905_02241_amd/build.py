@@ -1,7 +1,8 @@
 """Build libmech.so (HIP, gfx950) in-tree.
 
     python -m paper_1905_02241_amd.build          # compile
-    python -m paper_1905_02241_amd.build --asm    # also write the gfx950 assembly
+    python -m paper_1905_02241_amd.build --asm [DIR]   # also write the gfx950 assembly
+                                                       # to DIR (default _build/asm)
 
 Flags: -O3, FP64 hardware atomics (-munsafe-fp-atomics), packed FP32
 instructions disabled (-target-feature -packed-fp32-ops), C++17; linked
@@ -32,7 +33,7 @@ FLAGS = [
 ]
 
 
-def build(asm: bool = False, verbose: bool = False) -> str:
+def build(asm: str = "", verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
     cmd = [HIPCC, *FLAGS, *SOURCES, "-o", tmp]
     if verbose:
@@ -40,7 +41,7 @@ def build(asm: bool = False, verbose: bool = False) -> str:
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     if asm:
-        out = os.path.join(ROOT, "_work", "asm")
+        out = asm
         os.makedirs(out, exist_ok=True)
         subprocess.check_call([HIPCC, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-munsafe-fp-atomics",
                                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -50,4 +51,8 @@ def build(asm: bool = False, verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(asm="--asm" in sys.argv, verbose=True)
+    asm_dir = ""
+    if "--asm" in sys.argv:
+        i = sys.argv.index("--asm")
+        asm_dir = sys.argv[i + 1] if i + 1 < len(sys.argv) else os.path.join(ROOT, "_build", "asm")
+    build(asm=asm_dir, verbose=True)
