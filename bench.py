@@ -292,6 +292,30 @@ def variant_accuracy(w, settings, steps: int, sample: int):
     return out
 
 
+PROBE_FLAG_SETS = ((), ("nt_load",), ("nt_store",), ("nt_load", "nt_store"), ("8b",), ("chunked",),
+                   ("chunked", "nt_store"), ("chunked", "nt_load", "nt_store"))
+
+
+def probe_battery(mech, nbytes: int = 1 << 32):
+    """Every streaming probe at its best unroll (2, 4, 8) and blocks per CU
+    (2, 4, 8, 16): GB/s per op and flag set."""
+    out = {}
+    for op in ("copy", "triad", "split", "read", "write"):
+        for fl in PROBE_FLAG_SETS:
+            if op == "read" and "nt_store" in fl or op == "write" and "nt_load" in fl:
+                continue
+            best = None
+            for u in (2, 4, 8):
+                for b in (2, 4, 8, 16):
+                    g = mech.probe_stream(op, nbytes, unroll=u, blocks_per_cu=b, reps=5, flags=fl)
+                    if best is None or g > best[0]:
+                        best = (g, u, b)
+            key = f"{op}[{'+'.join(fl) or 'plain'}]"
+            out[key] = {"GBps": round(best[0], 1), "unroll": best[1], "blocks_per_cu": best[2]}
+            log(f"probe {key}: {best[0]:.0f} GB/s (unroll {best[1]}, {best[2]} blocks per CU)")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -304,6 +328,10 @@ def main():
                     help="run the launch-shape autotuner even when the tuning cache has an entry")
     ap.add_argument("--save-tuning", default=None, help="JSON file to record autotuned shapes in")
     ap.add_argument("--no-probe", action="store_true", help="skip the streaming-copy ceiling probe")
+    ap.add_argument("--probe-battery", action="store_true",
+                    help="instead of timing the workload: every streaming probe (copy, triad, split read/write "
+                         "waves, read, write) with and without non-temporal hints, 8-byte accesses and chunked "
+                         "mapping, each at its best unroll and blocks per CU")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-nodes", type=int, default=20000)
@@ -354,6 +382,10 @@ def main():
         sys.exit(1)
     mech.load_library()
     torch.cuda.set_device(0)
+
+    if args.probe_battery:
+        print(json.dumps({"probe_battery": probe_battery(mech)}), flush=True)
+        return
 
     t0 = time.perf_counter()
     w = W.make_config(args.config, scale=args.scale)

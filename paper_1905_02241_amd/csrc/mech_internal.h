@@ -205,7 +205,8 @@ hipError_t launch_visolated(const NodesDev &nd, const GlobDev &g, hipStream_t s)
 hipError_t launch_init(bool fp32, const PlainArgs &a, hipStream_t s);
 hipError_t launch_plain_cur(bool fp32, const PlainArgs &a, hipStream_t s);
 hipError_t launch_plain_state(bool fp32, const PlainArgs &a, hipStream_t s);
-hipError_t launch_stream(int op, int unroll, void *dst, const void *src, size_t n16, int grid, hipStream_t s);
+hipError_t launch_stream(int op, int unroll, int flags, void *dst, const void *src, size_t bytes, int grid,
+                         hipStream_t s);
 hipError_t launch_cable(const CableDev &c, const NodesDev &nd, const GlobDev &g, hipStream_t s);
 hipError_t cable_allow_lds(size_t bytes);
 hipError_t launch_cable_coeffs(const CableDev &c, const double *area, int n_nodes, int n_edges, hipStream_t s);

@@ -1445,53 +1445,125 @@ __global__ __launch_bounds__(1024) void k_resident(FusedArgs a, ResArgs r) {
 // --------------------------------------------------------- HBM probe --
 // Streaming probes that set the achievable ceiling the kernels are held to:
 // op 0 copy, op 1 read (xor-reduced so the loads stay live), op 2 write,
-// op 3 two reads and one write (dst = src_a ^ src_b, the STREAM-triad mix).
-// Each thread keeps U independent 16-byte accesses in flight per round.
-template <int OP, int U>
-__global__ __launch_bounds__(256) void k_stream(uint4 *__restrict__ dst, const uint4 *__restrict__ src, size_t n,
-                                                 uint4 *__restrict__ sink) {
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint4 acc = make_uint4(0u, 0u, 0u, 0u);
-    for (; i + (U - 1) * stride < n; i += U * stride) {
-        uint4 x[U], y[U];
-        if (OP != 2) {
+// op 3 two reads and one write (dst = src_a ^ src_b, the STREAM-triad mix),
+// op 4 reads in the even workgroups and writes in the odd ones (the read and
+// write streams come from different waves).  Each thread keeps U independent
+// accesses of T (16 or 8 bytes) in flight per round; NTL / NTS put the
+// non-temporal hint on the loads / stores.  The grid-stride mapping
+// interleaves all workgroups over the whole range; `chunked` gives each
+// workgroup one contiguous range instead (threads still stride by the
+// workgroup, so every wave access stays contiguous).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+template <class T> __device__ __forceinline__ unsigned fold(T x) {
+    unsigned r = 0;
 #pragma unroll
-            for (int u = 0; u < U; ++u) x[u] = src[i + u * stride];
-        }
-        if (OP == 3) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) y[u] = src[n + i + u * stride];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (OP == 0) dst[i + u * stride] = x[u];
-            if (OP == 3) dst[i + u * stride] = make_uint4(x[u].x ^ y[u].x, x[u].y ^ y[u].y, x[u].z ^ y[u].z, x[u].w ^ y[u].w);
-            if (OP == 1) { acc.x ^= x[u].x; acc.y ^= x[u].y; acc.z ^= x[u].z; acc.w ^= x[u].w; }
-            if (OP == 2) dst[i + u * stride] = make_uint4((unsigned)i, 0u, 0u, (unsigned)u);
-        }
-    }
-    for (; i < n; i += stride) {
-        if (OP == 0) dst[i] = src[i];
-        if (OP == 3) { const uint4 x = src[i], y = src[n + i]; dst[i] = make_uint4(x.x ^ y.x, x.y ^ y.y, x.z ^ y.z, x.w ^ y.w); }
-        if (OP == 1) { const uint4 x = src[i]; acc.x ^= x.x; acc.y ^= x.y; acc.z ^= x.z; acc.w ^= x.w; }
-        if (OP == 2) dst[i] = make_uint4((unsigned)i, 0u, 0u, 0u);
-    }
-    if (OP == 1 && (acc.x | acc.y | acc.z | acc.w) == 0x9E3779B9u) sink[0] = acc;  // practically never
+    for (int c = 0; c < (int)(sizeof(T) / 4); ++c) r |= x[c];
+    return r;
 }
 
-hipError_t launch_stream(int op, int unroll, void *dst, const void *src, size_t n16, int grid, hipStream_t s) {
-    if (n16 == 0) return hipSuccess;
-    uint4 *d = (uint4 *)dst;
-    const uint4 *r = (const uint4 *)src;
-#define MECH_STREAM_CASE(O, U) \
-    if (op == O && unroll == U) { k_stream<O, U><<<grid, 256, 0, s>>>(d, r, n16, d); return hipGetLastError(); }
-    MECH_STREAM_CASE(0, 1) MECH_STREAM_CASE(0, 2) MECH_STREAM_CASE(0, 4) MECH_STREAM_CASE(0, 8)
-    MECH_STREAM_CASE(1, 1) MECH_STREAM_CASE(1, 2) MECH_STREAM_CASE(1, 4) MECH_STREAM_CASE(1, 8)
-    MECH_STREAM_CASE(2, 1) MECH_STREAM_CASE(2, 2) MECH_STREAM_CASE(2, 4) MECH_STREAM_CASE(2, 8)
-    MECH_STREAM_CASE(3, 1) MECH_STREAM_CASE(3, 2) MECH_STREAM_CASE(3, 4) MECH_STREAM_CASE(3, 8)
-#undef MECH_STREAM_CASE
-    return hipErrorInvalidValue;
+template <int OP, int U, bool NTL, bool NTS, class T>
+__global__ __launch_bounds__(256) void k_stream(T *__restrict__ dst, const T *__restrict__ src, size_t n,
+                                                 int chunked, T *__restrict__ sink) {
+    int nb = (int)gridDim.x, b = (int)blockIdx.x;
+    bool reads = OP != 2, writes = OP != 1;
+    if (OP == 4) {
+        reads = (b & 1) == 0;
+        writes = !reads;
+        nb >>= 1;
+        b >>= 1;
+    }
+    size_t i, stride, end = n;
+    if (chunked) {
+        const size_t per = (n + (size_t)nb - 1) / (size_t)nb;
+        const size_t lo = min(n, per * (size_t)b);
+        end = min(n, lo + per);
+        i = lo + threadIdx.x;
+        stride = blockDim.x;
+    } else {
+        i = (size_t)b * blockDim.x + threadIdx.x;
+        stride = (size_t)nb * blockDim.x;
+    }
+    T acc = (T)0u;
+    if (reads && !writes) {
+        for (; i + (U - 1) * stride < end; i += U * stride) {
+            T x[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) x[u] = ld<NTL>(src + i + u * stride);
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc ^= x[u];
+        }
+        for (; i < end; i += stride) acc ^= ld<NTL>(src + i);
+        if (fold(acc) == 0x9E3779B9u) sink[0] = acc;   // practically never; keeps the loads live
+    } else if (writes && !reads) {
+        for (; i + (U - 1) * stride < end; i += U * stride) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) st<NTS>(dst + i + u * stride, (T)(unsigned)(i + u));
+        }
+        for (; i < end; i += stride) st<NTS>(dst + i, (T)(unsigned)i);
+    } else {
+        for (; i + (U - 1) * stride < end; i += U * stride) {
+            T x[U], y[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) x[u] = ld<NTL>(src + i + u * stride);
+            if (OP == 3) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) y[u] = ld<NTL>(src + n + i + u * stride);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) st<NTS>(dst + i + u * stride, OP == 3 ? (T)(x[u] ^ y[u]) : x[u]);
+        }
+        for (; i < end; i += stride) {
+            const T x = ld<NTL>(src + i);
+            st<NTS>(dst + i, OP == 3 ? (T)(x ^ ld<NTL>(src + n + i)) : x);
+        }
+    }
+}
+
+template <int OP, int U, bool NTL, bool NTS>
+static hipError_t stream_go(int wide, void *d, const void *r, size_t bytes, int grid, int chunked, hipStream_t s) {
+    if (wide) {
+        k_stream<OP, U, NTL, NTS, u32x4><<<grid, 256, 0, s>>>((u32x4 *)d, (const u32x4 *)r, bytes / 16, chunked,
+                                                               (u32x4 *)d);
+    } else {
+        k_stream<OP, U, NTL, NTS, u32x2><<<grid, 256, 0, s>>>((u32x2 *)d, (const u32x2 *)r, bytes / 8, chunked,
+                                                               (u32x2 *)d);
+    }
+    return hipGetLastError();
+}
+template <int OP, int U>
+static hipError_t stream_nt(int flags, void *d, const void *r, size_t bytes, int grid, hipStream_t s) {
+    const int wide = !(flags & MECH_PROBE_8B), ch = (flags & MECH_PROBE_CHUNKED) ? 1 : 0;
+    switch (flags & (MECH_PROBE_NT_LOAD | MECH_PROBE_NT_STORE)) {
+    case 0: return stream_go<OP, U, false, false>(wide, d, r, bytes, grid, ch, s);
+    case MECH_PROBE_NT_LOAD: return stream_go<OP, U, true, false>(wide, d, r, bytes, grid, ch, s);
+    case MECH_PROBE_NT_STORE: return stream_go<OP, U, false, true>(wide, d, r, bytes, grid, ch, s);
+    default: return stream_go<OP, U, true, true>(wide, d, r, bytes, grid, ch, s);
+    }
+}
+template <int OP>
+static hipError_t stream_u(int unroll, int flags, void *d, const void *r, size_t bytes, int grid, hipStream_t s) {
+    switch (unroll) {
+    case 1: return stream_nt<OP, 1>(flags, d, r, bytes, grid, s);
+    case 2: return stream_nt<OP, 2>(flags, d, r, bytes, grid, s);
+    case 4: return stream_nt<OP, 4>(flags, d, r, bytes, grid, s);
+    case 8: return stream_nt<OP, 8>(flags, d, r, bytes, grid, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_stream(int op, int unroll, int flags, void *dst, const void *src, size_t bytes, int grid,
+                         hipStream_t s) {
+    if (bytes == 0) return hipSuccess;
+    switch (op) {
+    case 0: return stream_u<0>(unroll, flags, dst, src, bytes, grid, s);
+    case 1: return stream_u<1>(unroll, flags, dst, src, bytes, grid, s);
+    case 2: return stream_u<2>(unroll, flags, dst, src, bytes, grid, s);
+    case 3: return stream_u<3>(unroll, flags, dst, src, bytes, grid, s);
+    case 4: return stream_u<4>(unroll, flags, dst, src, bytes, grid, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 // ------------------------------------------------------------ launchers --

@@ -1433,17 +1433,19 @@ int mech_sync(mech_ctx *c) {
     return MECH_OK;
 }
 
-int mech_probe_stream(int op, int unroll, int blocks_per_cu, void *dst, const void *src, size_t bytes,
+int mech_probe_stream(int op, int unroll, int blocks_per_cu, int flags, void *dst, const void *src, size_t bytes,
                       void *hip_stream) {
-    if (op < 0 || op > 3 || (unroll != 1 && unroll != 2 && unroll != 4 && unroll != 8) || blocks_per_cu < 1 ||
-        blocks_per_cu > 64)
-        return fail(nullptr, MECH_ERR_INVAL, "probe: op 0..2, unroll 1/2/4/8, blocks_per_cu 1..64");
+    if (op < 0 || op > 4 || (unroll != 1 && unroll != 2 && unroll != 4 && unroll != 8) || blocks_per_cu < 1 ||
+        blocks_per_cu > 64 || flags < 0 || flags > 15)
+        return fail(nullptr, MECH_ERR_INVAL, "probe: op 0..4, unroll 1/2/4/8, blocks_per_cu 1..64, flags 0..15");
     if (!dst || (op != 2 && !src) || bytes % 16 || ((uintptr_t)dst | (uintptr_t)src) % 16)
         return fail(nullptr, MECH_ERR_INVAL, "probe needs 16-byte aligned buffers and size");
     int dev = 0, cu = 256;
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev);
-    hipError_t e = launch_stream(op, unroll, dst, src, bytes / 16, blocks_per_cu * cu, (hipStream_t)hip_stream);
+    int grid = blocks_per_cu * cu;
+    if (op == 4) grid += grid & 1;   // a reading and a writing half
+    hipError_t e = launch_stream(op, unroll, flags, dst, src, bytes, grid, (hipStream_t)hip_stream);
     if (e != hipSuccess) return fail(nullptr, MECH_ERR_HIP, "probe: %s", hipGetErrorString(e));
     return MECH_OK;
 }

@@ -90,7 +90,7 @@ def load_library(path: str = LIB_PATH):
         "mech_spike_counts": [vp, ip, C.c_int64],
         "mech_sync": [vp],
         "mech_info": [vp, lp, lp],
-        "mech_probe_stream": [C.c_int, C.c_int, C.c_int, vp, vp, C.c_size_t, vp],
+        "mech_probe_stream": [C.c_int, C.c_int, C.c_int, C.c_int, vp, vp, C.c_size_t, vp],
         "mech_last_error": [vp],
         "mech_strerror": [C.c_int],
         "mech_free": [vp],
@@ -286,25 +286,30 @@ STATE_NAMES = {"pas": (), "hh": ("m", "h", "n"), "ih": ("m",), "cahva": ("m", "h
 CA_KINDS = ("cahva", "capump", "cabuf")
 
 
-PROBE_OPS = {"copy": 0, "read": 1, "write": 2, "triad": 3}
+PROBE_OPS = {"copy": 0, "read": 1, "write": 2, "triad": 3, "split": 4}
+PROBE_FLAGS = {"nt_load": 1, "nt_store": 2, "8b": 4, "chunked": 8}
 
 
 def probe_stream(op: str = "copy", nbytes: int = 1 << 32, unroll: int = 4, blocks_per_cu: int = 8,
-                 reps: int = 5) -> float:
+                 reps: int = 5, flags=()) -> float:
     """Achieved GB/s of the library's streaming probe over `nbytes` of HBM
-    traffic (copy: nbytes/2 read + nbytes/2 written; triad: 2 nbytes/3 read +
-    nbytes/3 written); median of `reps`.
+    traffic (copy and split: nbytes/2 read + nbytes/2 written; triad:
+    2 nbytes/3 read + nbytes/3 written; read, write: nbytes); median of
+    `reps` launches timed with events on the current stream.  `flags` names
+    MECH_PROBE_* options (nt_load, nt_store, 8b, chunked).
     Checks every return code and, for the copy, the copied bytes."""
-    import time
     import torch
     L = load_library()
-    part = {"copy": 2, "triad": 3}.get(op, 1)
+    part = {"copy": 2, "split": 2, "triad": 3}.get(op, 1)
+    fl = 0
+    for f in flags:
+        fl |= PROBE_FLAGS[f]
     half = (nbytes // part) // 16 * 16
     src = torch.empty(2 * half if op == "triad" else half, dtype=torch.uint8, device="cuda")
     dst = torch.zeros(half if op != "read" else 256, dtype=torch.uint8, device="cuda")
     src.fill_(7)
     s = torch.cuda.current_stream()
-    args = (PROBE_OPS[op], unroll, blocks_per_cu, dst.data_ptr(), src.data_ptr(), half, s.cuda_stream)
+    args = (PROBE_OPS[op], unroll, blocks_per_cu, fl, dst.data_ptr(), src.data_ptr(), half, s.cuda_stream)
 
     def launch():
         rc = L.mech_probe_stream(*args)
@@ -317,13 +322,15 @@ def probe_stream(op: str = "copy", nbytes: int = 1 << 32, unroll: int = 4, block
         raise RuntimeError("copy probe did not copy")
     ts = []
     for _ in range(reps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
         launch()
-        torch.cuda.synchronize()
-        ts.append(time.perf_counter() - t0)
+        e1.record(s)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
     ts.sort()
     moved = part * half
+    del src, dst
     return moved / ts[len(ts) // 2] / 1e9
 
 
