@@ -192,8 +192,52 @@ def node_sample(w, nodes: int, seed: int):
     return sub, keep, ids
 
 
-def cpu_baseline(w, target_s: float, nodes: int):
-    """The oracle (single thread) on a node sample of the same workload."""
+def host_cpu():
+    """The host's CPU model name (as lscpu reports it) and logical CPU count."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def usable_cores(cap: int) -> int:
+    """Cores this process may run on, at most `cap` (the CPU share of one
+    GPU on a shared host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(cap, n))
+
+
+def node_shards(w, nodes: int, parts: int, seed: int):
+    """`parts` disjoint node samples of about `nodes` nodes each, as
+    workloads: one sample of parts * nodes nodes cut into contiguous node
+    ranges (whole cells in cable mode)."""
+    import numpy as np
+    from paper_1905_02241_amd import workloads as W
+    sub, _, _ = node_sample(w, nodes * parts, seed)
+    if w.vmode == "cable":
+        sizes = np.asarray(sub.cell_sizes)
+        cuts = np.array_split(np.arange(sizes.shape[0]), parts)
+        return [W.cells_subset(sub, list(c))[0] for c in cuts if c.size]
+    return [W.subset(sub, c)[0] for c in np.array_split(np.arange(sub.n_nodes), parts) if c.size]
+
+
+def cpu_baseline(w, target_s: float, nodes: int, max_threads: int = 16):
+    """The oracle timed on the host: single-threaded on a node sample of the
+    same workload (the parity reference as it stands), then one thread per
+    usable core, each running the same single-threaded oracle on its own
+    disjoint node range of a larger sample (nodes are independent under a
+    clamp and in isolated mode, and cells in cable mode; the oracle keeps no
+    global state and its calls release the interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
     from oracle import oracle as O
     sub, _, _ = node_sample(w, nodes, 7)
     M = O.Model(sub)
@@ -204,10 +248,37 @@ def cpu_baseline(w, target_s: float, nodes: int):
     steps = int(max(20, min(5000, target_s / max(per, 1e-9))))
     t = time.perf_counter()
     M.run(20, steps)
-    dt = time.perf_counter() - t
-    return {"value": sub.n_instances * steps / dt, "unit": "instance-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{sub.n_nodes} nodes ({sub.n_instances} instances) of the same workload, {steps} steps, "
-                      f"single-threaded FP64 C, {dt:.1f} s"}
+    dt1 = time.perf_counter() - t
+    single = sub.n_instances * steps / dt1
+    del M
+
+    threads = usable_cores(max_threads)
+    shards = node_shards(w, nodes, threads, 8)
+    models = []
+    for s in shards:
+        m = O.Model(s)
+        m.init()
+        models.append(m)
+
+    def run(m):
+        t0 = time.perf_counter()
+        m.run(0, steps)
+        return time.perf_counter() - t0
+
+    with ThreadPoolExecutor(len(models)) as ex:
+        t = time.perf_counter()
+        per_thread = list(ex.map(run, models))
+        wall = time.perf_counter() - t
+    inst = sum(s.n_instances for s in shards)
+    model, ncpu = host_cpu()
+    return {"value": inst * steps / wall, "unit": "instance-updates/s", "cores": len(models), "kind": "oracle",
+            "sample": f"{len(models)} threads, each the single-threaded FP64 C oracle on its own node range of "
+                      f"{inst} instances over {sum(s.n_nodes for s in shards)} nodes of the same workload, "
+                      f"{steps} steps, {wall:.1f} s wall (slowest thread {max(per_thread):.1f} s)",
+            "single_thread": {"value": single, "cores": 1,
+                              "sample": f"{sub.n_nodes} nodes ({sub.n_instances} instances), {steps} steps, "
+                                        f"{dt1:.1f} s"},
+            "host": {"cpu_model": model, "logical_cpus": ncpu, "usable_cores": usable_cores(10 ** 6)}}
 
 
 def precision_report(w, steps: int, sample: int, torch, mech):
@@ -254,6 +325,29 @@ def precision_report(w, steps: int, sample: int, torch, mech):
     return out
 
 
+# The precision contract: FP64 STATEs within 1e-12 relative of the oracle;
+# FP32-mixed gates and synapse states within 1e-5 absolute, calcium (cai,
+# cab, about 5e-5 mM) within 1e-4 relative.
+PRECISION_TOL = {"fp64": {"state_rel": 1e-12, "cai_rel": 1e-12},
+                 "fp32": {"state_abs": 1e-5, "cai_rel": 1e-4}}
+
+
+def within_tolerance(rep, prec: str) -> bool:
+    """Whether every STATE of a precision report meets its tolerance."""
+    tol = PRECISION_TOL[prec]
+    for key, e in rep.items():
+        if key in ("v", "spikes"):
+            continue
+        name = key.split(".", 1)[1]
+        if name in ("cai", "cab") or prec == "fp64":
+            lim = tol["cai_rel"] if name in ("cai", "cab") else tol["state_rel"]
+            if not e["max_rel"] <= lim:
+                return False
+        elif not e["max_abs"] <= tol["state_abs"]:
+            return False
+    return True
+
+
 def variant_accuracy(w, settings, steps: int, sample: int):
     """How far a section 5.2 variant (closed-form conductance, Pade cnexp)
     moves the results: the oracle with the variant's globals against the
@@ -297,21 +391,25 @@ PROBE_FLAG_SETS = ((), ("nt_load",), ("nt_store",), ("nt_load", "nt_store"), ("8
 
 
 def probe_battery(mech, nbytes: int = 1 << 32):
-    """Every streaming probe at its best unroll (2, 4, 8) and blocks per CU
-    (2, 4, 8, 16): GB/s per op and flag set."""
+    """Every streaming probe at its best unroll (2, 4, 8; also 1 for the
+    seven-array probe) and blocks per CU (1, 2, 4, 8, 16): GB/s per op and
+    flag set, with the whole grid."""
     out = {}
-    for op in ("copy", "triad", "split", "read", "write"):
-        for fl in PROBE_FLAG_SETS:
+    rmw_sets = tuple(fl + extra for fl in ((), ("chunked",), ("nt_load", "nt_store"), ("chunked", "nt_load", "nt_store"))
+                     for extra in ((), ("aosoa",)))
+    for op in ("rmw7", "copy", "triad", "split", "read", "write"):
+        for fl in (rmw_sets if op == "rmw7" else PROBE_FLAG_SETS):
             if op == "read" and "nt_store" in fl or op == "write" and "nt_load" in fl:
                 continue
-            best = None
-            for u in (2, 4, 8):
-                for b in (2, 4, 8, 16):
+            best, grid = None, {}
+            for u in ((1, 2, 4, 8) if op == "rmw7" else (2, 4, 8)):
+                for b in (1, 2, 4, 8, 16):
                     g = mech.probe_stream(op, nbytes, unroll=u, blocks_per_cu=b, reps=5, flags=fl)
+                    grid[f"u{u}b{b}"] = round(g)
                     if best is None or g > best[0]:
                         best = (g, u, b)
             key = f"{op}[{'+'.join(fl) or 'plain'}]"
-            out[key] = {"GBps": round(best[0], 1), "unroll": best[1], "blocks_per_cu": best[2]}
+            out[key] = {"GBps": round(best[0], 1), "unroll": best[1], "blocks_per_cu": best[2], "grid": grid}
             log(f"probe {key}: {best[0]:.0f} GB/s (unroll {best[1]}, {best[2]} blocks per CU)")
     return out
 
@@ -333,7 +431,11 @@ def main():
                          "waves, read, write) with and without non-temporal hints, 8-byte accesses and chunked "
                          "mapping, each at its best unroll and blocks per CU")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--precision-steps", type=int, default=1000,
+                    help="steps of the per-state error check against the oracle in the bench record (0: skip)")
+    ap.add_argument("--precision-nodes", type=int, default=3000,
+                    help="node sample of the per-state error check in the bench record")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--cpu-nodes", type=int, default=20000)
     ap.add_argument("--precision-report", type=int, default=0, metavar="NODES",
                     help="instead of timing: per-state error of FP64 and FP32-mixed vs the oracle on a node sample")
@@ -421,8 +523,10 @@ def main():
 
     probe = None
     if not args.no_probe:
-        probe = max(mech.probe_stream("copy", 1 << 32, unroll=u, blocks_per_cu=b) for u in (2, 4, 8) for b in (4, 16))
-        log(f"copy probe: {probe:.0f} GB/s (read + write, 4 GiB, best of unroll 2/4/8 x 4/16 blocks per CU)")
+        probe = max(mech.probe_stream("copy", 1 << 32, unroll=u, blocks_per_cu=b, flags=fl)
+                    for u in (2, 4, 8) for b in (1, 2, 4) for fl in ((), ("nt_load", "nt_store")))
+        log(f"copy probe: {probe:.0f} GB/s (read + write, 4 GiB, best of unroll 2/4/8 x 1/2/4 blocks per CU, "
+            "with and without non-temporal hints)")
 
     head_key = "fp64-batched" if "fp64-batched" in res else next(iter(res))
     head = res[head_key]
@@ -460,10 +564,21 @@ def main():
         if f"{pr}-resident" in res and f"{pr}-batched" in res:
             out[f"{pr}_resident_over_{pr}_batched"] = (res[f"{pr}-resident"]["updates_per_s"] /
                                                        res[f"{pr}-batched"]["updates_per_s"])
+    if args.precision_steps > 0 and {"fp64-batched", "fp32-batched"} & set(res):
+        log(f"precision check: {args.precision_steps} steps, {args.precision_nodes}-node sample ...")
+        rep = precision_report(w, args.precision_steps, args.precision_nodes, torch, mech)
+        for pr in ("fp64", "fp32"):
+            rep[pr]["within_tolerance"] = within_tolerance(rep[pr], pr)
+        rep["tolerances"] = PRECISION_TOL
+        out["precision"] = rep
+        log(f"precision check: fp64 within tolerance {rep['fp64']['within_tolerance']}, "
+            f"fp32 within tolerance {rep['fp32']['within_tolerance']}")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, args.cpu_nodes)
-        log(f"cpu baseline {out['cpu_baseline']['value']:.4g} updates/s")
+        cb = out["cpu_baseline"]
+        log(f"cpu baseline {cb['value']:.4g} updates/s on {cb['cores']} threads, "
+            f"{cb['single_thread']['value']:.4g} on one ({cb['host']['cpu_model']})")
     print(json.dumps(out), flush=True)
 
 

@@ -34,3 +34,10 @@ def pytest_collection_modifyitems(config, items):
     for it in items:
         if "gpu" in it.keywords:
             it.add_marker(skip)
+
+
+def pytest_sessionfinish(session, exitstatus):
+    path = os.environ.get("PARITY_RECORD")
+    if path:
+        from tests.parity import dump_record
+        dump_record(path)

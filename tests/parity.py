@@ -20,6 +20,8 @@ difference's numerator scaled by dv.
 """
 from __future__ import annotations
 
+import json
+import os
 import sys
 import time
 
@@ -30,6 +32,22 @@ from oracle import oracle as O
 STATE_TOL = {"fp64": (1e-12, 0.0), "fp32": (0.0, 1e-5)}   # (rel, abs)
 CAI_REL = {"fp64": 1e-12, "fp32": 1e-4}
 NODE_TOL = {"fp64": 1e-11, "fp32": 2e-3}
+
+
+EPS = 2.0 ** -52
+_RECORD = []
+
+
+def record(label: str, key: str, prec: str, ratio: float, err: float, **extra):
+    """Keeps one comparison's worst ratio and error; written out at the end of
+    the session when PARITY_RECORD names a file (the calibration of the bars)."""
+    test = os.environ.get("PYTEST_CURRENT_TEST", "").split(" ")[0]
+    _RECORD.append({"test": test, "label": label, "key": key, "prec": prec, "ratio": ratio, "err": err, **extra})
+
+
+def dump_record(path: str):
+    with open(path, "w") as f:
+        json.dump(_RECORD, f)
 
 
 def log(msg: str):
@@ -56,6 +74,50 @@ def run_oracle(w, nsteps, k0=0):
     M.init()
     M.run(k0, nsteps)
     return M
+
+
+def oracle_threads() -> int:
+    """Threads for the sharded oracle: the usable cores, at most 16."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def run_oracle_sharded(w, nsteps, parts=None, k0=0):
+    """The oracle on a workload whose nodes are independent (clamp or
+    isolated mode): its nodes cut into contiguous ranges, each range run by
+    the single-threaded oracle in its own thread (the oracle keeps no global
+    state; its calls release the interpreter lock).  Returns a Model of the
+    whole workload holding the merged results, bit-identical to one
+    single-threaded run (every node's arithmetic is the same)."""
+    from concurrent.futures import ThreadPoolExecutor
+    from paper_1905_02241_amd import workloads as W
+    if w.vmode not in ("clamp", "isolated"):
+        raise ValueError("sharding needs independent nodes (clamp or isolated mode)")
+    parts = min(parts or oracle_threads(), max(1, w.n_nodes))
+    cuts = [c for c in np.array_split(np.arange(w.n_nodes), parts) if c.size]
+    shards = [W.subset(w, c) for c in cuts]
+
+    def go(sh):
+        M = O.Model(sh[0])
+        M.init()
+        M.run(k0, nsteps)
+        return M
+
+    with ThreadPoolExecutor(len(shards)) as ex:
+        runs = list(ex.map(go, shards))
+    full = O.Model(w)
+    full.init()
+    for (sub, keep), Ms, c in zip(shards, runs, cuts):
+        for key in ("v", "rhs", "d", "spikes", "cai_node", "ica_node"):
+            getattr(full, key)[c] = getattr(Ms, key)
+        for s in range(len(w.slots)):
+            for name, arr in Ms.states[s].items():
+                full.states[s][name][keep[s]] = arr
+            full.ica[s][keep[s]] = Ms.ica[s]
+    return full
 
 
 def node_scale(M) -> np.ndarray:
@@ -91,6 +153,9 @@ def compare_states(got, M, prec, keep=None, label=""):
             err = np.abs(g - ref)
             r = float(np.max(err / tol)) if err.size else 0.0
             worst[f"{s}:{sl.kind}.{name}"] = (r, float(err.max()) if err.size else 0.0)
+            rel_err = float(np.max(err / np.maximum(np.abs(ref), 1e-300))) if err.size else 0.0
+            record(label, f"{sl.kind}.{name}", prec, r, worst[f"{s}:{sl.kind}.{name}"][1], rel=rel_err,
+                   vmode=M.w.vmode)
     bad = {k: v for k, v in worst.items() if not v[0] <= 1.0}
     assert not bad, f"{label} state parity: {bad}"
     return worst
@@ -105,6 +170,9 @@ def compare_nodes(got, M, prec, nodes=None, label="", check_v=True):
         tol = NODE_TOL[prec] * S + 1e-300
         r = float(np.max(np.abs(g - ref) / tol)) if ref.size else 0.0
         out[key] = r
+        units = float(np.max(np.abs(g - ref) / (EPS * S + 1e-300))) if ref.size else 0.0
+        record(label, key, prec, r, float(np.max(np.abs(g - ref))) if ref.size else 0.0, eps_S=units,
+               vmode=M.w.vmode)
         assert r <= 1.0, f"{label} {key} parity ratio {r}"
     if check_v:
         g = got["v"] if nodes is None else got["v"][nodes]
@@ -117,6 +185,7 @@ def compare_nodes(got, M, prec, nodes=None, label="", check_v=True):
             tol = (1e-12 if prec == "fp64" else 1e-4) * (np.abs(M.v) + 1.0)
         r = float(np.max(np.abs(g - M.v) / tol)) if M.v.size else 0.0
         out["v"] = r
+        record(label, "v", prec, r, float(np.max(np.abs(g - M.v))) if M.v.size else 0.0, vmode=M.w.vmode)
         assert r <= 1.0, f"{label} v parity ratio {r}"
     return out
 
