@@ -521,12 +521,19 @@ def main():
         res[v] = time_variant(w, prec, path, args.steps, args.warmup, args.autotune, torch, mech, launch,
                               args.save_tuning, resident, args.plain_scatter == "atomic")
 
-    probe = None
+    probe = hh_probe = hh_probe_tiles = None
     if not args.no_probe:
         probe = max(mech.probe_stream("copy", 1 << 32, unroll=u, blocks_per_cu=b, flags=fl)
                     for u in (2, 4, 8) for b in (1, 2, 4) for fl in ((), ("nt_load", "nt_store")))
         log(f"copy probe: {probe:.0f} GB/s (read + write, 4 GiB, best of unroll 2/4/8 x 1/2/4 blocks per CU, "
             "with and without non-temporal hints)")
+        # the stream of one hh slot (seven FP64 arrays, three rewritten), grid-stride and with one
+        # contiguous range per workgroup as the fused kernel's tiles have
+        hh_probe, hh_probe_tiles = (
+            max(mech.probe_stream("rmw7", 1 << 32, unroll=u, blocks_per_cu=b, flags=fl + extra)
+                for u in (1, 4) for b in (1, 4) for fl in ((), ("nt_load", "nt_store")))
+            for extra in ((), ("chunked",)))
+        log(f"hh-shaped probe: {hh_probe:.0f} GB/s grid-stride, {hh_probe_tiles:.0f} GB/s one range per workgroup")
 
     head_key = "fp64-batched" if "fp64-batched" in res else next(iter(res))
     head = res[head_key]
@@ -553,7 +560,9 @@ def main():
                      "kernel": f"k_fused (state+cur, {w.vmode})",
                      "alg_bytes_per_launch": head["alg_bytes_per_step"],
                      "copy_probe_GBps": probe,
-                     "frac_of_copy_probe": (achieved / probe) if probe else None},
+                     "frac_of_copy_probe": (achieved / probe) if probe else None,
+                     "hh_stream_probe_GBps": hh_probe,
+                     "hh_stream_probe_one_range_per_workgroup_GBps": hh_probe_tiles},
         "variants": res,
     }
     if "fp32-batched" in res and "fp64-plain" in res:

@@ -125,12 +125,17 @@ enum { MECH_V_EXTERNAL = 0, MECH_V_CLAMP = 1, MECH_V_ISOLATED = 2, MECH_V_CABLE 
  *        eagerly (the paper's per-mechanism kernel structure);
  * BATCHED: per step one fused launch over a table of node tiles that runs
  *        state(k-1), events(k) and cur(k) of every type and provides the
- *        next voltage, with chunks of steps replayed from a HIP graph;
+ *        next voltage, with chunks of steps replayed from a HIP graph.  Each
+ *        node's rhs, d (and calcium current) is summed in fixed point with
+ *        resolution 2^-67 (each contribution rounded to a multiple of 2^-67,
+ *        exactly when its magnitude is >= 2^-15) and rounded to double
+ *        once, so the result does not depend on the order in which
+ *        contributions arrive: runs and launch shapes give the same bits;
  * RESIDENT: time-fused.  The BATCHED path's tiles, but each workgroup keeps
  *        its tile (node data and every instance array) in LDS for up to
  *        mech_set_resident_steps() steps and writes STATEs back once, so
  *        STATEs do not cross HBM every step.  Same per-step arithmetic and
- *        results as BATCHED up to the rounding order of rhs/d.  CLAMP and
+ *        node sums as BATCHED (FP64: the same bits).  CLAMP and
  *        ISOLATED modes only (MECH_ERR_INVAL otherwise); every tile must fit
  *        the device's LDS per workgroup (160 KiB on gfx950; MECH_ERR_STATE
  *        otherwise: lower tile_instances / tile_nodes with
@@ -159,7 +164,9 @@ int mech_required_bytes(int64_t n_nodes, const mech_type_desc *types, int n_type
  * `dev_bytes` bytes (MECH_ERR_NOMEM if short), uploads the index arrays and
  * the tile table, and sets every parameter to its default and every global
  * to its default.  `hip_stream` is a hipStream_t (NULL: the null stream).
- * At most 8 types; each count < 2^31.                                     */
+ * At most 8 types; each count < 2^31; at most 2^19 instances (all types
+ * together) on one node (MECH_ERR_INVAL), the bound of the fused paths'
+ * fixed-point node sums.                                                  */
 int mech_alloc(mech_ctx **out, int64_t n_nodes, const mech_type_desc *types, int n_types, int prec,
                void *dev_buf, size_t dev_bytes, void *hip_stream);
 
@@ -277,8 +284,9 @@ int mech_step(mech_ctx *ctx, int64_t nsteps, int64_t k0, double dt, int vmode, i
  * hint, as they are touched once per step; MECH_LAUNCH_PLAIN_ATOMIC: the
  * PLAIN path's current update scatters one FP64 atomic per instance instead
  * of the wave-segmented per-node sum, for comparison).  Rebuilds
- * the tile table.  Results do not depend on the shape except for the
- * rounding order of rhs/d.                                                 */
+ * the tile table.  BATCHED and RESIDENT results do not depend on the shape
+ * (their node sums are order-independent); PLAIN's rhs/d differ from one
+ * run to the next by the rounding order of its atomics.                    */
 enum { MECH_LAUNCH_XCD_ORDER = 1, MECH_LAUNCH_NONTEMPORAL = 2, MECH_LAUNCH_PLAIN_ATOMIC = 4 };
 int mech_set_launch(mech_ctx *ctx, int block, int tile_instances, int tile_nodes, int blocks_per_cu,
                     int flags);
@@ -330,15 +338,22 @@ int mech_info(const mech_ctx *ctx, int64_t *n_tiles, int64_t *max_tile_nodes);
  *   op 3 reads src[0, bytes) and src[bytes, 2 bytes) and writes their xor
  *        to dst (two reads per write, the STREAM-triad mix);
  *   op 4 reads src[0, bytes) in the even workgroups and writes dst[0, bytes)
- *        in the odd ones (read and write streams from different waves).
+ *        in the odd ones (read and write streams from different waves);
+ *   op 5 treats dst[0, bytes) as seven FP64 arrays of n = bytes / 56
+ *        elements (n a multiple of 256; src unused), reads all seven and
+ *        rewrites the first three, the access shape of a Hodgkin-Huxley
+ *        slot's STATEs and PARAMETERs (HBM traffic 10/7 bytes).
  * `flags` (bitwise or of MECH_PROBE_*): non-temporal hint on the loads or
- * on the stores, 8-byte instead of 16-byte accesses, and one contiguous
- * chunk per workgroup instead of the grid-stride mapping.  The streaming HBM
- * ceilings the mechanism kernels are compared with.  Asynchronous.         */
+ * on the stores, 8-byte instead of 16-byte accesses, one contiguous chunk
+ * per workgroup instead of the grid-stride mapping, and (op 5) the seven
+ * arrays interleaved in blocks of 256 elements instead of laid end to end.
+ * The streaming HBM ceilings the mechanism kernels are compared with.
+ * Asynchronous.                                                            */
 #define MECH_PROBE_NT_LOAD 1
 #define MECH_PROBE_NT_STORE 2
 #define MECH_PROBE_8B 4
 #define MECH_PROBE_CHUNKED 8
+#define MECH_PROBE_AOSOA 16
 int mech_probe_stream(int op, int unroll, int blocks_per_cu, int flags, void *dst, const void *src, size_t bytes,
                       void *hip_stream);
 

@@ -346,6 +346,46 @@ void orc_instance_current(const orc_globals *gl, const orc_nodes *nd, const orc_
     }
 }
 
+/* Sum of the magnitudes of the terms that make up instance_i, at v.        */
+static double instance_terms(const orc_globals *gl, const orc_nodes *nd, const orc_slot *s, int64_t i, double v) {
+    switch (s->kind) {
+    case ORC_HH: {
+        double m = s->st[0][i], h = s->st[1][i], n = s->st[2][i];
+        double gna = s->par[0][i] * m * m * m * h;
+        double gk = s->par[1][i] * n * n * n * n;
+        return fabs(gna * (v - gl->ena)) + fabs(gk * (v - gl->ek)) + fabs(s->par[2][i] * (v - s->par[3][i]));
+    }
+    case ORC_SYN: {
+        double ga = s->st[1][i] - s->st[0][i];
+        double gn = s->st[3][i] - s->st[2][i];
+        return 1e-3 * (fabs(ga) + fabs(gn * orc_mg_block(v, gl->mg))) * fabs(v - gl->e_syn);
+    }
+    default:
+        return fabs(instance_i(gl, nd, s, i, v));
+    }
+}
+
+void orc_node_scales(const orc_globals *gl, const orc_nodes *nd, const orc_slot *slots, int nslots,
+                     double *terms, double *gsum, int32_t *count) {
+    for (int64_t n = 0; n < nd->n_nodes; ++n) {
+        terms[n] = 0.0;
+        gsum[n] = 0.0;
+        count[n] = 0;
+    }
+    for (int s = 0; s < nslots; ++s) {
+        const orc_slot *sl = &slots[s];
+        for (int64_t i = 0; i < sl->n; ++i) {
+            int32_t ni = sl->node[i];
+            double v = nd->v[ni], I0, g;
+            double sc = sl->kind == ORC_SYN ? 1e2 / nd->area[ni] : 1.0;
+            orc_instance_current(gl, nd, sl, i, v, &I0, &g);
+            terms[ni] += sc * instance_terms(gl, nd, sl, i, v);
+            gsum[ni] += fabs(sc * g);
+            count[ni] += 1;
+        }
+    }
+}
+
 /* --------------------------------------------------------------- phases -- */
 void orc_init(const orc_globals *gl, orc_nodes *nd, orc_slot *slots, int nslots) {
     for (int s = 0; s < nslots; ++s) {

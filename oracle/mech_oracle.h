@@ -155,6 +155,16 @@ uint64_t orc_event_threshold(double rate_hz, double dt);
 void orc_instance_current(const orc_globals *gl, const orc_nodes *nd, const orc_slot *s, int64_t i,
                           double v, double *cur, double *cond);
 
+/* Per-node scales of the rounding error of the current update, for the
+ * parity tolerances (not part of the method): at each instance's node v,
+ * terms[n] += |s| T_i where T_i is the sum of the magnitudes of the terms
+ * added into the instance's current (hh: its three ionic currents; the
+ * synapse: its two receptor currents; the other kinds: |I|), gsum[n] +=
+ * |s g_i| and count[n] += 1, with s = 100/area for the synapse and 1
+ * otherwise.  The outputs are overwritten.                                  */
+void orc_node_scales(const orc_globals *gl, const orc_nodes *nd, const orc_slot *slots, int nslots,
+                     double *terms, double *gsum, int32_t *count);
+
 /* ---- phases and the full step loop ------------------------------------ */
 void orc_init(const orc_globals *gl, orc_nodes *nd, orc_slot *slots, int nslots);
 void orc_events(const orc_globals *gl, orc_slot *slots, int nslots, int64_t k, double dt);

@@ -104,6 +104,8 @@ def lib():
         L.orc_cabuf_bound.restype = C.c_double
         L.orc_instance_current.argtypes = [C.POINTER(_Globals), C.POINTER(_Nodes), C.POINTER(_Slot), C.c_int64,
                                            C.c_double, _dp, _dp]
+        L.orc_node_scales.argtypes = [C.POINTER(_Globals), C.POINTER(_Nodes), C.POINTER(_Slot), C.c_int, _dp, _dp,
+                                      _ip]
         sig = [C.POINTER(_Globals), C.POINTER(_Nodes), C.POINTER(_Slot), C.c_int]
         L.orc_init.argtypes = sig
         L.orc_cur.argtypes = sig
@@ -320,6 +322,16 @@ class Model:
 
     def cabuf_bound(self, cai: float) -> float:
         return lib().orc_cabuf_bound(C.byref(self._g), cai)
+
+    def node_scales(self):
+        """Rounding scales of the current update at the model's v and STATEs
+        (orc_node_scales): per node the summed term magnitudes |s| T_i, the
+        summed |s g_i| and the number of instances.  For tolerances only."""
+        n = self.n_nodes
+        terms, gsum, cnt = np.zeros(n), np.zeros(n), np.zeros(n, dtype=np.int32)
+        lib().orc_node_scales(C.byref(self._g), C.byref(self._nodes), self._slots, self.nslots, _ptr(terms),
+                              _ptr(gsum), _ptr(cnt, _ip))
+        return terms, gsum, cnt
 
     def instance_current(self, s: int, i: int, v: float):
         cur, cond = C.c_double(), C.c_double()

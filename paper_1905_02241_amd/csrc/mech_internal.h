@@ -16,7 +16,8 @@ constexpr int kPad = 64;             // instances per padding unit (one wave)
 constexpr int kAlign = 256;          // byte alignment of every carved array
 constexpr int kMinTileBudget = 64;   // smallest tile work budget (instances)
 constexpr int kMinTileNodes = 64;
-constexpr int kMaxTileNodes = 2048;  // LDS: 32 B per node -> 64 KiB per block (96 KiB with the shared calcium ion)
+constexpr int kMaxPerNode = 1 << 19; // instances on one node: the fused paths' fixed-point node sums stay exact
+constexpr int kMaxTileNodes = 2048;  // LDS: 48 B per node -> 96 KiB per block (144 KiB with the shared calcium ion)
 
 // Step-phase flags of the fused kernel.
 enum : int { kDoState = 1, kDoCur = 2 };
@@ -173,13 +174,13 @@ __host__ __device__ inline size_t res_slot_bytes(int kind, int n, int ss) {
     return b;
 }
 
-// LDS doubles per tile node: v, rhs and d accumulators, 100/area (point
-// processes), 1e-3 cm/dt (isolated) or the four clamp waveform parameters, and the
-// shared calcium ion's cai and ica accumulator; then an int spike counter
-// per node and a 16-byte aligned table: 16 bytes per slot and 32 bytes of
-// run ends.
+// LDS 8-byte words per tile node: v, the rhs and d accumulators (two words
+// each), 100/area (point processes), 1e-3 cm/dt (isolated) or the four clamp
+// waveform parameters, and the shared calcium ion's cai and ica accumulator
+// (two words); then an int spike counter per node and a 16-byte aligned
+// table: 16 bytes per slot and 32 bytes of run ends.
 __host__ __device__ inline int res_node_doubles(int vmode, bool has_syn, bool ion) {
-    return 3 + (has_syn ? 1 : 0) + (vmode == MECH_V_CLAMP ? 4 : 1) + (ion ? 2 : 0);
+    return 5 + (has_syn ? 1 : 0) + (vmode == MECH_V_CLAMP ? 4 : 1) + (ion ? 3 : 0);
 }
 __host__ __device__ inline size_t res_node_bytes(int nn, int vmode, bool has_syn, bool ion) {
     return 8 * (size_t)nn * res_node_doubles(vmode, has_syn, ion) + res_round8(4 * (size_t)nn) + 8 + 16 * (kMaxSlots + 2);

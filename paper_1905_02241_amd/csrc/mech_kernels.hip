@@ -1060,13 +1060,86 @@ hipError_t cable_allow_lds(size_t bytes) {
 }
 
 // ---------------------------------------------------------- fused path --
-// LDS per tile node: v, 100/area, rhs and d accumulators (4 doubles); under
-// the shared calcium ion also the node's cai and its calcium current
-// accumulator (6 doubles).
+// Order-independent node sums.  The waves of a tile add their instances'
+// contributions to a node in whatever order they run, and FP64 addition is
+// not associative, so floating-point accumulators would make rhs, d and
+// every later v, STATE and spike count depend on scheduling and on the
+// launch shape.  Each node sum is therefore kept in fixed point, as two
+// 64-bit integer words added with integer LDS atomics, which are
+// associative.  A contribution x (|x| < 2^20) is split into
+// h = round(x 2^23) and l = round((x 2^23 - h) 2^44), |l| <= 2^43, so that
+// x = (h 2^44 + l) 2^-67 within half a unit 2^-67 (exactly when
+// |x| >= 2^-15, whose last mantissa bit is then at or above 2^-67).  Both roundings use the FP64 adder: adding
+// M = 1.5 * 2^52 to y (|y| < 2^51) leaves round(y) in the low bits of the
+// sum, and y - ((y + M) - M) is the exact remainder.  With at most 2^19
+// contributions per node neither word's sum can overflow, so no carry is
+// needed while adding; the flush combines the words into the 128-bit total
+// and rounds it to FP64 once.  Larger or non-finite contributions raise the
+// kernel's error flag and count as 0.  The host rejects workloads with more
+// instances on one node (kMaxPerNode).
+struct Acc {
+    unsigned long long *lo, *hi;
+};
+__device__ __forceinline__ void fx_zero(Acc a, int j) {
+    a.lo[j] = 0ull;
+    a.hi[j] = 0ull;
+}
+__device__ __forceinline__ long long fx_round(double y, double &rem) {
+    constexpr double M = 0x1.8p52;
+    const double t = y + M;
+    rem = y - (t - M);
+    return (long long)(__double_as_longlong(t) - __double_as_longlong(M));
+}
+__device__ __forceinline__ void fx_add(Acc a, int j, double x, int &flag) {
+    const bool ok = fabs(x) < 0x1p20;
+    flag |= ok ? 0 : 1;
+    double r;
+    const long long h = fx_round(ok ? x * 0x1p23 : 0.0, r);
+    double r2;
+    const long long l = fx_round(r * 0x1p44, r2);
+    atomicAdd(a.hi + j, (unsigned long long)h);
+    atomicAdd(a.lo + j, (unsigned long long)l);
+}
+// The total H 2^44 + L (the two words' signed sums) as a 128-bit two's
+// complement pair, then its magnitude's two words converted separately and
+// added (nothing cancels; within one rounding of the exact total), and the
+// sign applied.
+__device__ __forceinline__ double fx_get(Acc a, int j) {
+    const long long H = (long long)a.hi[j], L = (long long)a.lo[j];
+    const unsigned long long sh = (unsigned long long)H << 44;
+    unsigned long long lo = sh + (unsigned long long)L;
+    unsigned long long hi = (unsigned long long)((H >> 20) + (L >> 63)) + (lo < sh ? 1ull : 0ull);
+    const bool neg = (long long)hi < 0;
+    if (neg) {   // two's complement negation of the pair
+        lo = ~lo + 1ull;
+        hi = ~hi + (lo == 0ull ? 1ull : 0ull);
+    }
+    const double m = (double)hi * 0x1p-3 + (double)lo * 0x1p-67;
+    return neg ? -m : m;
+}
+
+// LDS per tile node: v and 100/area (two doubles), the rhs and d
+// accumulators (four 64-bit words); under the shared calcium ion also the
+// node's cai and its calcium current accumulator (three more words).
+// One instance's contributions into its node's sums (the synapse's in
+// nA and uS, scaled by 100/area into mA/cm2 and S/cm2).
+template <int KIND, int PH>
+__device__ __forceinline__ void tile_add(int j, double ci, double cg, const double *sc, Acc ar, Acc ad,
+                                         int &flag) {
+    if (PH & kDoCur) {
+        if (KIND == MECH_SYN) {
+            ci *= sc[j];
+            cg *= sc[j];
+        }
+        fx_add(ar, j, -ci, flag);
+        fx_add(ad, j, cg, flag);
+    }
+}
+
 // Instance i of a slot within a tile whose nodes start at nlo.
 template <class S, int KIND, int PH, bool NT, bool EXT>
 __device__ __forceinline__ void tile_one(const SlotDev &sl, int i, int nlo, const double *vl, const double *sc,
-                                         double *ar, double *ad, const double *cl, double *ai, const GlobDev &g,
+                                         Acc ar, Acc ad, const double *cl, Acc ai, const GlobDev &g,
                                          long long k, bool ion, int &flag) {
     // an identity slot (instance i on node i) needs no index load
     const int j = (sl.identity ? i : ld<NT>(sl.ni + i)) - nlo;
@@ -1074,23 +1147,16 @@ __device__ __forceinline__ void tile_one(const SlotDev &sl, int i, int nlo, cons
     if (EXT && is_ca_kind(KIND) && ion) {
         double ica;
         ca_shared<S, PH, NT>(sl, i, vl[j], cl[j], g, ci, cg, ica, flag);
-        if (PH & kDoCur) atomicAdd(&ai[j], ica);
+        if (PH & kDoCur) fx_add(ai, j, ica, flag);
     } else {
         instance<S, KIND, PH, NT, true>(sl, i, vl[j], g, k, ci, cg, flag);
     }
-    if (PH & kDoCur) {
-        if (KIND == MECH_SYN) {
-            ci *= sc[j];
-            cg *= sc[j];
-        }
-        atomicAdd(&ar[j], -ci);
-        atomicAdd(&ad[j], cg);
-    }
+    tile_add<KIND, PH>(j, ci, cg, sc, ar, ad, flag);
 }
 
 template <class S, int KIND, int PH, bool NT, bool EXT>
 __device__ __forceinline__ void tile_slot(const SlotDev &sl, int lo, int hi, int nlo, const double *vl,
-                                          const double *sc, double *ar, double *ad, const double *cl, double *ai,
+                                          const double *sc, Acc ar, Acc ad, const double *cl, Acc ai,
                                           const GlobDev &g, long long k, bool ion, int &flag) {
     for (int i = lo + (int)threadIdx.x; i < hi; i += (int)blockDim.x)
         tile_one<S, KIND, PH, NT, EXT>(sl, i, nlo, vl, sc, ar, ad, cl, ai, g, k, ion, flag);
@@ -1113,8 +1179,11 @@ __device__ __forceinline__ int tile_of(int b, int T, int xcd_order) {
 template <class S, int PH, int VM, bool NT, bool EXT = false>
 __global__ __launch_bounds__(1024) void k_fused(FusedArgs a, int tn) {
     extern __shared__ double lds[];
-    double *vl = lds, *sc = lds + tn, *ar = lds + 2 * tn, *ad = lds + 3 * tn;
-    double *cl = lds + 4 * tn, *ai = lds + 5 * tn;
+    unsigned long long *w = (unsigned long long *)lds;
+    double *vl = lds, *sc = lds + tn;
+    const Acc ar{w + 2 * tn, w + 3 * tn}, ad{w + 4 * tn, w + 5 * tn};
+    double *cl = lds + 6 * tn;
+    const Acc ai{w + 7 * tn, w + 8 * tn};
     const bool ion = EXT && a.g.shared_ca;
     const long long k = *a.kdev + a.kofs;
     int flag = 0;
@@ -1126,12 +1195,12 @@ __global__ __launch_bounds__(1024) void k_fused(FusedArgs a, int tn) {
         for (int j = threadIdx.x; j < nn; j += blockDim.x) {
             vl[j] = a.nd.v[nlo + j];
             if (PH & kDoCur) {
-                ar[j] = 0.0;
-                ad[j] = 0.0;
+                fx_zero(ar, j);
+                fx_zero(ad, j);
                 if (a.has_syn) sc[j] = 1e2 / a.nd.area[nlo + j];
                 if (ion) {
                     cl[j] = a.nd.cai[nlo + j];
-                    ai[j] = 0.0;
+                    fx_zero(ai, j);
                 }
             }
         }
@@ -1159,7 +1228,7 @@ __global__ __launch_bounds__(1024) void k_fused(FusedArgs a, int tn) {
             __syncthreads();
             for (int j = threadIdx.x; j < nn; j += blockDim.x) {
                 const int n = nlo + j;
-                const double r = ar[j], dd = ad[j];
+                const double r = fx_get(ar, j), dd = fx_get(ad, j);
                 a.nd.rhs[n] = r;
                 a.nd.d[n] = dd;
                 if (VM == MECH_V_ISOLATED) a.nd.v[n] = isolated_v(a.nd, a.g, n, vl[j], r, dd);
@@ -1168,10 +1237,11 @@ __global__ __launch_bounds__(1024) void k_fused(FusedArgs a, int tn) {
                     // the node's pool advances with this step's calcium current,
                     // as a cahva instance's own pool does in this pass
                     double c = cl[j];
-                    ion_pool(a.g, ai[j], c);
+                    const double ica = fx_get(ai, j);
+                    ion_pool(a.g, ica, c);
                     flag |= bad(c);
                     a.nd.cai[n] = c;
-                    a.nd.ica[n] = ai[j];
+                    a.nd.ica[n] = ica;
                 }
             }
         }
@@ -1268,8 +1338,8 @@ __device__ __forceinline__ void res_copy(const SlotDev &g, const SlotDev &l, int
 // registers 1.52 / 0.81.
 template <class S, int PH, bool EXT>
 __device__ __forceinline__ void res_pass(const FusedArgs &a, const int *r0, const int *r1, const int4 *tab, char *inst,
-                                         const double *vl, const double *sc, double *ar, double *ad, const double *cl,
-                                         double *ai, long long k, bool ion, int &flag) {
+                                         const double *vl, const double *sc, Acc ar, Acc ad, const double *cl,
+                                         Acc ai, long long k, bool ion, int &flag) {
     const int4 *ends = tab + kMaxSlots;
     const int total = __builtin_amdgcn_readfirstlane(ends[1].w);
     const int lane = (int)(threadIdx.x & 63);
@@ -1321,13 +1391,16 @@ __global__ __launch_bounds__(1024) void k_resident(FusedArgs a, ResArgs r) {
         const int *r1 = r0 + a.row;
         const int nlo = r0[0], nn = r1[0] - nlo;
         // node region and slot table (res_node_bytes), then the slots' instance arrays
-        double *vl = lds, *ar = lds + nn, *ad = lds + 2 * nn, *q = lds + 3 * nn;
+        unsigned long long *w = (unsigned long long *)lds;
+        double *vl = lds, *q = lds + 5 * nn;
+        const Acc ar{w + nn, w + 2 * nn}, ad{w + 3 * nn, w + 4 * nn};
         double *sc = q;
         if (syn) q += nn;
         double *md = q;   // 1e-3 cm/dt (isolated) or the clamp waveform, 4 per node
         q += (VM == MECH_V_CLAMP ? 4 : 1) * nn;
-        double *cl = q, *ai = q + nn;
-        if (ion) q += 2 * nn;
+        double *cl = q;
+        const Acc ai{(unsigned long long *)q + nn, (unsigned long long *)q + 2 * nn};
+        if (ion) q += 3 * nn;
         int *spk = (int *)q;
         const size_t toff = (((char *)q - (char *)lds) + res_round8(4 * (size_t)nn) + 15) & ~(size_t)15;
         int4 *tab = (int4 *)((char *)lds + toff);
@@ -1351,8 +1424,8 @@ __global__ __launch_bounds__(1024) void k_resident(FusedArgs a, ResArgs r) {
         for (int j = threadIdx.x; j < nn; j += blockDim.x) {
             const int n = nlo + j;
             vl[j] = a.nd.v[n];
-            ar[j] = 0.0;
-            ad[j] = 0.0;
+            fx_zero(ar, j);
+            fx_zero(ad, j);
             if (syn) sc[j] = 1e2 / a.nd.area[n];
             if (VM == MECH_V_CLAMP) {
                 md[4 * j] = a.nd.c_off[n];
@@ -1364,7 +1437,7 @@ __global__ __launch_bounds__(1024) void k_resident(FusedArgs a, ResArgs r) {
             }
             if (ion) {
                 cl[j] = a.nd.cai[n];
-                ai[j] = 0.0;
+                fx_zero(ai, j);
             }
             spk[j] = 0;
         }
@@ -1389,7 +1462,7 @@ __global__ __launch_bounds__(1024) void k_resident(FusedArgs a, ResArgs r) {
             const bool last = sub + 1 == r.nsub;
             for (int j = threadIdx.x; j < nn; j += blockDim.x) {
                 const int n = nlo + j;
-                const double rr = ar[j], dd = ad[j], v0 = vl[j];
+                const double rr = fx_get(ar, j), dd = fx_get(ad, j), v0 = vl[j];
                 double v1;
                 if (VM == MECH_V_ISOLATED) {
                     v1 = v0 + rr / (md[j] + dd);
@@ -1400,11 +1473,12 @@ __global__ __launch_bounds__(1024) void k_resident(FusedArgs a, ResArgs r) {
                                                          md[4 * j + 3]);
                 }
                 vl[j] = v1;
-                ar[j] = 0.0;
-                ad[j] = 0.0;
+                fx_zero(ar, j);
+                fx_zero(ad, j);
+                const double ica = ion ? fx_get(ai, j) : 0.0;
                 if (ion) {
                     double c = cl[j];
-                    ion_pool(a.g, ai[j], c);
+                    ion_pool(a.g, ica, c);
                     flag |= bad(c);
                     cl[j] = c;
                 }
@@ -1414,10 +1488,10 @@ __global__ __launch_bounds__(1024) void k_resident(FusedArgs a, ResArgs r) {
                     a.nd.v[n] = v1;
                     if (ion) {
                         a.nd.cai[n] = cl[j];
-                        a.nd.ica[n] = ai[j];
+                        a.nd.ica[n] = ica;
                     }
                 }
-                if (ion) ai[j] = 0.0;
+                if (ion) fx_zero(ai, j);
             }
             __syncthreads();
         }
@@ -1521,6 +1595,54 @@ __global__ __launch_bounds__(256) void k_stream(T *__restrict__ dst, const T *__
     }
 }
 
+// op 5: seven FP64 arrays of n elements, the shape of one Hodgkin-Huxley
+// slot of the fused step: three read and rewritten (the STATEs), four read
+// only (the PARAMETERs).  AOS interleaves the arrays in blocks of 256
+// elements (element i of array a at ((i / 256) 7 + a) 256 + i % 256), so a
+// wave's seven accesses fall in one 14 KiB region instead of seven pages
+// n elements apart; n is a multiple of 256 then.
+template <int U, bool NTL, bool NTS, bool AOS>
+__global__ __launch_bounds__(256) void k_rmw7(double *__restrict__ base, size_t n, int chunked) {
+    const int nb = (int)gridDim.x, b = (int)blockIdx.x;
+    size_t i, stride, end = n;
+    if (chunked) {
+        const size_t per = (n + (size_t)nb - 1) / (size_t)nb;
+        const size_t lo = min(n, per * (size_t)b);
+        end = min(n, lo + per);
+        i = lo + threadIdx.x;
+        stride = blockDim.x;
+    } else {
+        i = (size_t)b * blockDim.x + threadIdx.x;
+        stride = (size_t)nb * blockDim.x;
+    }
+    auto at = [n](int a, size_t j) -> size_t {
+        return AOS ? ((j >> 8) * 7 + (size_t)a) * 256 + (j & 255) : (size_t)a * n + j;
+    };
+    auto one = [&](size_t j) {
+        double x[7];
+#pragma unroll
+        for (int a = 0; a < 7; ++a) x[a] = ld<NTL>(base + at(a, j));
+        st<NTS>(base + at(0, j), x[0] * x[3] + x[4]);
+        st<NTS>(base + at(1, j), x[1] * x[5] + x[6]);
+        st<NTS>(base + at(2, j), x[2] * x[3] + x[6]);
+    };
+    for (; i + (U - 1) * stride < end; i += U * stride) {
+        double x[U][7];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int a = 0; a < 7; ++a) x[u][a] = ld<NTL>(base + at(a, i + u * stride));
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const size_t j = i + u * stride;
+            st<NTS>(base + at(0, j), x[u][0] * x[u][3] + x[u][4]);
+            st<NTS>(base + at(1, j), x[u][1] * x[u][5] + x[u][6]);
+            st<NTS>(base + at(2, j), x[u][2] * x[u][3] + x[u][6]);
+        }
+    }
+    for (; i < end; i += stride) one(i);
+}
+
 template <int OP, int U, bool NTL, bool NTS>
 static hipError_t stream_go(int wide, void *d, const void *r, size_t bytes, int grid, int chunked, hipStream_t s) {
     if (wide) {
@@ -1532,14 +1654,31 @@ static hipError_t stream_go(int wide, void *d, const void *r, size_t bytes, int 
     }
     return hipGetLastError();
 }
+template <int U, bool NTL, bool NTS>
+static hipError_t rmw7_go(int aos, void *d, size_t bytes, int grid, int chunked, hipStream_t s) {
+    const size_t n = bytes / 56;
+    if (aos) k_rmw7<U, NTL, NTS, true><<<grid, 256, 0, s>>>((double *)d, n, chunked);
+    else k_rmw7<U, NTL, NTS, false><<<grid, 256, 0, s>>>((double *)d, n, chunked);
+    return hipGetLastError();
+}
 template <int OP, int U>
 static hipError_t stream_nt(int flags, void *d, const void *r, size_t bytes, int grid, hipStream_t s) {
     const int wide = !(flags & MECH_PROBE_8B), ch = (flags & MECH_PROBE_CHUNKED) ? 1 : 0;
-    switch (flags & (MECH_PROBE_NT_LOAD | MECH_PROBE_NT_STORE)) {
-    case 0: return stream_go<OP, U, false, false>(wide, d, r, bytes, grid, ch, s);
-    case MECH_PROBE_NT_LOAD: return stream_go<OP, U, true, false>(wide, d, r, bytes, grid, ch, s);
-    case MECH_PROBE_NT_STORE: return stream_go<OP, U, false, true>(wide, d, r, bytes, grid, ch, s);
-    default: return stream_go<OP, U, true, true>(wide, d, r, bytes, grid, ch, s);
+    if constexpr (OP == 5) {
+        const int aos = (flags & MECH_PROBE_AOSOA) ? 1 : 0;
+        switch (flags & (MECH_PROBE_NT_LOAD | MECH_PROBE_NT_STORE)) {
+        case 0: return rmw7_go<U, false, false>(aos, d, bytes, grid, ch, s);
+        case MECH_PROBE_NT_LOAD: return rmw7_go<U, true, false>(aos, d, bytes, grid, ch, s);
+        case MECH_PROBE_NT_STORE: return rmw7_go<U, false, true>(aos, d, bytes, grid, ch, s);
+        default: return rmw7_go<U, true, true>(aos, d, bytes, grid, ch, s);
+        }
+    } else {
+        switch (flags & (MECH_PROBE_NT_LOAD | MECH_PROBE_NT_STORE)) {
+        case 0: return stream_go<OP, U, false, false>(wide, d, r, bytes, grid, ch, s);
+        case MECH_PROBE_NT_LOAD: return stream_go<OP, U, true, false>(wide, d, r, bytes, grid, ch, s);
+        case MECH_PROBE_NT_STORE: return stream_go<OP, U, false, true>(wide, d, r, bytes, grid, ch, s);
+        default: return stream_go<OP, U, true, true>(wide, d, r, bytes, grid, ch, s);
+        }
     }
 }
 template <int OP>
@@ -1562,6 +1701,7 @@ hipError_t launch_stream(int op, int unroll, int flags, void *dst, const void *s
     case 2: return stream_u<2>(unroll, flags, dst, src, bytes, grid, s);
     case 3: return stream_u<3>(unroll, flags, dst, src, bytes, grid, s);
     case 4: return stream_u<4>(unroll, flags, dst, src, bytes, grid, s);
+    case 5: return stream_u<5>(unroll, flags, dst, src, bytes, grid, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1676,22 +1816,23 @@ static hipError_t fused_t(int phases, int vmode, const FusedArgs &a, int grid, i
     default: return fused_vm<S, kDoCur | kDoState, NT, EXT>(vmode, a, grid, block, lds, tn, s);
     }
 }
-size_t fused_lds_bytes(int tile_nodes, bool ion) { return (ion ? 6 : 4) * sizeof(double) * (size_t)tile_nodes; }
+size_t fused_lds_bytes(int tile_nodes, bool ion) { return (ion ? 9 : 6) * 8 * (size_t)tile_nodes; }
 
-// Lets every extended fused instantiation (those that run the shared
-// calcium ion) take up to `bytes` of dynamic LDS.
+// Lets every fused instantiation take up to `bytes` of dynamic LDS.
 hipError_t fused_allow_lds(size_t bytes) {
     const int b = (int)bytes;
     const void *fns[] = {
-#define MECH_FUSED_FNS(S)                                                                                       \
-    (const void *)k_fused<S, kDoState, MECH_V_EXTERNAL, false, true>,                                             \
-        (const void *)k_fused<S, kDoCur, MECH_V_EXTERNAL, false, true>,                                           \
-        (const void *)k_fused<S, kDoCur, MECH_V_CLAMP, false, true>,                                              \
-        (const void *)k_fused<S, kDoCur, MECH_V_ISOLATED, false, true>,                                           \
-        (const void *)k_fused<S, kDoCur | kDoState, MECH_V_EXTERNAL, false, true>,                                \
-        (const void *)k_fused<S, kDoCur | kDoState, MECH_V_CLAMP, false, true>,                                   \
-        (const void *)k_fused<S, kDoCur | kDoState, MECH_V_ISOLATED, false, true>
-        MECH_FUSED_FNS(double), MECH_FUSED_FNS(float)
+#define MECH_FUSED_FNS(S, NT, EXT)                                                                              \
+    (const void *)k_fused<S, kDoState, MECH_V_EXTERNAL, NT, EXT>,                                                 \
+        (const void *)k_fused<S, kDoCur, MECH_V_EXTERNAL, NT, EXT>,                                               \
+        (const void *)k_fused<S, kDoCur, MECH_V_CLAMP, NT, EXT>,                                                  \
+        (const void *)k_fused<S, kDoCur, MECH_V_ISOLATED, NT, EXT>,                                               \
+        (const void *)k_fused<S, kDoCur | kDoState, MECH_V_EXTERNAL, NT, EXT>,                                    \
+        (const void *)k_fused<S, kDoCur | kDoState, MECH_V_CLAMP, NT, EXT>,                                       \
+        (const void *)k_fused<S, kDoCur | kDoState, MECH_V_ISOLATED, NT, EXT>
+        MECH_FUSED_FNS(double, false, false), MECH_FUSED_FNS(float, false, false),
+        MECH_FUSED_FNS(double, true, false), MECH_FUSED_FNS(float, true, false),
+        MECH_FUSED_FNS(double, false, true), MECH_FUSED_FNS(float, false, true)
 #undef MECH_FUSED_FNS
     };
     for (const void *f : fns) {

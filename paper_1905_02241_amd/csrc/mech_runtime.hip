@@ -349,7 +349,6 @@ struct mech_ctx {
     NodesDev nd{};
     CableDev cable{};
     bool nodes_bound = false, clamp_bound = false, has_syn = false, cable_bound = false;
-    bool ion_lds = false;          // fused kernels allowed the LDS of the shared calcium ion
     // fused-path launch shape and tile table
     int block = 256, tile_budget = 2048, tile_nodes = 1024, blocks_per_cu = 0, launch_flags = MECH_LAUNCH_XCD_ORDER;
     int64_t n_tiles = 0, max_tile_nodes = 0;
@@ -885,6 +884,19 @@ int mech_alloc(mech_ctx **out, int64_t n_nodes, const mech_type_desc *types, int
             }
         }
     }
+    {
+        // the fused paths sum a node's contributions in fixed point, exact up
+        // to kMaxPerNode of them
+        std::vector<int32_t> per(n_nodes, 0);
+        for (const SlotHost &h : c->slots)
+            for (int32_t n : h.ni)
+                if (++per[n] > kMaxPerNode) {
+                    int code = fail(nullptr, MECH_ERR_INVAL, "node %d carries more than %d instances", n,
+                                    kMaxPerNode);
+                    delete c;
+                    return code;
+                }
+    }
     compute_layout(n_nodes, c->slots, prec, c->L);
     if (dev_bytes < c->L.total) {
         int code = fail(nullptr, MECH_ERR_NOMEM, "device buffer has %zu bytes, %zu required", dev_bytes, c->L.total);
@@ -915,6 +927,13 @@ int mech_alloc(mech_ctx **out, int64_t n_nodes, const mech_type_desc *types, int
             rc = find_slot_var(c, s, K.param[j].name, false, &off, &isd);
             if (rc == MECH_OK) rc = upload_var(c, s, off, isd, &K.defaults[j], 1);
         }
+    }
+    if (rc == MECH_OK) {
+        // the fused kernels' node accumulators take 48 B of LDS per tile node
+        // (72 B under the shared calcium ion), beyond the default 64 KiB at
+        // the largest tiles
+        hipError_t e = fused_allow_lds(fused_lds_bytes(kMaxTileNodes, true));
+        if (e != hipSuccess) rc = fail(c, MECH_ERR_HIP, "fused kernels' LDS limit: %s", hipGetErrorString(e));
     }
     if (rc == MECH_OK) {
         hipError_t e = launch_set_k((long long *)(c->buf + c->L.off_kdev), 0, c->stream);
@@ -1121,11 +1140,6 @@ int mech_set_global(mech_ctx *c, const char *name, double value) {
         if (value != 0.0 && value != 1.0) return fail(c, MECH_ERR_INVAL, "shared_ca must be 0 or 1");
         if (value != 0.0 && !c->nd.cai)
             return fail(c, MECH_ERR_STATE, "shared_ca needs a cahva, capump or cabuf type");
-        if (value != 0.0 && !c->ion_lds) {
-            // the fused pass then keeps two more doubles per tile node in LDS
-            HIPCHK(c, fused_allow_lds(fused_lds_bytes(kMaxTileNodes, true)));
-            c->ion_lds = true;
-        }
         G.shared_ca = value != 0.0;
         clear_graphs(c);
         return MECH_OK;
@@ -1435,11 +1449,13 @@ int mech_sync(mech_ctx *c) {
 
 int mech_probe_stream(int op, int unroll, int blocks_per_cu, int flags, void *dst, const void *src, size_t bytes,
                       void *hip_stream) {
-    if (op < 0 || op > 4 || (unroll != 1 && unroll != 2 && unroll != 4 && unroll != 8) || blocks_per_cu < 1 ||
-        blocks_per_cu > 64 || flags < 0 || flags > 15)
-        return fail(nullptr, MECH_ERR_INVAL, "probe: op 0..4, unroll 1/2/4/8, blocks_per_cu 1..64, flags 0..15");
-    if (!dst || (op != 2 && !src) || bytes % 16 || ((uintptr_t)dst | (uintptr_t)src) % 16)
+    if (op < 0 || op > 5 || (unroll != 1 && unroll != 2 && unroll != 4 && unroll != 8) || blocks_per_cu < 1 ||
+        blocks_per_cu > 64 || flags < 0 || flags > 31)
+        return fail(nullptr, MECH_ERR_INVAL, "probe: op 0..5, unroll 1/2/4/8, blocks_per_cu 1..64, flags 0..31");
+    if (!dst || (op != 2 && op != 5 && !src) || bytes % 16 || ((uintptr_t)dst | (uintptr_t)src) % 16)
         return fail(nullptr, MECH_ERR_INVAL, "probe needs 16-byte aligned buffers and size");
+    if (op == 5 && (bytes % 56 || (bytes / 56) % 256))
+        return fail(nullptr, MECH_ERR_INVAL, "probe op 5: bytes must be 56 times a multiple of 256");
     int dev = 0, cu = 256;
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev);

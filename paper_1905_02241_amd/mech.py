@@ -286,17 +286,18 @@ STATE_NAMES = {"pas": (), "hh": ("m", "h", "n"), "ih": ("m",), "cahva": ("m", "h
 CA_KINDS = ("cahva", "capump", "cabuf")
 
 
-PROBE_OPS = {"copy": 0, "read": 1, "write": 2, "triad": 3, "split": 4}
-PROBE_FLAGS = {"nt_load": 1, "nt_store": 2, "8b": 4, "chunked": 8}
+PROBE_OPS = {"copy": 0, "read": 1, "write": 2, "triad": 3, "split": 4, "rmw7": 5}
+PROBE_FLAGS = {"nt_load": 1, "nt_store": 2, "8b": 4, "chunked": 8, "aosoa": 16}
 
 
 def probe_stream(op: str = "copy", nbytes: int = 1 << 32, unroll: int = 4, blocks_per_cu: int = 8,
                  reps: int = 5, flags=()) -> float:
     """Achieved GB/s of the library's streaming probe over `nbytes` of HBM
     traffic (copy and split: nbytes/2 read + nbytes/2 written; triad:
-    2 nbytes/3 read + nbytes/3 written; read, write: nbytes); median of
-    `reps` launches timed with events on the current stream.  `flags` names
-    MECH_PROBE_* options (nt_load, nt_store, 8b, chunked).
+    2 nbytes/3 read + nbytes/3 written; read, write: nbytes; rmw7: seven
+    arrays of 7 nbytes/10 read, three of them rewritten); median of `reps`
+    launches timed with events on the current stream.  `flags` names
+    MECH_PROBE_* options (nt_load, nt_store, 8b, chunked, aosoa).
     Checks every return code and, for the copy, the copied bytes."""
     import torch
     L = load_library()
@@ -304,10 +305,16 @@ def probe_stream(op: str = "copy", nbytes: int = 1 << 32, unroll: int = 4, block
     fl = 0
     for f in flags:
         fl |= PROBE_FLAGS[f]
-    half = (nbytes // part) // 16 * 16
-    src = torch.empty(2 * half if op == "triad" else half, dtype=torch.uint8, device="cuda")
-    dst = torch.zeros(half if op != "read" else 256, dtype=torch.uint8, device="cuda")
-    src.fill_(7)
+    if op == "rmw7":
+        half = (nbytes * 7 // 10) // (56 * 256) * (56 * 256)
+        src = torch.empty(16, dtype=torch.uint8, device="cuda")
+        dst = torch.zeros(half // 8, dtype=torch.float64, device="cuda")
+        dst.fill_(0.5)
+    else:
+        half = (nbytes // part) // 16 * 16
+        src = torch.empty(2 * half if op == "triad" else half, dtype=torch.uint8, device="cuda")
+        dst = torch.zeros(half if op != "read" else 256, dtype=torch.uint8, device="cuda")
+        src.fill_(7)
     s = torch.cuda.current_stream()
     args = (PROBE_OPS[op], unroll, blocks_per_cu, fl, dst.data_ptr(), src.data_ptr(), half, s.cuda_stream)
 
@@ -329,7 +336,7 @@ def probe_stream(op: str = "copy", nbytes: int = 1 << 32, unroll: int = 4, block
         e1.synchronize()
         ts.append(e0.elapsed_time(e1) * 1e-3)
     ts.sort()
-    moved = part * half
+    moved = half * 10 // 7 if op == "rmw7" else part * half
     del src, dst
     return moved / ts[len(ts) // 2] / 1e9
 

@@ -126,6 +126,13 @@ def test_validation_codes(lib):
     assert lib.mech_alloc(C.byref(ctx), 4, d, 1, 0, fake, 16, None) == mech.ERR_NOMEM
     assert lib.mech_alloc(C.byref(ctx), 4, d, 1, 0, fake + 8, 1 << 30, None) == mech.ERR_INVAL
     assert lib.mech_alloc(C.byref(ctx), 4, d, 1, 0, None, 1 << 30, None) == mech.ERR_INVAL
+    # at most 2^19 instances on one node, all types together (the bound of
+    # the fused paths' fixed-point node sums)
+    d, keep = _descs([("syn", np.zeros((1 << 19) - 1, dtype=np.int32)), ("pas", np.arange(4))])
+    assert lib.mech_alloc(C.byref(ctx), 4, d, 2, 0, fake, 16, None) == mech.ERR_NOMEM
+    d, keep = _descs([("syn", np.zeros(1 << 19, dtype=np.int32)), ("pas", np.arange(4))])
+    assert lib.mech_alloc(C.byref(ctx), 4, d, 2, 0, fake, 1 << 30, None) == mech.ERR_INVAL
+    assert b"more than" in lib.mech_last_error(None)
     assert not ctx.value
     # null-context calls
     assert lib.mech_init(None) == mech.ERR_INVAL
