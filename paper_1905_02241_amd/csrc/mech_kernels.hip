@@ -1074,9 +1074,10 @@ hipError_t cable_allow_lds(size_t bytes) {
 // sum, and y - ((y + M) - M) is the exact remainder.  With at most 2^19
 // contributions per node neither word's sum can overflow, so no carry is
 // needed while adding; the flush combines the words into the 128-bit total
-// and rounds it to FP64 once.  Larger or non-finite contributions raise the
-// kernel's error flag and count as 0.  The host rejects workloads with more
-// instances on one node (kMaxPerNode).
+// and rounds it to FP64 once.  A larger or non-finite contribution raises
+// the kernel's error flag (its words are then meaningless, and the step is
+// reported as failed at the next mech_sync).  The host rejects workloads
+// with more instances on one node (kMaxPerNode).
 struct Acc {
     unsigned long long *lo, *hi;
 };
@@ -1091,10 +1092,9 @@ __device__ __forceinline__ long long fx_round(double y, double &rem) {
     return (long long)(__double_as_longlong(t) - __double_as_longlong(M));
 }
 __device__ __forceinline__ void fx_add(Acc a, int j, double x, int &flag) {
-    const bool ok = fabs(x) < 0x1p20;
-    flag |= ok ? 0 : 1;
+    flag |= fabs(x) < 0x1p20 ? 0 : 1;
     double r;
-    const long long h = fx_round(ok ? x * 0x1p23 : 0.0, r);
+    const long long h = fx_round(x * 0x1p23, r);
     double r2;
     const long long l = fx_round(r * 0x1p44, r2);
     atomicAdd(a.hi + j, (unsigned long long)h);
