@@ -49,7 +49,9 @@ def test_tiny_isolated_fp64_spikes(path):
 
 @pytest.mark.parametrize("path", PATHS)
 def test_tiny_isolated_fp32_reports(path):
-    """FP32-mixed in free-voltage mode: reported, spike counts must mostly agree."""
+    """FP32-mixed in free-voltage mode: v differs from the FP64 oracle by the
+    FP32 rounding of the currents (reported); every node's spike count is
+    the oracle's."""
     w = W.make_tiny(2, kinds=("pas", "hh", "cahva", "syn"), n_nodes=40, syn_per_node=6.0,
                     vmode="isolated", event_rate_hz=300.0, nsteps=600)
     w.area[:] = np.linspace(100.0, 400.0, w.n_nodes)
@@ -58,7 +60,7 @@ def test_tiny_isolated_fp32_reports(path):
     M = run_oracle(w, 600)
     match = np.mean(got["spikes"] == M.spikes)
     log(f"isolated fp32 {path}: spike match {match:.3f}, max |dv| {np.max(np.abs(got['v'] - M.v)):.3g} mV")
-    assert match >= 0.9
+    assert match == 1.0
 
 
 def test_external_phase_calls():
@@ -449,22 +451,40 @@ def test_config5_plain_fp64_sampled_spikes():
 
 def test_config5_fp32_sampled_free_voltage():
     """FP32-mixed batched in free-voltage mode, 1,000 steps, 30,000-node
-    sample: the voltage feeds the FP32 state rounding back into the gates,
-    so this reports the per-state error and the spike agreement."""
+    sample.  The voltage feeds the FP32 rounding of the currents back into
+    every later gate, so the per-state bar of a clamp (1e-5 absolute, 1e-4
+    relative for calcium) cannot hold on every node over a long horizon.
+    Enforced: at least 99 % of the instances of every STATE within that bar;
+    on every instance, the gate error within the bar plus the steepest gate
+    slope (0.05 per mV) times its node's voltage error; spike counts equal
+    on at least 99.9 % of the nodes."""
     w = _c5()
     got, M, nodes = _sampled(5, 1000, "fp32", "batched", 30000, w=w, check_states=False)
     sub, keep = W.subset(w, nodes)
     match = got["spikes"][nodes] == M.spikes
-    errs = {}
+    dv_node = np.abs(got["v"][nodes] - M.v)
+    report, bad = {}, []
     for s, sl in enumerate(M.w.slots):
+        inst_dv = dv_node[np.asarray(M.w.slots[s].node)]
         for name, ref in M.states[s].items():
+            if not ref.size:
+                continue
             g = got["states"][s][name][keep[s]]
-            e = np.abs(g - ref) / (np.abs(ref) if name in ("cai", "cab") else 1.0)
-            errs[f"{sl.kind}.{name}"] = float(e.max()) if e.size else 0.0
-    dv = float(np.max(np.abs(got["v"][nodes] - M.v)))
+            calcium = name in ("cai", "cab")
+            e = np.abs(g - ref) / (np.abs(ref) if calcium else 1.0)
+            bar = 1e-4 if calcium else 1e-5
+            within = float(np.mean(e <= bar))
+            report[f"{sl.kind}.{name}"] = (float(e.max()), float(np.quantile(e, 0.999)), within)
+            if within < 0.99:
+                bad.append((sl.kind, name, within))
+            if not calcium and not np.all(e <= bar + 0.05 * inst_dv):
+                bad.append((sl.kind, name, "beyond bar + slope * dv"))
     log(f"c5 fp32 free voltage: spike match {match.mean():.5f} ({int(M.spikes.sum())} oracle spikes), "
-        f"max |dv| {dv:.3g} mV, state errors {errs}")
-    assert match.mean() >= 0.99
+        f"max |dv| {dv_node.max():.3g} mV, 99.9th percentile {np.quantile(dv_node, 0.999):.3g} mV; "
+        "per state (max, 99.9th percentile, fraction within bar): "
+        + ", ".join(f"{k} {v[0]:.2g}/{v[1]:.2g}/{v[2]:.4f}" for k, v in report.items()))
+    assert not bad, bad
+    assert match.mean() >= 0.999
 
 
 # ------------------------------------------------- time-fused path --
@@ -652,7 +672,7 @@ def test_config5_resident_fp32_reports():
             for s, sl in enumerate(M.w.slots) for name, ref in M.states[s].items() if ref.size}
     log(f"c5 resident fp32: spike match {match:.4f} ({int(M.spikes.sum())} oracle spikes), max |dv| {dv:.3g} mV, "
         f"state errors {errs}")
-    assert match >= 0.99
+    assert match == 1.0
 
 
 def test_config5_resident_fp64_sampled_spikes():
@@ -953,7 +973,7 @@ def test_cable_cells_fp32_reports(path):
     M = run_oracle(w, 400)
     match = np.mean(got["spikes"] == M.spikes)
     log(f"cable fp32 {path}: spike match {match:.3f}, max |dv| {np.max(np.abs(got['v'] - M.v)):.3g} mV")
-    assert match >= 0.9
+    assert match == 1.0
 
 
 @pytest.mark.parametrize("path", PATHS)
