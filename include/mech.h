@@ -170,6 +170,22 @@ int mech_required_bytes(int64_t n_nodes, const mech_type_desc *types, int n_type
 int mech_alloc(mech_ctx **out, int64_t n_nodes, const mech_type_desc *types, int n_types, int prec,
                void *dev_buf, size_t dev_bytes, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): mech_alloc with
+ * the device buffer taken from a static area of the library instead of the
+ * caller, 64 MiB on each device (held until the process ends).  Same
+ * arguments, checks and results as mech_alloc otherwise; the context then
+ * behaves as one made by mech_alloc (the caller still binds its node
+ * vectors).  Allocates no device memory.  One live context per device:
+ * MECH_ERR_STATE while another static context on the current device has not
+ * been freed (mech_free releases the area, whose contents then stay until
+ * the next mech_alloc_static overwrites them); MECH_ERR_NOMEM when
+ * mech_required_bytes exceeds the area.  Calls from several host threads
+ * are serialised; work of one static context on several streams races as
+ * for any context.                                                         */
+int mech_alloc_static(mech_ctx **out, int64_t n_nodes, const mech_type_desc *types, int n_types, int prec,
+                      void *hip_stream);
+
 /* Bind caller-owned device node vectors (double, n_nodes each).  v, rhs, d
  * are required; area is required if a MECH_SYN type exists; cm is required
  * for MECH_V_ISOLATED (may be NULL otherwise).                             */

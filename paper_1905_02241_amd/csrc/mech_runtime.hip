@@ -17,11 +17,17 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
 
 using namespace mech;
+
+// Device memory of the contexts made by mech_alloc_static (see the static
+// device area below): 64 MiB on every device the library runs on.
+constexpr size_t kStaticBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kStaticBytes];
 
 namespace {
 
@@ -363,6 +369,7 @@ struct mech_ctx {
     // graphs of kGraphSteps fused steps, keyed by (vmode, dt)
     std::map<std::pair<int, uint64_t>, hipGraphExec_t> graphs;
     std::string err;
+    int static_dev = -1;           // device whose static area holds this context (mech_alloc_static)
 };
 
 namespace {
@@ -782,6 +789,26 @@ int step_resident(mech_ctx *c, int64_t nsteps, int64_t k0, double dt, int vmode)
     return MECH_OK;
 }
 
+// ------------------------------------------------- static device area --
+// Device memory of the contexts made by mech_alloc_static, for callers that
+// cannot allocate.  One array per device: every device the library runs on
+// holds its copy until the process ends.  In host code `scratch` only names
+// the symbol; its address on a device comes from hipGetSymbolAddress, taken
+// once per device with that device current and kept in g_static.
+constexpr int kMaxDevices = 64;
+
+struct StaticArea {
+    char *ptr = nullptr;           // device address of `scratch` on this device
+    bool in_use = false;           // a live context occupies it
+};
+std::mutex g_static_mu;
+StaticArea g_static[kMaxDevices];
+
+void static_release(int dev) {
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (dev >= 0 && dev < kMaxDevices) g_static[dev].in_use = false;
+}
+
 }  // namespace
 
 // ================================================================ C ABI ==
@@ -956,6 +983,44 @@ int mech_alloc(mech_ctx **out, int64_t n_nodes, const mech_type_desc *types, int
         return rc;
     }
     *out = c;
+    return MECH_OK;
+}
+
+int mech_alloc_static(mech_ctx **out, int64_t n_nodes, const mech_type_desc *types, int n_types, int prec,
+                      void *hip_stream) {
+    if (!out) return fail(nullptr, MECH_ERR_INVAL, "null out");
+    *out = nullptr;
+    size_t need = 0;
+    int rc = mech_required_bytes(n_nodes, types, n_types, prec, &need);
+    if (rc) return rc;
+    if (need > kStaticBytes)
+        return fail(nullptr, MECH_ERR_NOMEM, "the context needs %zu bytes; the static area holds %zu (use mech_alloc)",
+                    need, kStaticBytes);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(nullptr, MECH_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(nullptr, MECH_ERR_INVAL, "device %d beyond %d", dev, kMaxDevices);
+    std::unique_lock<std::mutex> lock(g_static_mu);
+    StaticArea &a = g_static[dev];
+    if (!a.ptr) {
+        // once per device, with that device current
+        char *p = nullptr;
+        e = hipGetSymbolAddress((void **)&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(nullptr, MECH_ERR_HIP, "hipGetSymbolAddress: %s", hipGetErrorString(e));
+        a.ptr = p;
+    }
+    if (a.in_use)
+        return fail(nullptr, MECH_ERR_STATE, "the static area of device %d holds a live context (mech_free it first)",
+                    dev);
+    a.in_use = true;
+    lock.unlock();
+    rc = mech_alloc(out, n_nodes, types, n_types, prec, a.ptr, kStaticBytes, hip_stream);
+    if (rc) {
+        static_release(dev);
+        return rc;
+    }
+    (*out)->static_dev = dev;
     return MECH_OK;
 }
 
@@ -1471,6 +1536,7 @@ void mech_free(mech_ctx *c) {
     (void)hipStreamSynchronize(c->stream);
     clear_graphs(c);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+    if (c->static_dev >= 0) static_release(c->static_dev);
     delete c;
 }
 

@@ -28,7 +28,7 @@ GLOBAL_NAMES = ("celsius", "ena", "ek", "eh", "cao", "cai0", "tau_ca", "ca_gamma
                 "buf_total", "buf_kon", "buf_koff", "newton_iters", "shared_ca")
 
 # Exported symbols of include/mech.h (checked by the CPU tests).
-SYMBOLS = ("mech_required_bytes", "mech_alloc", "mech_bind_nodes", "mech_bind_clamp", "mech_cable_required_bytes",
+SYMBOLS = ("mech_required_bytes", "mech_alloc", "mech_alloc_static", "mech_bind_nodes", "mech_bind_clamp", "mech_cable_required_bytes",
            "mech_cable_plan",
            "mech_bind_cable", "mech_set_params",
            "mech_set_global", "mech_init", "mech_cur", "mech_state", "mech_step", "mech_set_launch",
@@ -69,6 +69,7 @@ def load_library(path: str = LIB_PATH):
     sig = {
         "mech_required_bytes": [C.c_int64, C.POINTER(TypeDesc), C.c_int, C.c_int, C.POINTER(C.c_size_t)],
         "mech_alloc": [C.POINTER(vp), C.c_int64, C.POINTER(TypeDesc), C.c_int, C.c_int, vp, C.c_size_t, vp],
+        "mech_alloc_static": [C.POINTER(vp), C.c_int64, C.POINTER(TypeDesc), C.c_int, C.c_int, vp],
         "mech_bind_nodes": [vp, vp, vp, vp, vp, vp],
         "mech_bind_clamp": [vp, vp, vp, vp, vp],
         "mech_cable_required_bytes": [C.c_int64, ip, C.c_int32, C.POINTER(C.c_size_t)],
@@ -121,7 +122,8 @@ class Mechanisms:
     float64 tensors on the device owned by this object (``v``, ``rhs``,
     ``d``, ``area``, ``cm``, ``clamp``)."""
 
-    def __init__(self, n_nodes: int, types, prec: str = "fp64", stream=None, device: str = "cuda"):
+    def __init__(self, n_nodes: int, types, prec: str = "fp64", stream=None, device: str = "cuda",
+                 static: bool = False):
         import torch
         self.torch = torch
         self.L = load_library()
@@ -141,8 +143,10 @@ class Mechanisms:
         self.nbytes = int(nbytes.value)
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        # torch's caching allocator returns 512-byte aligned blocks
-        self.buf = torch.empty(max(self.nbytes, 256), dtype=torch.uint8, device=self.device)
+        # torch's caching allocator returns 512-byte aligned blocks; a static
+        # context takes the library's own device area instead (mech_alloc_static)
+        self.static = bool(static)
+        self.buf = None if self.static else torch.empty(max(self.nbytes, 256), dtype=torch.uint8, device=self.device)
         f64 = dict(dtype=torch.float64, device=self.device)
         self.v = torch.full((self.n_nodes,), -65.0, **f64)
         self.rhs = torch.zeros(self.n_nodes, **f64)
@@ -151,8 +155,12 @@ class Mechanisms:
         self.cm = torch.ones(self.n_nodes, **f64)
         self.clamp = [torch.zeros(self.n_nodes, **f64) for _ in range(4)]
         ctx = C.c_void_p()
-        self._check(self.L.mech_alloc(C.byref(ctx), self.n_nodes, descs, len(types), PREC[prec],
-                                      self.buf.data_ptr(), self.nbytes, self.stream.cuda_stream), None)
+        if self.static:
+            self._check(self.L.mech_alloc_static(C.byref(ctx), self.n_nodes, descs, len(types), PREC[prec],
+                                                 self.stream.cuda_stream), None)
+        else:
+            self._check(self.L.mech_alloc(C.byref(ctx), self.n_nodes, descs, len(types), PREC[prec],
+                                          self.buf.data_ptr(), self.nbytes, self.stream.cuda_stream), None)
         self.ctx = ctx
         self._check(self.L.mech_bind_nodes(ctx, _ptr(self.v), _ptr(self.rhs), _ptr(self.d), _ptr(self.area),
                                            _ptr(self.cm)))
@@ -367,12 +375,14 @@ def cable_plan(parent, unit_nodes: int = 0) -> Dict[str, np.ndarray]:
     return out
 
 
-def from_workload(w, prec: str = "fp64", init: bool = True, unit_nodes: int = 0) -> Mechanisms:
+def from_workload(w, prec: str = "fp64", init: bool = True, unit_nodes: int = 0, static: bool = False) -> Mechanisms:
     """Build a context from a workload (paper_1905_02241_amd.workloads):
     node index, parameters, globals, node arrays (and cell trees, cut into
     units of at most unit_nodes, 0 for the device's capacity); v = v_init
-    everywhere and, if `init`, every STATE at its steady state there."""
-    m = Mechanisms(w.n_nodes, [(s.kind, s.node) for s in w.slots], prec=prec)
+    everywhere and, if `init`, every STATE at its steady state there.
+    static: the context lives in the library's static device area
+    (mech_alloc_static)."""
+    m = Mechanisms(w.n_nodes, [(s.kind, s.node) for s in w.slots], prec=prec, static=static)
     m.set_globals(w.globals)
     for i, s in enumerate(w.slots):
         for name, vals in s.params.items():

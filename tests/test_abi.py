@@ -133,6 +133,14 @@ def test_validation_codes(lib):
     d, keep = _descs([("syn", np.zeros(1 << 19, dtype=np.int32)), ("pas", np.arange(4))])
     assert lib.mech_alloc(C.byref(ctx), 4, d, 2, 0, fake, 1 << 30, None) == mech.ERR_INVAL
     assert b"more than" in lib.mech_last_error(None)
+    # the static area (mech_alloc_static) rejects contexts larger than it
+    # before any device call
+    d, keep = _descs([("hh", np.arange(1 << 22, dtype=np.int32))])
+    assert lib.mech_alloc_static(C.byref(ctx), 1 << 22, d, 1, 0, None) == mech.ERR_NOMEM
+    assert b"static area" in lib.mech_last_error(None)
+    d, keep = _descs([(9, np.arange(4))])
+    assert lib.mech_alloc_static(C.byref(ctx), 4, d, 1, 0, None) == mech.ERR_INVAL
+    assert lib.mech_alloc_static(None, 4, d, 1, 0, None) == mech.ERR_INVAL
     assert not ctx.value
     # null-context calls
     assert lib.mech_init(None) == mech.ERR_INVAL
