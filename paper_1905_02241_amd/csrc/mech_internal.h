@@ -194,6 +194,11 @@ struct PlainArgs {
     GlobDev g;
     NodesDev nd;
     int atomic_scatter;        // one FP64 atomic per instance instead of the wave-segmented sum
+    // per wave of the slot (ceil(n/64) entries): the node of a run that
+    // began in an earlier wave, or -1, and that run's sums in this wave
+    // (rhs, d, calcium current)
+    int *carry_node;
+    double *carry_val;
 };
 
 // Launchers (defined in mech_kernels.hip).  All return hipGetLastError().

@@ -580,36 +580,48 @@ __device__ __forceinline__ void ion_pool(const GlobDev &g, double ica, double &c
 // Segmented inclusive sum over a wave of instances sorted by node: after the
 // log2(64) shuffle steps each lane holds the sum of its node's run up to
 // itself, so the run's last lane carries the node's total.  Returns true on
-// that lane.  Lanes with key < 0 (past the end) form no run.
-__device__ __forceinline__ bool segmented_sum(int key, double &x, double &y) {
+// that lane.  Lanes with key < 0 (past the end) form no run.  Z: also sum z
+// (the calcium current under the shared ion).
+template <bool Z>
+__device__ __forceinline__ bool segmented_sum(int key, double &x, double &y, double &z) {
     const int lane = (int)(threadIdx.x & 63);
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
         const double xo = __shfl_up(x, d, 64);
         const double yo = __shfl_up(y, d, 64);
+        const double zo = Z ? __shfl_up(z, d, 64) : 0.0;
         const int ko = __shfl_up(key, d, 64);
         if (lane >= d && ko == key) {
             x += xo;
             y += yo;
+            if (Z) z += zo;
         }
     }
     const int kn = __shfl_down(key, 1, 64);
     return key >= 0 && (lane == 63 || kn != key);
 }
 
+// The current update of one type, a thread per instance.  Identity types
+// read-modify-write their node.  Node-sorted types sum each node's run within
+// the wave (fixed shuffle order) and add it with one FP64 atomic, so a node
+// receives one atomic per type; only a run that began in an earlier wave
+// would add a second one in an order set by scheduling.  The part of such a
+// run in this wave goes to the type's carry slot of this wave instead, and
+// k_plain_carry adds those parts in wave order after the kernel.  rhs and d
+// therefore do not change from run to run.  With atomic_scatter every
+// instance adds its own atomic (the comparison point; order not fixed).
 template <class S, int KIND>
 __global__ __launch_bounds__(256) void k_plain_cur(PlainArgs a) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool shared = is_ca_kind(KIND) && a.g.shared_ca;
     int flag = 0;
     int ni = -1;
-    double ci = 0.0, cg = 0.0;
+    double ci = 0.0, cg = 0.0, ica = 0.0;
     if (i < a.slot.n) {
         ni = a.slot.ni[i];
         const double v = a.nd.v[ni];
-        if (is_ca_kind(KIND) && a.g.shared_ca) {
-            double ica;
+        if (shared) {
             ca_shared<S, kDoCur>(a.slot, i, v, a.nd.cai[ni], a.g, ci, cg, ica, flag);
-            unsafeAtomicAdd(&a.nd.ica[ni], ica);
         } else {
             instance<S, KIND, kDoCur>(a.slot, i, v, a.g, a.k, ci, cg, flag);
         }
@@ -625,19 +637,63 @@ __global__ __launch_bounds__(256) void k_plain_cur(PlainArgs a) {
         if (ni >= 0) {
             a.nd.rhs[ni] -= ci;
             a.nd.d[ni] += cg;
+            if (shared) a.nd.ica[ni] += ica;
         }
     } else if (a.atomic_scatter) {
-        // one FP64 atomic per instance (the comparison point of the sum below)
         if (ni >= 0) {
             unsafeAtomicAdd(&a.nd.rhs[ni], -ci);
             unsafeAtomicAdd(&a.nd.d[ni], cg);
+            if (shared) unsafeAtomicAdd(&a.nd.ica[ni], ica);
         }
-    } else if (segmented_sum(ni, ci, cg)) {
-        // node-sorted instances: one FP64 atomic per node run in the wave
-        unsafeAtomicAdd(&a.nd.rhs[ni], -ci);
-        unsafeAtomicAdd(&a.nd.d[ni], cg);
+    } else {
+        const int lane = (int)(threadIdx.x & 63);
+        const int i0 = i - lane;   // the wave's first instance
+        if (i0 < a.slot.n) {
+            const int c = i0 >> 6;
+            // does the wave's first run continue a run of the previous wave?
+            int prev = -1;
+            if (lane == 0 && i0 > 0) prev = a.slot.ni[i0 - 1];
+            prev = __shfl(prev, 0, 64);
+            const int first = __shfl(ni, 0, 64);
+            const bool cont = prev == first;
+            double x = -ci, y = cg, z = ica;
+            const bool last = shared ? segmented_sum<true>(ni, x, y, z) : segmented_sum<false>(ni, x, y, z);
+            if (last) {
+                if (cont && ni == first) {
+                    a.carry_node[c] = ni;
+                    a.carry_val[3 * (size_t)c] = x;
+                    a.carry_val[3 * (size_t)c + 1] = y;
+                    a.carry_val[3 * (size_t)c + 2] = z;
+                } else {
+                    unsafeAtomicAdd(&a.nd.rhs[ni], x);
+                    unsafeAtomicAdd(&a.nd.d[ni], y);
+                    if (shared) unsafeAtomicAdd(&a.nd.ica[ni], z);
+                }
+            }
+            if (lane == 0 && !cont) a.carry_node[c] = -1;
+        }
     }
     if (flag) atomicOr(a.err, 1);
+}
+
+// The parts of node runs that crossed into later waves (k_plain_cur's carry
+// slots), added in wave order: the thread of the first slot of each chain
+// (consecutive slots of one node) sums the chain and adds it to its node,
+// which no other thread of this launch touches.
+__global__ __launch_bounds__(256) void k_plain_carry(PlainArgs a, int n_chunks, int shared) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_chunks) return;
+    const int n = a.carry_node[c];
+    if (n < 0 || (c > 0 && a.carry_node[c - 1] == n)) return;
+    double x = 0.0, y = 0.0, z = 0.0;
+    for (int q = c; q < n_chunks && a.carry_node[q] == n; ++q) {
+        x += a.carry_val[3 * (size_t)q];
+        y += a.carry_val[3 * (size_t)q + 1];
+        z += a.carry_val[3 * (size_t)q + 2];
+    }
+    a.nd.rhs[n] += x;
+    a.nd.d[n] += y;
+    if (shared) a.nd.ica[n] += z;
 }
 
 template <class S, int KIND>
@@ -1772,7 +1828,11 @@ static hipError_t cur_t(const PlainArgs &a, hipStream_t s) {
 }
 hipError_t launch_plain_cur(bool fp32, const PlainArgs &a, hipStream_t s) {
     if (a.slot.n == 0) return hipSuccess;
-    return fp32 ? cur_t<float>(a, s) : cur_t<double>(a, s);
+    const hipError_t e = fp32 ? cur_t<float>(a, s) : cur_t<double>(a, s);
+    if (e != hipSuccess || a.slot.identity || a.atomic_scatter) return e;
+    const int n_chunks = (a.slot.n + 63) / 64;
+    k_plain_carry<<<blocks(n_chunks, 256), 256, 0, s>>>(a, n_chunks, a.g.shared_ca ? 1 : 0);
+    return hipGetLastError();
 }
 
 template <class S>

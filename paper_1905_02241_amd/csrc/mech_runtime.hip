@@ -20,6 +20,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 using namespace mech;
@@ -82,6 +83,7 @@ struct SlotHost {
     std::vector<int32_t> perm;     // internal -> caller index (empty when identity)
     std::vector<int32_t> ni;       // node index, internal (sorted) order
     size_t off_ni = 0, off_gid = 0, off_ica = 0;
+    size_t off_carry = 0;          // plain path: per wave, a node (int) then three doubles
     size_t off_st[kMaxStates] = {}, off_par[kMaxParams] = {};
     bool has_gid = false, has_ica = false;
 };
@@ -329,6 +331,12 @@ void compute_layout(int64_t n_nodes, std::vector<SlotHost> &slots, int prec, Lay
     L.off_spikes = off; off = align_up(off + 4 * (size_t)std::max<int64_t>(n_nodes, 1));
     L.off_err = off; off = align_up(off + 4);
     L.off_kdev = off; off = align_up(off + 8);
+    for (auto &s : slots) {
+        const size_t nch = (size_t)s.np / kPad;
+        s.off_carry = off;
+        off = align_up(off + 4 * nch);
+        off = align_up(off + 24 * nch);
+    }
     L.has_ion = false;
     for (auto &s : slots) L.has_ion |= is_ca_kind(s.kind);
     if (L.has_ion) { L.off_ion = off; off = align_up(off + 16 * (size_t)std::max<int64_t>(n_nodes, 1)); }
@@ -366,8 +374,8 @@ struct mech_ctx {
     // largest tile's LDS on that path per (voltage mode, shared ion), for the
     // current tile table (cleared when the table is rebuilt)
     std::map<std::pair<int, int>, size_t> res_lds_cache;
-    // graphs of kGraphSteps fused steps, keyed by (vmode, dt)
-    std::map<std::pair<int, uint64_t>, hipGraphExec_t> graphs;
+    // graphs of 1..kGraphSteps fused steps, keyed by (vmode, dt, steps)
+    std::map<std::tuple<int, uint64_t, int>, hipGraphExec_t> graphs;
     std::string err;
     int static_dev = -1;           // device whose static area holds this context (mech_alloc_static)
 };
@@ -599,6 +607,9 @@ int launch_plain_phase(mech_ctx *c, bool cur, int64_t k, const GlobDev &g, int a
     if (cur && !accumulate && g.shared_ca) HIPCHK(c, launch_fill(c->nd.ica, c->nd.ica, (int)c->n_nodes, c->stream));
     for (int s = 0; s < (int)c->slots.size(); ++s) {
         a.slot = slot_dev(c, s);
+        const SlotHost &h = c->slots[s];
+        a.carry_node = (int *)(c->buf + h.off_carry);
+        a.carry_val = (double *)(c->buf + h.off_carry + align_up(4 * ((size_t)h.np / kPad)));
         if (cur) HIPCHK(c, launch_plain_cur(c->fp32, a, c->stream));
         else HIPCHK(c, launch_plain_state(c->fp32, a, c->stream));
     }
@@ -642,20 +653,22 @@ int launch_fused_phase(mech_ctx *c, int phases, int vmode, const GlobDev &g, int
     return MECH_OK;
 }
 
-int get_graph(mech_ctx *c, int vmode, double dt, const GlobDev &g, hipGraphExec_t *out) {
+// A graph of n (1..kGraphSteps) fused steps: pass j reads the step index
+// from the device counter plus j, and the last node advances the counter by
+// n, so one graph serves every chunk of that length.
+int get_graph(mech_ctx *c, int vmode, double dt, const GlobDev &g, int n, hipGraphExec_t *out) {
     uint64_t bits;
     memcpy(&bits, &dt, 8);
-    auto key = std::make_pair(vmode, bits);
+    auto key = std::make_tuple(vmode, bits, n);
     auto it = c->graphs.find(key);
     if (it != c->graphs.end()) { *out = it->second; return MECH_OK; }
     if (!c->capture_stream)
         HIPCHK(c, hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
     HIPCHK(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
     int rc = MECH_OK;
-    for (int j = 0; j < kGraphSteps && rc == MECH_OK; ++j)
+    for (int j = 0; j < n && rc == MECH_OK; ++j)
         rc = launch_fused_phase(c, kDoState | kDoCur, vmode, g, j, c->capture_stream);
-    hipError_t e1 = rc == MECH_OK ? launch_bump_k((long long *)(c->buf + c->L.off_kdev), kGraphSteps,
-                                                  c->capture_stream)
+    hipError_t e1 = rc == MECH_OK ? launch_bump_k((long long *)(c->buf + c->L.off_kdev), n, c->capture_stream)
                                   : hipSuccess;
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(c->capture_stream, &graph);
@@ -695,17 +708,17 @@ int step_batched(mech_ctx *c, int64_t nsteps, int64_t k0, double dt, int vmode, 
     HIPCHK(c, launch_set_k(kdev, k0, c->stream));
     int rc = launch_fused_phase(c, kDoCur, vmode, g, 0, c->stream);
     if (rc) return rc;
-    // middle passes: state(k-1) + events(k) + cur(k) for k = k0+1 .. k0+nsteps-1
+    // middle passes: state(k-1) + events(k) + cur(k) for k = k0+1 .. k0+nsteps-1,
+    // replayed from graphs of kGraphSteps passes and one of the remainder
     int64_t mids = nsteps - 1;
     HIPCHK(c, launch_set_k(kdev, k0 + 1, c->stream));
-    if (use_graph && mids >= kGraphSteps) {
+    while (use_graph && mids > 0) {
+        const int n = (int)std::min<int64_t>(mids, kGraphSteps);
         hipGraphExec_t exec;
-        rc = get_graph(c, vmode, dt, g, &exec);
+        rc = get_graph(c, vmode, dt, g, n, &exec);
         if (rc) return rc;
-        while (mids >= kGraphSteps) {
-            HIPCHK(c, hipGraphLaunch(exec, c->stream));
-            mids -= kGraphSteps;
-        }
+        HIPCHK(c, hipGraphLaunch(exec, c->stream));
+        mids -= n;
     }
     for (int64_t j = 0; j < mids; ++j) {
         rc = launch_fused_phase(c, kDoState | kDoCur, vmode, g, (int)j, c->stream);
@@ -1364,7 +1377,7 @@ static int autotune_impl(mech_ctx *c, double dt, int vmode, int nsteps, int reps
         // stays available through mech_set_launch but is not searched
         for (int b : {128, 256, 512})
             for (int ipt : {1, 2, 4, 8})
-                for (int bpc : {0, 8})
+                for (int bpc : {0, 1, 2, 8})
                     for (int fl : {0, (int)MECH_LAUNCH_XCD_ORDER}) {
                         const int budget = b * ipt;
                         cand.push_back({b, budget, std::min(kMaxTileNodes, std::max(kMinTileNodes, budget)), bpc, fl});

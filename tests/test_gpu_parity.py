@@ -238,6 +238,49 @@ def test_fused_free_voltage_bit_identical_across_runs_and_shapes(prec):
     log(f"free voltage {prec}: {int(base['spikes'].sum())} spikes, identical over 7 runs")
 
 
+@pytest.mark.parametrize("prec", PRECS)
+def test_plain_free_voltage_bit_identical_across_runs(prec):
+    """The plain path sums each node's run within a wave in a fixed shuffle
+    order and adds the parts of runs that cross into later waves in wave
+    order (k_plain_carry), so repeated runs give the same bits."""
+    w = _free_workload()
+    a, _ = run_gpu(w, 400, "plain", prec)
+    assert a["spikes"].sum() > 0
+    b, _ = run_gpu(w, 400, "plain", prec)
+    _assert_same_bits(a, b, "plain repeat")
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_node_index_long_runs_bit_exact(path):
+    """Runs of 1 to 300 instances per node, so that runs cross one or several
+    waves: dyadic values make every sum exact, so rhs and d must equal
+    numpy's np.add.at bit for bit."""
+    rng = np.random.default_rng(15)
+    n_nodes = 400
+    per = rng.integers(0, 300, n_nodes)
+    per[::37] = 0
+    node = np.repeat(np.arange(n_nodes), per).astype(np.int32)
+    node = node[rng.permutation(node.shape[0])]
+    g = rng.integers(1, 64, node.shape[0]) * 2.0 ** -12
+    e = rng.integers(-90, 10, node.shape[0]).astype(float)
+    m = mech.Mechanisms(n_nodes, [("pas", node)], prec="fp64")
+    m.set_params(0, "g", g)
+    m.set_params(0, "e", e)
+    m.set_global("fd_dv", 2.0 ** -10)
+    m.set_launch(128, 512, 256, 0)
+    v = rng.integers(-100, 40, n_nodes).astype(float)
+    m.set_node_array("v", v)
+    m.init()
+    m.step(1, 0, 0.025, "external", path)
+    got = m.nodes()
+    rhs = np.zeros(n_nodes)
+    d = np.zeros(n_nodes)
+    np.add.at(rhs, node, -g * (v[node] - e))
+    np.add.at(d, node, g)
+    assert np.array_equal(got["rhs"], rhs)
+    assert np.array_equal(got["d"], d)
+
+
 def test_resident_free_voltage_fp64_bit_identical_to_batched():
     """The time-fused path runs the per-step path's per-instance code and the
     same exact node sums: in FP64 free-voltage mode it gives the per-step
