@@ -358,11 +358,18 @@ int mech_info(const mech_ctx *ctx, int64_t *n_tiles, int64_t *max_tile_nodes);
  *   op 5 treats dst[0, bytes) as seven FP64 arrays of n = bytes / 56
  *        elements (n a multiple of 256; src unused), reads all seven and
  *        rewrites the first three, the access shape of a Hodgkin-Huxley
- *        slot's STATEs and PARAMETERs (HBM traffic 10/7 bytes).
+ *        slot's STATEs and PARAMETERs (HBM traffic 10/7 bytes);
+ *   op 6 treats dst[0, bytes) as twenty FP64 arrays of n = bytes / 160
+ *        elements (n a multiple of 2048; src unused) in four groups of five,
+ *        two of each group rewritten, streamed in tiles of 2048 elements
+ *        dealt round-robin to the workgroups, group after group within a
+ *        tile (the fused kernel's pattern; HBM traffic 28/20 bytes).
  * `flags` (bitwise or of MECH_PROBE_*): non-temporal hint on the loads or
  * on the stores, 8-byte instead of 16-byte accesses, one contiguous chunk
- * per workgroup instead of the grid-stride mapping, and (op 5) the seven
- * arrays interleaved in blocks of 256 elements instead of laid end to end.
+ * per workgroup instead of the grid-stride mapping, and for op 5 the seven
+ * arrays interleaved in blocks of 256 elements instead of laid end to end,
+ * or (TILED) tiles of 2048 elements dealt round-robin to the workgroups;
+ * for op 6 AOSOA stores each tile's twenty arrays contiguously.
  * The streaming HBM ceilings the mechanism kernels are compared with.
  * Asynchronous.                                                            */
 #define MECH_PROBE_NT_LOAD 1
@@ -370,6 +377,7 @@ int mech_info(const mech_ctx *ctx, int64_t *n_tiles, int64_t *max_tile_nodes);
 #define MECH_PROBE_8B 4
 #define MECH_PROBE_CHUNKED 8
 #define MECH_PROBE_AOSOA 16
+#define MECH_PROBE_TILED 32
 int mech_probe_stream(int op, int unroll, int blocks_per_cu, int flags, void *dst, const void *src, size_t bytes,
                       void *hip_stream);
 

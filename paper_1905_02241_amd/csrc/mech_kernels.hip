@@ -1657,20 +1657,13 @@ __global__ __launch_bounds__(256) void k_stream(T *__restrict__ dst, const T *__
 // elements (element i of array a at ((i / 256) 7 + a) 256 + i % 256), so a
 // wave's seven accesses fall in one 14 KiB region instead of seven pages
 // n elements apart; n is a multiple of 256 then.
+// `mapping`: 0 grid-stride, 1 one contiguous range per workgroup, 2 tiles of
+// 2048 elements dealt round-robin to the workgroups (the fused kernel's
+// pattern: each workgroup streams its own range, and the ranges in flight at
+// one time are neighbours).
 template <int U, bool NTL, bool NTS, bool AOS>
-__global__ __launch_bounds__(256) void k_rmw7(double *__restrict__ base, size_t n, int chunked) {
+__global__ __launch_bounds__(256) void k_rmw7(double *__restrict__ base, size_t n, int mapping) {
     const int nb = (int)gridDim.x, b = (int)blockIdx.x;
-    size_t i, stride, end = n;
-    if (chunked) {
-        const size_t per = (n + (size_t)nb - 1) / (size_t)nb;
-        const size_t lo = min(n, per * (size_t)b);
-        end = min(n, lo + per);
-        i = lo + threadIdx.x;
-        stride = blockDim.x;
-    } else {
-        i = (size_t)b * blockDim.x + threadIdx.x;
-        stride = (size_t)nb * blockDim.x;
-    }
     auto at = [n](int a, size_t j) -> size_t {
         return AOS ? ((j >> 8) * 7 + (size_t)a) * 256 + (j & 255) : (size_t)a * n + j;
     };
@@ -1682,21 +1675,84 @@ __global__ __launch_bounds__(256) void k_rmw7(double *__restrict__ base, size_t 
         st<NTS>(base + at(1, j), x[1] * x[5] + x[6]);
         st<NTS>(base + at(2, j), x[2] * x[3] + x[6]);
     };
-    for (; i + (U - 1) * stride < end; i += U * stride) {
-        double x[U][7];
+    auto range = [&](size_t i, size_t stride, size_t end) {
+        for (; i + (U - 1) * stride < end; i += U * stride) {
+            double x[U][7];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+            for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int a = 0; a < 7; ++a) x[u][a] = ld<NTL>(base + at(a, i + u * stride));
+                for (int a = 0; a < 7; ++a) x[u][a] = ld<NTL>(base + at(a, i + u * stride));
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const size_t j = i + u * stride;
-            st<NTS>(base + at(0, j), x[u][0] * x[u][3] + x[u][4]);
-            st<NTS>(base + at(1, j), x[u][1] * x[u][5] + x[u][6]);
-            st<NTS>(base + at(2, j), x[u][2] * x[u][3] + x[u][6]);
+            for (int u = 0; u < U; ++u) {
+                const size_t j = i + u * stride;
+                st<NTS>(base + at(0, j), x[u][0] * x[u][3] + x[u][4]);
+                st<NTS>(base + at(1, j), x[u][1] * x[u][5] + x[u][6]);
+                st<NTS>(base + at(2, j), x[u][2] * x[u][3] + x[u][6]);
+            }
+        }
+        for (; i < end; i += stride) one(i);
+    };
+    if (mapping == 2) {
+        constexpr size_t T = 2048;
+        for (size_t lo = (size_t)b * T; lo < n; lo += (size_t)nb * T) range(lo + threadIdx.x, blockDim.x, min(n, lo + T));
+    } else if (mapping == 1) {
+        const size_t per = (n + (size_t)nb - 1) / (size_t)nb;
+        const size_t lo = min(n, per * (size_t)b);
+        range(lo + threadIdx.x, blockDim.x, min(n, lo + per));
+    } else {
+        range((size_t)b * blockDim.x + threadIdx.x, (size_t)nb * blockDim.x, n);
+    }
+}
+
+// op 6: twenty FP64 arrays of n elements in four groups of five (two read
+// and rewritten, three read only), streamed in tiles of 2048 elements dealt
+// round-robin to the workgroups, one group after another within a tile: the
+// fused kernel's pattern of several mechanism types per node tile.  TM
+// (tile-major) stores each tile's twenty arrays contiguously
+// (element j of array a at ((j / 2048) 20 + a) 2048 + j % 2048), so a tile
+// is one contiguous range; n is a multiple of 2048.
+template <int U, bool NTL, bool NTS, bool TM>
+__global__ __launch_bounds__(256) void k_rmw20(double *__restrict__ base, size_t n) {
+    constexpr size_t T = 2048;
+    const int nb = (int)gridDim.x, b = (int)blockIdx.x;
+    auto at = [n](int a, size_t j) -> size_t {
+        return TM ? ((j / T) * 20 + (size_t)a) * T + (j % T) : (size_t)a * n + j;
+    };
+    for (size_t lo = (size_t)b * T; lo < n; lo += (size_t)nb * T) {
+        const size_t end = min(n, lo + T);
+#pragma unroll 1
+        for (int g = 0; g < 4; ++g) {
+            const int a0 = 5 * g;
+            size_t i = lo + threadIdx.x;
+            for (; i + (U - 1) * blockDim.x < end; i += U * blockDim.x) {
+                double x[U][5];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int a = 0; a < 5; ++a) x[u][a] = ld<NTL>(base + at(a0 + a, i + u * blockDim.x));
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const size_t j = i + u * blockDim.x;
+                    st<NTS>(base + at(a0, j), x[u][0] * x[u][2] + x[u][3]);
+                    st<NTS>(base + at(a0 + 1, j), x[u][1] * x[u][4] + x[u][3]);
+                }
+            }
+            for (; i < end; i += blockDim.x) {
+                double x[5];
+#pragma unroll
+                for (int a = 0; a < 5; ++a) x[a] = ld<NTL>(base + at(a0 + a, i));
+                st<NTS>(base + at(a0, i), x[0] * x[2] + x[3]);
+                st<NTS>(base + at(a0 + 1, i), x[1] * x[4] + x[3]);
+            }
         }
     }
-    for (; i < end; i += stride) one(i);
+}
+template <int U, bool NTL, bool NTS>
+static hipError_t rmw20_go(int tm, void *d, size_t bytes, int grid, hipStream_t s) {
+    const size_t n = bytes / 160;
+    if (tm) k_rmw20<U, NTL, NTS, true><<<grid, 256, 0, s>>>((double *)d, n);
+    else k_rmw20<U, NTL, NTS, false><<<grid, 256, 0, s>>>((double *)d, n);
+    return hipGetLastError();
 }
 
 template <int OP, int U, bool NTL, bool NTS>
@@ -1719,9 +1775,19 @@ static hipError_t rmw7_go(int aos, void *d, size_t bytes, int grid, int chunked,
 }
 template <int OP, int U>
 static hipError_t stream_nt(int flags, void *d, const void *r, size_t bytes, int grid, hipStream_t s) {
-    const int wide = !(flags & MECH_PROBE_8B), ch = (flags & MECH_PROBE_CHUNKED) ? 1 : 0;
-    if constexpr (OP == 5) {
+    const int wide = !(flags & MECH_PROBE_8B);
+    int ch = (flags & MECH_PROBE_CHUNKED) ? 1 : 0;
+    if constexpr (OP == 6) {
+        const int tm = (flags & MECH_PROBE_AOSOA) ? 1 : 0;
+        switch (flags & (MECH_PROBE_NT_LOAD | MECH_PROBE_NT_STORE)) {
+        case 0: return rmw20_go<U, false, false>(tm, d, bytes, grid, s);
+        case MECH_PROBE_NT_LOAD: return rmw20_go<U, true, false>(tm, d, bytes, grid, s);
+        case MECH_PROBE_NT_STORE: return rmw20_go<U, false, true>(tm, d, bytes, grid, s);
+        default: return rmw20_go<U, true, true>(tm, d, bytes, grid, s);
+        }
+    } else if constexpr (OP == 5) {
         const int aos = (flags & MECH_PROBE_AOSOA) ? 1 : 0;
+        if (flags & MECH_PROBE_TILED) ch = 2;
         switch (flags & (MECH_PROBE_NT_LOAD | MECH_PROBE_NT_STORE)) {
         case 0: return rmw7_go<U, false, false>(aos, d, bytes, grid, ch, s);
         case MECH_PROBE_NT_LOAD: return rmw7_go<U, true, false>(aos, d, bytes, grid, ch, s);
@@ -1758,6 +1824,7 @@ hipError_t launch_stream(int op, int unroll, int flags, void *dst, const void *s
     case 3: return stream_u<3>(unroll, flags, dst, src, bytes, grid, s);
     case 4: return stream_u<4>(unroll, flags, dst, src, bytes, grid, s);
     case 5: return stream_u<5>(unroll, flags, dst, src, bytes, grid, s);
+    case 6: return stream_u<6>(unroll, flags, dst, src, bytes, grid, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -1527,13 +1527,15 @@ int mech_sync(mech_ctx *c) {
 
 int mech_probe_stream(int op, int unroll, int blocks_per_cu, int flags, void *dst, const void *src, size_t bytes,
                       void *hip_stream) {
-    if (op < 0 || op > 5 || (unroll != 1 && unroll != 2 && unroll != 4 && unroll != 8) || blocks_per_cu < 1 ||
-        blocks_per_cu > 64 || flags < 0 || flags > 31)
-        return fail(nullptr, MECH_ERR_INVAL, "probe: op 0..5, unroll 1/2/4/8, blocks_per_cu 1..64, flags 0..31");
-    if (!dst || (op != 2 && op != 5 && !src) || bytes % 16 || ((uintptr_t)dst | (uintptr_t)src) % 16)
+    if (op < 0 || op > 6 || (unroll != 1 && unroll != 2 && unroll != 4 && unroll != 8) || blocks_per_cu < 1 ||
+        blocks_per_cu > 64 || flags < 0 || flags > 63)
+        return fail(nullptr, MECH_ERR_INVAL, "probe: op 0..6, unroll 1/2/4/8, blocks_per_cu 1..64, flags 0..63");
+    if (!dst || (op != 2 && op < 5 && !src) || bytes % 16 || ((uintptr_t)dst | (uintptr_t)src) % 16)
         return fail(nullptr, MECH_ERR_INVAL, "probe needs 16-byte aligned buffers and size");
     if (op == 5 && (bytes % 56 || (bytes / 56) % 256))
         return fail(nullptr, MECH_ERR_INVAL, "probe op 5: bytes must be 56 times a multiple of 256");
+    if (op == 6 && (bytes % 160 || (bytes / 160) % 2048))
+        return fail(nullptr, MECH_ERR_INVAL, "probe op 6: bytes must be 160 times a multiple of 2048");
     int dev = 0, cu = 256;
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev);

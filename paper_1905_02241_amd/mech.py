@@ -294,8 +294,8 @@ STATE_NAMES = {"pas": (), "hh": ("m", "h", "n"), "ih": ("m",), "cahva": ("m", "h
 CA_KINDS = ("cahva", "capump", "cabuf")
 
 
-PROBE_OPS = {"copy": 0, "read": 1, "write": 2, "triad": 3, "split": 4, "rmw7": 5}
-PROBE_FLAGS = {"nt_load": 1, "nt_store": 2, "8b": 4, "chunked": 8, "aosoa": 16}
+PROBE_OPS = {"copy": 0, "read": 1, "write": 2, "triad": 3, "split": 4, "rmw7": 5, "rmw20": 6}
+PROBE_FLAGS = {"nt_load": 1, "nt_store": 2, "8b": 4, "chunked": 8, "aosoa": 16, "tiled": 32}
 
 
 def probe_stream(op: str = "copy", nbytes: int = 1 << 32, unroll: int = 4, blocks_per_cu: int = 8,
@@ -313,7 +313,12 @@ def probe_stream(op: str = "copy", nbytes: int = 1 << 32, unroll: int = 4, block
     fl = 0
     for f in flags:
         fl |= PROBE_FLAGS[f]
-    if op == "rmw7":
+    if op == "rmw20":
+        half = (nbytes * 20 // 28) // (160 * 2048) * (160 * 2048)
+        src = torch.empty(16, dtype=torch.uint8, device="cuda")
+        dst = torch.zeros(half // 8, dtype=torch.float64, device="cuda")
+        dst.fill_(0.5)
+    elif op == "rmw7":
         half = (nbytes * 7 // 10) // (56 * 256) * (56 * 256)
         src = torch.empty(16, dtype=torch.uint8, device="cuda")
         dst = torch.zeros(half // 8, dtype=torch.float64, device="cuda")
@@ -344,7 +349,7 @@ def probe_stream(op: str = "copy", nbytes: int = 1 << 32, unroll: int = 4, block
         e1.synchronize()
         ts.append(e0.elapsed_time(e1) * 1e-3)
     ts.sort()
-    moved = half * 10 // 7 if op == "rmw7" else part * half
+    moved = half * 10 // 7 if op == "rmw7" else half * 28 // 20 if op == "rmw20" else part * half
     del src, dst
     return moved / ts[len(ts) // 2] / 1e9
 
