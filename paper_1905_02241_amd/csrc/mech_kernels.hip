@@ -408,105 +408,100 @@ template <bool NT, class T> __device__ __forceinline__ void st(T *p, T v) {
 // FOLD (fused path): the calcium pool needs only cai and the ica of the
 // current update, so it is advanced right after that update in the same pass
 // rather than stored and re-read by the next pass's state update.
+// The update is split into its loads (load_inst: every STATE and PARAMETER
+// the pass reads, and the event stream id) and the rest (apply_inst), so
+// that the fused tile loop can issue the loads of several instances before
+// it computes any of them; instance() is the two in sequence.
+template <class S> struct InstIn {
+    S s[4];                 // STATEs
+    S p[4];                 // PARAMETERs
+    S ica;                  // the last ica (pool update in the state pass)
+    unsigned long long id;  // event stream of a synapse
+};
+
 template <class S, int KIND, int PH, bool NT = false, bool FOLD = false>
-__device__ __forceinline__ void instance(const SlotDev &sl, int i, double v, const GlobDev &g, long long k,
-                                         double &ci, double &cg, int &flag) {
+__device__ __forceinline__ void load_inst(const SlotDev &sl, int i, InstIn<S> &q) {
+    constexpr bool cur = (PH & kDoCur) != 0, state = (PH & kDoState) != 0;
+    constexpr int n_st = KIND == MECH_PAS ? 0 : KIND == MECH_IH ? 1 : KIND == MECH_SYN ? 4 : 3;
+    constexpr int n_par = KIND == MECH_PAS ? 2 : KIND == MECH_HH ? 4 : KIND == MECH_SYN ? 0 : 1;
+#pragma unroll
+    for (int j = 0; j < n_st; ++j) q.s[j] = ld<NT>((const S *)sl.st[j] + i);
+    if constexpr (cur) {
+#pragma unroll
+        for (int j = 0; j < n_par; ++j) q.p[j] = ld<NT>((const S *)sl.par[j] + i);
+    }
+    if constexpr (KIND == MECH_CAHVA || KIND == MECH_CAPUMP || KIND == MECH_CABUF) {
+        if (state && !FOLD) q.ica = ld<NT>((const S *)sl.ica + i);
+    }
+    if constexpr (KIND == MECH_CABUF) {
+        if ((state && !FOLD) || (cur && FOLD)) q.s[3] = ld<NT>((const S *)sl.st[3] + i);
+    }
+    if constexpr (KIND == MECH_SYN && cur)
+        q.id = sl.gid ? (unsigned long long)(long long)sl.gid[i] : (unsigned long long)i;
+}
+
+template <class S, int KIND, int PH, bool NT = false, bool FOLD = false>
+__device__ __forceinline__ void apply_inst(const SlotDev &sl, int i, InstIn<S> &q, double v, const GlobDev &g,
+                                           long long k, double &ci, double &cg, int &flag) {
     ci = 0.0;
     cg = 0.0;
     if constexpr (KIND == MECH_PAS) {
-        if (PH & kDoCur) {
-            const S gp = ld<NT>((const S *)sl.par[0] + i);
-            const double e = (double)ld<NT>((const S *)sl.par[1] + i);
-            lin_cur<S>(v, gp, e, g, ci, cg);
-        }
+        if (PH & kDoCur) lin_cur<S>(v, q.p[0], (double)q.p[1], g, ci, cg);
     } else if constexpr (KIND == MECH_HH) {
-        S *M = (S *)sl.st[0], *H = (S *)sl.st[1], *N = (S *)sl.st[2];
-        S m = ld<NT>(M + i), h = ld<NT>(H + i), n = ld<NT>(N + i);
+        S &m = q.s[0], &h = q.s[1], &n = q.s[2];
         if (PH & kDoState) {
             hh_state(v, g, m, h, n);
             flag |= bad(m) | bad(h) | bad(n);
-            st<NT>(M + i, m); st<NT>(H + i, h); st<NT>(N + i, n);
+            st<NT>((S *)sl.st[0] + i, m); st<NT>((S *)sl.st[1] + i, h); st<NT>((S *)sl.st[2] + i, n);
         }
-        if (PH & kDoCur) {
-            const S gnabar = ld<NT>((const S *)sl.par[0] + i);
-            const S gkbar = ld<NT>((const S *)sl.par[1] + i);
-            const S gl = ld<NT>((const S *)sl.par[2] + i);
-            const double el = (double)ld<NT>((const S *)sl.par[3] + i);
-            hh_cur<S>(v, m, h, n, gnabar, gkbar, gl, el, g, ci, cg);
-        }
+        if (PH & kDoCur) hh_cur<S>(v, m, h, n, q.p[0], q.p[1], q.p[2], (double)q.p[3], g, ci, cg);
     } else if constexpr (KIND == MECH_IH) {
-        S *M = (S *)sl.st[0];
-        S m = ld<NT>(M + i);
+        S &m = q.s[0];
         if (PH & kDoState) {
             ih_state(v, g, m);
             flag |= bad(m);
-            st<NT>(M + i, m);
+            st<NT>((S *)sl.st[0] + i, m);
         }
-        if (PH & kDoCur) {
-            const S gbar = ld<NT>((const S *)sl.par[0] + i);
-            lin_cur<S>(v, (S)(gbar * m), g.eh, g, ci, cg);
-        }
-    } else if constexpr (KIND == MECH_CAHVA) {
+        if (PH & kDoCur) lin_cur<S>(v, (S)(q.p[0] * m), g.eh, g, ci, cg);
+    } else if constexpr (KIND == MECH_CAHVA || KIND == MECH_CAPUMP) {
         S *M = (S *)sl.st[0], *H = (S *)sl.st[1], *CAI = (S *)sl.st[2], *ICA = (S *)sl.ica;
-        S m = ld<NT>(M + i), h = ld<NT>(H + i), cai = ld<NT>(CAI + i);
+        S &m = q.s[0], &h = q.s[1], &cai = q.s[2];
+        auto pool = [&g](S ica, S &c) {
+            if constexpr (KIND == MECH_CAHVA) ca_pool(g, ica, c);
+            else capump_pool(g, ica, c);
+        };
         if (PH & kDoState) {
             ca_gates(v, g, m, h);
-            if (!FOLD) ca_pool(g, ld<NT>(ICA + i), cai);
+            if (!FOLD) pool(q.ica, cai);
             flag |= bad(m) | bad(h) | bad(cai);
             st<NT>(M + i, m); st<NT>(H + i, h);
             if (!FOLD) st<NT>(CAI + i, cai);
         }
         if (PH & kDoCur) {
-            const S gbar = ld<NT>((const S *)sl.par[0] + i);
-            const S ica = (S)ca_cur<S>(v, m, h, cai, gbar, g, ci, cg);
+            const S ica = (S)ca_cur<S>(v, m, h, cai, q.p[0], g, ci, cg);
             st<NT>(ICA + i, ica);
             if (FOLD) {
-                ca_pool(g, ica, cai);
+                pool(ica, cai);
                 flag |= bad(cai);
                 st<NT>(CAI + i, cai);
             }
         }
     } else if constexpr (KIND == MECH_KMARKOV) {
-        S *X0 = (S *)sl.st[0], *X1 = (S *)sl.st[1], *X2 = (S *)sl.st[2];
-        S c1 = ld<NT>(X0 + i), c2 = ld<NT>(X1 + i), o = ld<NT>(X2 + i);
+        S &c1 = q.s[0], &c2 = q.s[1], &o = q.s[2];
         if (PH & kDoState) {
             kmarkov_state(v, g, c1, c2, o);
             flag |= bad(c1) | bad(c2) | bad(o);
-            st<NT>(X0 + i, c1); st<NT>(X1 + i, c2); st<NT>(X2 + i, o);
+            st<NT>((S *)sl.st[0] + i, c1); st<NT>((S *)sl.st[1] + i, c2); st<NT>((S *)sl.st[2] + i, o);
         }
-        if (PH & kDoCur) {
-            const S gbar = ld<NT>((const S *)sl.par[0] + i);
-            lin_cur<S>(v, (S)(gbar * o), g.ek, g, ci, cg);
-        }
-    } else if constexpr (KIND == MECH_CAPUMP) {
-        S *M = (S *)sl.st[0], *H = (S *)sl.st[1], *CAI = (S *)sl.st[2], *ICA = (S *)sl.ica;
-        S m = ld<NT>(M + i), h = ld<NT>(H + i), cai = ld<NT>(CAI + i);
-        if (PH & kDoState) {
-            ca_gates(v, g, m, h);
-            if (!FOLD) capump_pool(g, ld<NT>(ICA + i), cai);
-            flag |= bad(m) | bad(h) | bad(cai);
-            st<NT>(M + i, m); st<NT>(H + i, h);
-            if (!FOLD) st<NT>(CAI + i, cai);
-        }
-        if (PH & kDoCur) {
-            const S gbar = ld<NT>((const S *)sl.par[0] + i);
-            const S ica = (S)ca_cur<S>(v, m, h, cai, gbar, g, ci, cg);
-            st<NT>(ICA + i, ica);
-            if (FOLD) {
-                capump_pool(g, ica, cai);
-                flag |= bad(cai);
-                st<NT>(CAI + i, cai);
-            }
-        }
+        if (PH & kDoCur) lin_cur<S>(v, (S)(q.p[0] * o), g.ek, g, ci, cg);
     } else if constexpr (KIND == MECH_CABUF) {
         S *M = (S *)sl.st[0], *H = (S *)sl.st[1], *CAI = (S *)sl.st[2], *CAB = (S *)sl.st[3];
         S *ICA = (S *)sl.ica;
-        S m = ld<NT>(M + i), h = ld<NT>(H + i), cai = ld<NT>(CAI + i);
+        S &m = q.s[0], &h = q.s[1], &cai = q.s[2], &cab = q.s[3];
         if (PH & kDoState) {
             ca_gates(v, g, m, h);
             if (!FOLD) {
-                S cab = ld<NT>(CAB + i);
-                cabuf_pool<S>(g, ld<NT>(ICA + i), cai, cab);
+                cabuf_pool<S>(g, q.ica, cai, cab);
                 flag |= bad(cab);
                 st<NT>(CAI + i, cai); st<NT>(CAB + i, cab);
             }
@@ -514,25 +509,19 @@ __device__ __forceinline__ void instance(const SlotDev &sl, int i, double v, con
             st<NT>(M + i, m); st<NT>(H + i, h);
         }
         if (PH & kDoCur) {
-            const S gbar = ld<NT>((const S *)sl.par[0] + i);
-            const S ica = (S)ca_cur<S>(v, m, h, cai, gbar, g, ci, cg);
+            const S ica = (S)ca_cur<S>(v, m, h, cai, q.p[0], g, ci, cg);
             st<NT>(ICA + i, ica);
             if (FOLD) {
-                S cab = ld<NT>(CAB + i);
                 cabuf_pool<S>(g, ica, cai, cab);
                 flag |= bad(cai) | bad(cab);
                 st<NT>(CAI + i, cai); st<NT>(CAB + i, cab);
             }
         }
     } else if constexpr (KIND == MECH_SYN) {
-        S x[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) x[j] = ld<NT>((const S *)sl.st[j] + i);
+        S *x = q.s;
         if (PH & kDoState) syn_decay(x, g);
         if (PH & kDoCur) {
-            const unsigned long long id = sl.gid ? (unsigned long long)(long long)sl.gid[i]
-                                                 : (unsigned long long)i;
-            if (splitmix(g.seed, id, (unsigned long long)k) < g.threshold) {
+            if (splitmix(g.seed, q.id, (unsigned long long)k) < g.threshold) {
                 const double w = ((const double *)sl.par[0])[i];
                 x[0] += (S)(w * g.fa);
                 x[1] += (S)(w * g.fa);
@@ -545,6 +534,14 @@ __device__ __forceinline__ void instance(const SlotDev &sl, int i, double v, con
 #pragma unroll
         for (int j = 0; j < 4; ++j) st<NT>((S *)sl.st[j] + i, x[j]);
     }
+}
+
+template <class S, int KIND, int PH, bool NT = false, bool FOLD = false>
+__device__ __forceinline__ void instance(const SlotDev &sl, int i, double v, const GlobDev &g, long long k,
+                                         double &ci, double &cg, int &flag) {
+    InstIn<S> q;
+    load_inst<S, KIND, PH, NT, FOLD>(sl, i, q);
+    apply_inst<S, KIND, PH, NT, FOLD>(sl, i, q, v, g, k, ci, cg, flag);
 }
 
 // A cahva, capump or cabuf instance under the shared calcium ion: its gates,
@@ -1233,7 +1230,7 @@ __device__ __forceinline__ int tile_of(int b, int T, int xcd_order) {
 // the shared calcium ion (a run-time switch there).  They are kept apart so
 // that the default instantiations keep their register budget.
 template <class S, int PH, int VM, bool NT, bool EXT = false>
-__global__ __launch_bounds__(1024) void k_fused(FusedArgs a, int tn) {
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(sizeof(S) == 4 ? 5 : 1))) void k_fused(FusedArgs a, int tn) {
     extern __shared__ double lds[];
     unsigned long long *w = (unsigned long long *)lds;
     double *vl = lds, *sc = lds + tn;
