@@ -303,9 +303,10 @@ def probe_stream(op: str = "copy", nbytes: int = 1 << 32, unroll: int = 4, block
     """Achieved GB/s of the library's streaming probe over `nbytes` of HBM
     traffic (copy and split: nbytes/2 read + nbytes/2 written; triad:
     2 nbytes/3 read + nbytes/3 written; read, write: nbytes; rmw7: seven
-    arrays of 7 nbytes/10 read, three of them rewritten); median of `reps`
+    arrays of 7 nbytes/10 read, three of them rewritten; rmw20: twenty
+    arrays of 20 nbytes/28 read, eight of them rewritten); median of `reps`
     launches timed with events on the current stream.  `flags` names
-    MECH_PROBE_* options (nt_load, nt_store, 8b, chunked, aosoa).
+    MECH_PROBE_* options (nt_load, nt_store, 8b, chunked, aosoa, tiled).
     Checks every return code and, for the copy, the copied bytes."""
     import torch
     L = load_library()
