@@ -401,18 +401,21 @@ PROBE_FLAG_SETS = ((), ("nt_load",), ("nt_store",), ("nt_load", "nt_store"), ("8
 
 
 def probe_battery(mech, nbytes: int = 1 << 32):
-    """Every streaming probe at its best unroll (2, 4, 8; also 1 for the
-    seven-array probe) and blocks per CU (1, 2, 4, 8, 16): GB/s per op and
-    flag set, with the whole grid."""
+    """Every streaming probe at its best unroll (2, 4, 8; 1 to 8 for the
+    seven-array probe, 1 to 4 for the twenty-array one) and blocks per CU
+    (1, 2, 4, 8, 16): GB/s per op and flag set, with the whole grid."""
     out = {}
     rmw_sets = tuple(fl + extra for fl in ((), ("chunked",), ("nt_load", "nt_store"), ("chunked", "nt_load", "nt_store"))
-                     for extra in ((), ("aosoa",)))
-    for op in ("rmw7", "copy", "triad", "split", "read", "write"):
-        for fl in (rmw_sets if op == "rmw7" else PROBE_FLAG_SETS):
+                     for extra in ((), ("aosoa",))) + (("tiled",), ("tiled", "nt_load", "nt_store"))
+    rmw20_sets = ((), ("aosoa",), ("nt_load", "nt_store"), ("aosoa", "nt_load", "nt_store"))
+    sets = {"rmw7": rmw_sets, "rmw20": rmw20_sets}
+    unrolls = {"rmw7": (1, 2, 4, 8), "rmw20": (1, 2, 4)}
+    for op in ("rmw7", "rmw20", "copy", "triad", "split", "read", "write"):
+        for fl in sets.get(op, PROBE_FLAG_SETS):
             if op == "read" and "nt_store" in fl or op == "write" and "nt_load" in fl:
                 continue
             best, grid = None, {}
-            for u in ((1, 2, 4, 8) if op == "rmw7" else (2, 4, 8)):
+            for u in unrolls.get(op, (2, 4, 8)):
                 for b in (1, 2, 4, 8, 16):
                     g = mech.probe_stream(op, nbytes, unroll=u, blocks_per_cu=b, reps=5, flags=fl)
                     grid[f"u{u}b{b}"] = round(g)

@@ -1230,7 +1230,7 @@ __device__ __forceinline__ int tile_of(int b, int T, int xcd_order) {
 // the shared calcium ion (a run-time switch there).  They are kept apart so
 // that the default instantiations keep their register budget.
 template <class S, int PH, int VM, bool NT, bool EXT = false>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(sizeof(S) == 4 ? 5 : 1))) void k_fused(FusedArgs a, int tn) {
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(sizeof(S) == 4 && VM != MECH_V_CLAMP ? 5 : 1))) void k_fused(FusedArgs a, int tn) {
     extern __shared__ double lds[];
     unsigned long long *w = (unsigned long long *)lds;
     double *vl = lds, *sc = lds + tn;
