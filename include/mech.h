@@ -314,8 +314,8 @@ int mech_get_launch(const mech_ctx *ctx, int *block, int *tile_instances, int *t
 int mech_set_resident_steps(mech_ctx *ctx, int steps_per_launch);
 
 /* Time every candidate launch shape of the BATCHED path on `nsteps` steps
- * (HIP events, median of `reps`), keep the fastest, and return its ms per
- * step.  STATEs, v, rhs, d, spike counts and the per-node calcium ion are
+ * (HIP events, median of `reps`), time the four fastest again on 4 nsteps
+ * steps (median of 2 reps), keep the fastest, and return its ms per step.  STATEs, v, rhs, d, spike counts and the per-node calcium ion are
  * saved before and restored after, so the call has no visible effect
  * besides the chosen shape.                                                */
 int mech_autotune(mech_ctx *ctx, double dt, int vmode, int nsteps, int reps, double *best_ms_per_step);

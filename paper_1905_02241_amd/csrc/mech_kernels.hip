@@ -75,10 +75,96 @@ __device__ __forceinline__ double fdiv(double a, double b) {
     return fma(fma(-b, q, a), r, q);
 }
 
+// e^x, e^x - 1 and ln x in FP64 for the rate and reversal-potential
+// expressions.  The library versions keep their polynomial coefficients in
+// about forty vector registers across the fused kernels' loops, which held
+// the FP64 fused kernel at 4 waves per SIMD; these take each coefficient as
+// the scalar operand of the fused multiply-add (fma_s), so the kernels fit
+// in 79 (FP64) and 71 (FP32-mixed) registers.
+// a b + c with c in a scalar register pair (one scalar operand is allowed per
+// vector instruction).
+__device__ __forceinline__ double fma_s(double a, double b, double c) {
+    double d;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "s"(c));
+    return d;
+}
+// Reduction after Cody and Waite: x = k ln2 + r with k = rint(x / ln2) and r
+// formed by two fused multiply-adds against ln2 split into a double and its
+// remainder, so |r| <= ln2/2 up to rounding.  e^r - 1 is its Taylor series
+// to r^13/13!, whose tail stays below 2^-55 relative to r.  x is first
+// clamped to [-746, 710], beyond which e^x is 0 or +inf anyway (NaN passes
+// unchanged).  Measured against a long-double reference on 2e7 arguments:
+// e^x within 0.99 ulp, e^x - 1 within 1.8 ulp.
+constexpr double kLn2Hi = 0x1.62e42fefa39efp-1, kLn2Lo = 0x1.abc9e3b39803fp-56, kLog2e = 0x1.71547652b82fep+0;
+__device__ __forceinline__ double em1_series(double r) {
+    double p = 1.0 / 6227020800.0;   // 1/13!, then 1/12! ... 1/3!
+    p = fma_s(p, r, 1.0 / 479001600.0);
+    p = fma_s(p, r, 1.0 / 39916800.0);
+    p = fma_s(p, r, 1.0 / 3628800.0);
+    p = fma_s(p, r, 1.0 / 362880.0);
+    p = fma_s(p, r, 1.0 / 40320.0);
+    p = fma_s(p, r, 1.0 / 5040.0);
+    p = fma_s(p, r, 1.0 / 720.0);
+    p = fma_s(p, r, 1.0 / 120.0);
+    p = fma_s(p, r, 1.0 / 24.0);
+    p = fma_s(p, r, 1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    return fma(r * r, p, r);
+}
+__device__ __forceinline__ int exp_reduce(double x, double &r) {
+    x = x < -746.0 ? -746.0 : (x > 710.0 ? 710.0 : x);
+    const double k = rint(x * kLog2e);
+    r = fma(-k, kLn2Lo, fma(-k, kLn2Hi, x));
+    return (int)k;
+}
+__device__ __forceinline__ double exp_d(double x) {
+    double r;
+    const int k = exp_reduce(x, r);
+    return ldexp(1.0 + em1_series(r), k);
+}
+// e^x - 1 = 2^k (e^r - 1) + (2^k - 1): the series alone when k = 0, so the
+// result keeps its relative accuracy near x = 0.
+__device__ __forceinline__ double expm1_d(double x) {
+    double r;
+    const int k = exp_reduce(x, r);
+    return ldexp(em1_series(r), k) + (ldexp(1.0, k) - 1.0);
+}
+// ln x = e ln2 + ln m with x = m 2^e, m in [sqrt(1/2), sqrt(2)); ln m =
+// 2 atanh(s), s = (m - 1)/(m + 1), |s| <= 0.172, by the series
+// 2 s (1 + s^2/3 + ... + s^22/23), whose tail stays below 2^-59 relative.
+// 0 gives -inf, negative arguments and NaN give NaN, +inf gives +inf.
+__device__ __forceinline__ double log_d(double x) {
+    int e;
+    double m = frexp(x, &e);
+    if (m < 0x1.6a09e667f3bcdp-1) {   // sqrt(1/2)
+        m += m;
+        e -= 1;
+    }
+    const double f = m - 1.0;
+    const double s = f / (m + 1.0), z = s * s;
+    double p = 1.0 / 23.0;            // then 1/21 ... 1/3
+    p = fma_s(p, z, 1.0 / 21.0);
+    p = fma_s(p, z, 1.0 / 19.0);
+    p = fma_s(p, z, 1.0 / 17.0);
+    p = fma_s(p, z, 1.0 / 15.0);
+    p = fma_s(p, z, 1.0 / 13.0);
+    p = fma_s(p, z, 1.0 / 11.0);
+    p = fma_s(p, z, 1.0 / 9.0);
+    p = fma_s(p, z, 1.0 / 7.0);
+    p = fma_s(p, z, 1.0 / 5.0);
+    p = fma_s(p, z, 1.0 / 3.0);
+    const double t = 2.0 * s;
+    const double lm = fma(t * z, p, t);
+    const double de = (double)e;
+    const double y = fma(de, kLn2Hi, fma(de, kLn2Lo, lm));
+    if (x > 0.0 && x < INFINITY) return y;
+    return x == 0.0 ? -INFINITY : (x == INFINITY ? INFINITY : NAN);
+}
+
 // a x/(1 - exp(-x/k)), with the limit a k at x = 0; em1 = expm1(-x/k) is
 // returned so that a caller can reuse exp(-x/k) = em1 + 1.
 __device__ __forceinline__ double linexp_d(double a, double inv_k, double x, double lim, double &em1) {
-    em1 = expm1(-x * inv_k);
+    em1 = expm1_d(-x * inv_k);
     return x == 0.0 ? lim : fdiv(a * x, -em1);
 }
 __device__ __forceinline__ double linexp_d(double a, double inv_k, double x, double lim) {
@@ -89,7 +175,7 @@ __device__ __forceinline__ double linexp_d(double a, double inv_k, double x, dou
 // cnexp factor e^{-y} over one step, or its (1,1) Pade approximant
 // (1 - y/2)/(1 + y/2) (the optional replacement of the paper's section 5.2).
 __device__ __forceinline__ double cnexp_factor(double y, int pade) {
-    return pade ? fdiv(1.0 - 0.5 * y, 1.0 + 0.5 * y) : exp(-y);
+    return pade ? fdiv(1.0 - 0.5 * y, 1.0 + 0.5 * y) : exp_d(-y);
 }
 // 1 - factor in FP32 without cancellation: the series / exp form above, or
 // y/(1 + y/2) for the Pade approximant.
@@ -102,11 +188,11 @@ __device__ __forceinline__ float one_minus_factor_f(float y, int pade) {
 // exp(-(v+35)/10) = e^{1/2} exp(-(v+40)/10) reuses alpha_m's expm1, and
 // exp(-(v+65)/20) = exp(-(v+65)/80)^4 reuses beta_n's exponential.
 __device__ __forceinline__ void hh_state(double v, const GlobDev &g, double &m, double &h, double &n) {
-    const double e80 = exp((v + 65.0) * (-1.0 / 80.0));
+    const double e80 = exp_d((v + 65.0) * (-1.0 / 80.0));
     const double e80_2 = e80 * e80;
     double em1_m;
     const double am = linexp_d(0.1, 0.1, v + 40.0, 1.0, em1_m);
-    const double bm = 4.0 * exp((v + 65.0) * (-1.0 / 18.0));
+    const double bm = 4.0 * exp_d((v + 65.0) * (-1.0 / 18.0));
     const double ah = 0.07 * (e80_2 * e80_2);
     const double bh = fdiv(1.0, 1.0 + (em1_m + 1.0) * 1.6487212707001282);   // e^{1/2}
     const double an = linexp_d(0.01, 0.1, v + 55.0, 0.1);
@@ -138,11 +224,11 @@ __device__ __forceinline__ void hh_state(double vd, const GlobDev &g, float &m, 
 
 __device__ __forceinline__ void hh_inf(double v, double &m, double &h, double &n) {
     const double am = linexp_d(0.1, 0.1, v + 40.0, 1.0);
-    const double bm = 4.0 * exp(-(v + 65.0) / 18.0);
-    const double ah = 0.07 * exp(-(v + 65.0) / 20.0);
-    const double bh = 1.0 / (1.0 + exp(-(v + 35.0) / 10.0));
+    const double bm = 4.0 * exp_d(-(v + 65.0) / 18.0);
+    const double ah = 0.07 * exp_d(-(v + 65.0) / 20.0);
+    const double bh = 1.0 / (1.0 + exp_d(-(v + 35.0) / 10.0));
     const double an = linexp_d(0.01, 0.1, v + 55.0, 0.1);
-    const double bn = 0.125 * exp(-(v + 65.0) / 80.0);
+    const double bn = 0.125 * exp_d(-(v + 65.0) / 80.0);
     m = am / (am + bm);
     h = ah / (ah + bh);
     n = an / (an + bn);
@@ -150,7 +236,7 @@ __device__ __forceinline__ void hh_inf(double v, double &m, double &h, double &n
 
 // Ih: alpha = 0.005 exp(-(v+90)/20), beta = 0.005 exp((v+90)/20).
 __device__ __forceinline__ void ih_state(double v, const GlobDev &g, double &m) {
-    const double e = exp((v + 90.0) * 0.05);
+    const double e = exp_d((v + 90.0) * 0.05);
     const double a = fdiv(0.005, e), b = 0.005 * e, s = a + b;
     const double mi = fdiv(a, s);
     m = mi + (m - mi) * cnexp_factor(g.dt * s, g.pade);
@@ -161,7 +247,7 @@ __device__ __forceinline__ void ih_state(double vd, const GlobDev &g, float &m) 
     m += (a * frcp(s) - m) * one_minus_factor_f((float)g.dt * s, g.pade);
 }
 __device__ __forceinline__ double ih_inf(double v) {
-    const double a = 0.005 * exp(-(v + 90.0) / 20.0), b = 0.005 * exp((v + 90.0) / 20.0);
+    const double a = 0.005 * exp_d(-(v + 90.0) / 20.0), b = 0.005 * exp_d((v + 90.0) / 20.0);
     return a / (a + b);
 }
 
@@ -170,9 +256,9 @@ __device__ __forceinline__ double ih_inf(double v) {
 // exp(-(v+20)/10)).
 __device__ __forceinline__ void ca_gates(double v, const GlobDev &g, double &m, double &h) {
     const double am = linexp_d(0.1, 0.2, v + 20.0, 0.5);
-    const double bm = 0.8 * exp((v + 45.0) * (-1.0 / 15.0));
-    const double ah = 0.0005 * exp((v + 60.0) * (-0.04));
-    const double bh = fdiv(0.006, 1.0 + exp((v + 20.0) * (-0.1)));
+    const double bm = 0.8 * exp_d((v + 45.0) * (-1.0 / 15.0));
+    const double ah = 0.0005 * exp_d((v + 60.0) * (-0.04));
+    const double bh = fdiv(0.006, 1.0 + exp_d((v + 20.0) * (-0.1)));
     const double sm = am + bm, sh = ah + bh;
     const double mi = fdiv(am, sm), hi = fdiv(ah, sh);
     m = mi + (m - mi) * cnexp_factor(g.dt * sm, g.pade);
@@ -201,9 +287,9 @@ __device__ __forceinline__ void ca_pool(const GlobDev &g, float ica, float &cai)
 }
 __device__ __forceinline__ void ca_inf(double v, double &m, double &h) {
     const double am = linexp_d(0.1, 0.2, v + 20.0, 0.5);
-    const double bm = 0.8 * exp(-(v + 45.0) / 15.0);
-    const double ah = 0.0005 * exp(-(v + 60.0) / 25.0);
-    const double bh = 0.006 / (1.0 + exp(-(v + 20.0) / 10.0));
+    const double bm = 0.8 * exp_d(-(v + 45.0) / 15.0);
+    const double ah = 0.0005 * exp_d(-(v + 60.0) / 25.0);
+    const double bh = 0.006 / (1.0 + exp_d(-(v + 20.0) / 10.0));
     m = am / (am + bm);
     h = ah / (ah + bh);
 }
@@ -228,7 +314,7 @@ __device__ __forceinline__ void kmarkov_solve(T a, T b, T dt, T &c1, T &c2, T &o
 }
 __device__ __forceinline__ void kmarkov_state(double v, const GlobDev &g, double &c1, double &c2, double &o) {
     const double an = linexp_d(0.01, 0.1, v + 55.0, 0.1);
-    const double bn = 0.125 * exp((v + 65.0) * (-1.0 / 80.0));
+    const double bn = 0.125 * exp_d((v + 65.0) * (-1.0 / 80.0));
     kmarkov_solve<double>(g.q10 * an, g.q10 * bn, g.dt, c1, c2, o);
 }
 __device__ __forceinline__ void kmarkov_state(double vd, const GlobDev &g, float &c1, float &c2, float &o) {
@@ -356,7 +442,7 @@ __device__ __forceinline__ void lin_cur(double v, S gbar_x, double e, const Glob
 template <class S>
 __device__ __forceinline__ double ca_cur(double v, S m, S h, S cai, S gbar, const GlobDev &g, double &i0,
                                          double &gg) {
-    const double eca = g.nernst * log(g.cao / (double)cai);
+    const double eca = g.nernst * log_d(g.cao / (double)cai);
     const double gc = (double)(gbar * m * m * h);
     i0 = gc * (v - eca);
     if (g.analytic_g) {
@@ -374,7 +460,7 @@ template <class S>
 __device__ __forceinline__ void syn_cur(double v, const S *x, const GlobDev &g, double &i0, double &gg) {
     const double ga = (double)(x[1] - x[0]);
     const double gn = (double)(x[3] - x[2]);
-    const double ex = exp(-0.062 * v);
+    const double ex = exp_d(-0.062 * v);
     const double b0 = fdiv(1.0, 1.0 + ex * g.mg_357);
     i0 = 1e-3 * (ga + gn * b0) * (v - g.e_syn);
     if (g.analytic_g) {
@@ -1230,7 +1316,7 @@ __device__ __forceinline__ int tile_of(int b, int T, int xcd_order) {
 // the shared calcium ion (a run-time switch there).  They are kept apart so
 // that the default instantiations keep their register budget.
 template <class S, int PH, int VM, bool NT, bool EXT = false>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(sizeof(S) == 4 && VM != MECH_V_CLAMP ? 5 : 1))) void k_fused(FusedArgs a, int tn) {
+__global__ __launch_bounds__(1024) void k_fused(FusedArgs a, int tn) {
     extern __shared__ double lds[];
     unsigned long long *w = (unsigned long long *)lds;
     double *vl = lds, *sc = lds + tn;

@@ -12,6 +12,7 @@
 #include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
+#include <utility>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -1395,31 +1396,55 @@ static int autotune_impl(mech_ctx *c, double dt, int vmode, int nsteps, int reps
     }
     const int ion_on = c->gl.shared_ca && c->nd.cai;
     const size_t cap = device_lds_bytes();
-    for (const Shape &sh : cand) {
-        if (rc) break;
-        rc = mech_set_launch(c, sh.block, sh.budget, sh.nodes, sh.bpc, sh.flags);
-        if (rc) break;
-        if (resident && res_lds_need(c, vmode, ion_on) > cap) continue;
-        auto run = [&](int n, int64_t k0) {
-            return resident ? step_resident(c, n, k0, dt, vmode) : step_batched(c, n, k0, dt, vmode, false);
+    // median ms per step of one shape over `r` runs of `n` steps; +inf if its
+    // tiles do not fit the LDS of a workgroup
+    auto time_shape = [&](const Shape &sh, int n, int r, double &t) -> int {
+        t = 1e300;
+        int q = mech_set_launch(c, sh.block, sh.budget, sh.nodes, sh.bpc, sh.flags);
+        if (q) return q;
+        if (resident && res_lds_need(c, vmode, ion_on) > cap) return MECH_OK;
+        auto run = [&](int m, int64_t k0) {
+            return resident ? step_resident(c, m, k0, dt, vmode) : step_batched(c, m, k0, dt, vmode, false);
         };
-        rc = run(1, 0);  // warm-up
+        q = run(1, 0);  // warm-up
         std::vector<double> ts;
-        for (int r = 0; r < reps && rc == MECH_OK; ++r) {
+        for (int j = 0; j < r && q == MECH_OK; ++j) {
             (void)hipEventRecord(e0, c->stream);
-            rc = run(nsteps, 1);
+            q = run(n, 1);
             (void)hipEventRecord(e1, c->stream);
             (void)hipEventSynchronize(e1);
             float ms = 0;
             (void)hipEventElapsedTime(&ms, e0, e1);
-            ts.push_back(ms / nsteps);
+            ts.push_back(ms / n);
         }
-        if (rc) break;
+        if (q) return q;
         std::sort(ts.begin(), ts.end());
-        const double med = ts[ts.size() / 2];
-        if (med < best_t) {
-            best_t = med;
-            best[0] = sh.block; best[1] = sh.budget; best[2] = sh.nodes; best[3] = sh.bpc; best[4] = sh.flags;
+        t = ts[ts.size() / 2];
+        return MECH_OK;
+    };
+    // a first pass over every candidate, then the four fastest again with
+    // four times the steps and twice the repeats (short runs rank shapes
+    // within a few per cent of each other in noise)
+    std::vector<std::pair<double, Shape>> timed;
+    for (const Shape &sh : cand) {
+        double t;
+        rc = time_shape(sh, nsteps, reps, t);
+        if (rc) break;
+        if (t < 1e299) timed.push_back({t, sh});
+    }
+    if (rc == MECH_OK) {
+        std::sort(timed.begin(), timed.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
+        if (timed.size() > 4) timed.resize(4);
+        for (auto &ts : timed) {
+            if (timed.size() > 1) {
+                rc = time_shape(ts.second, 4 * nsteps, 2 * reps, ts.first);
+                if (rc) break;
+            }
+            if (ts.first < best_t) {
+                best_t = ts.first;
+                const Shape &sh = ts.second;
+                best[0] = sh.block; best[1] = sh.budget; best[2] = sh.nodes; best[3] = sh.bpc; best[4] = sh.flags;
+            }
         }
     }
     (void)hipEventDestroy(e0);
