@@ -161,6 +161,43 @@ __device__ __forceinline__ double log_d(double x) {
     return x == 0.0 ? -INFINITY : (x == INFINITY ? INFINITY : NAN);
 }
 
+// sin x for the clamp waveform: x = k pi/2 + r with k = rint(2x/pi) and r
+// formed by three fused multiply-adds against pi/2 split into three doubles
+// (accurate while |k| stays far below 2^50), |r| <= pi/4; sin r and cos r
+// by their Taylor series to r^19/19! and r^18/18!, and the quadrant k mod 4
+// picks +-sin r or +-cos r.  Written out for the same reason as exp_d (the
+// library sine holds a large reduction table and its registers).
+__device__ __forceinline__ double sin_d(double x) {
+    const double k = rint(x * 0x1.45f306dc9c883p-1);   // 2/pi
+    double r = fma(-k, 0x1.921fb54442d18p+0, x);
+    r = fma(-k, 0x1.1a62633145c07p-54, r);
+    r = fma(-k, -0x1.f1976b7ed8fbcp-110, r);
+    const double z = r * r;
+    double ps = -1.0 / 121645100408832000.0;   // -1/19!, then 1/17! ... 1/5!
+    ps = fma_s(ps, z, 1.0 / 355687428096000.0);
+    ps = fma_s(ps, z, -1.0 / 1307674368000.0);
+    ps = fma_s(ps, z, 1.0 / 6227020800.0);
+    ps = fma_s(ps, z, -1.0 / 39916800.0);
+    ps = fma_s(ps, z, 1.0 / 362880.0);
+    ps = fma_s(ps, z, -1.0 / 5040.0);
+    ps = fma_s(ps, z, 1.0 / 120.0);
+    ps = fma(ps, z, -1.0 / 6.0);
+    const double sr = fma(r * z, ps, r);
+    double pc = 1.0 / 6402373705728000.0;   // 1/18!, then -1/16! ... -1/4!
+    pc = fma_s(pc, z, -1.0 / 20922789888000.0);
+    pc = fma_s(pc, z, 1.0 / 87178291200.0);
+    pc = fma_s(pc, z, -1.0 / 479001600.0);
+    pc = fma_s(pc, z, 1.0 / 3628800.0);
+    pc = fma_s(pc, z, -1.0 / 40320.0);
+    pc = fma_s(pc, z, 1.0 / 720.0);
+    pc = fma_s(pc, z, -1.0 / 24.0);
+    pc = fma(pc, z, 0.5);   // now 1/2 - z/24 + ...
+    const double cr = fma(-z, pc, 1.0);
+    const double q = k - 4.0 * floor(k * 0.25);   // k mod 4, exact
+    const double y = (q == 0.0 || q == 2.0) ? sr : cr;
+    return (q >= 2.0) ? -y : y;
+}
+
 // a x/(1 - exp(-x/k)), with the limit a k at x = 0; em1 = expm1(-x/k) is
 // returned so that a caller can reuse exp(-x/k) = em1 + 1.
 __device__ __forceinline__ double linexp_d(double a, double inv_k, double x, double lim, double &em1) {
@@ -861,7 +898,7 @@ __global__ void k_bump_k(long long *kdev, long long by) {
 }
 
 __device__ __forceinline__ double clamp_v(const NodesDev &nd, int n, double t) {
-    return nd.c_off[n] + nd.c_amp[n] * sin(2.0 * 3.14159265358979323846 * nd.c_freq[n] * t * 1e-3 + nd.c_phase[n]);
+    return nd.c_off[n] + nd.c_amp[n] * sin_d(2.0 * 3.14159265358979323846 * nd.c_freq[n] * t * 1e-3 + nd.c_phase[n]);
 }
 
 __global__ void k_vclamp(NodesDev nd, double t) {
@@ -1608,7 +1645,7 @@ __global__ __launch_bounds__(1024) void k_resident(FusedArgs a, ResArgs r) {
                     if (v0 < a.g.vthresh && v1 >= a.g.vthresh) spk[j] += 1;
                 } else {
                     const double t1 = (double)(k + 1) * a.g.dt;
-                    v1 = md[4 * j] + md[4 * j + 1] * sin(2.0 * 3.14159265358979323846 * md[4 * j + 2] * t1 * 1e-3 +
+                    v1 = md[4 * j] + md[4 * j + 1] * sin_d(2.0 * 3.14159265358979323846 * md[4 * j + 2] * t1 * 1e-3 +
                                                          md[4 * j + 3]);
                 }
                 vl[j] = v1;
