@@ -64,16 +64,27 @@ def alg_bytes_per_step(w, prec: str) -> int:
     return tot
 
 
+KERNEL_SOURCES = ("mech_kernels.hip", "mech_math.h", "mech_internal.h")
+
+
+def kernel_source_sha256() -> str:
+    """SHA-256 of the kernel sources, concatenated in KERNEL_SOURCES order:
+    the key under which profile summaries record what they measured."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1905_02241_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(w, prec: str):
     """HBM bytes per launch of the fused kernel from the committed rocprofv3
     summary (FETCH_SIZE and WRITE_SIZE, calibrated on the copy probe), or None
     when the summary is missing or was taken on a different kernel source."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", f"k_fused_{w.name}_hbm_traffic.txt")
-    src = os.path.join(ROOT, "paper_1905_02241_amd", "csrc", "mech_kernels.hip")
     if not os.path.exists(path):
         return None
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    sha = kernel_source_sha256()
     vals = {}
     for line in open(path):
         if ":" in line and not line.startswith("#"):

@@ -19,7 +19,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmech.so")
 SOURCES = [os.path.join(CSRC, f) for f in ("mech_kernels.hip", "mech_runtime.hip")]
-HEADERS = [os.path.join(CSRC, "mech_internal.h"), os.path.join(ROOT, "include", "mech.h")]
+HEADERS = [os.path.join(CSRC, "mech_internal.h"), os.path.join(CSRC, "mech_math.h"), os.path.join(ROOT, "include", "mech.h")]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
