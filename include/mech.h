@@ -203,9 +203,9 @@ int mech_cable_required_bytes(int64_t n_nodes, const int32_t *parent, int32_t un
  * order) and every cell a contiguous node range that starts at its root
  * (MECH_ERR_INVAL otherwise).  g_axial (device, double[n_nodes], caller
  * owned): the axial conductance in uS between node n and its parent.
- * unit_nodes bounds the nodes one workgroup solves together in LDS (36 B
+ * unit_nodes bounds the nodes one workgroup solves together in LDS (44 B
  * per node): 0 takes the library's default of 1024, a value above the
- * device's LDS capacity (4323 nodes on gfx950) is reduced to it, a
+ * device's LDS capacity (3537 nodes on gfx950) is reduced to it, a
  * negative one is MECH_ERR_INVAL.  Any bound gives the same elimination up
  * to rounding; it only changes how cells are cut.  A cell larger than the bound is cut into subtrees that
  * fit and a trunk, which is solved in global memory if it is still too

@@ -83,9 +83,16 @@ struct NodesDev {
 // ghost rows.  Rows of the solve live at positions: every node has one, and
 // every piece root has a second one as a ghost in its trunk's unit.
 enum { kUnitFull = 0, kUnitPiece = 1, kUnitTop = 2 };
-// LDS of a unit solved there, per position: D and R (16 B) and one edge
-// record (two packed 16-bit rows, two couplings: 20 B).
-constexpr int kCableLdsBytesPerNode = 36;
+// LDS of a unit solved there, per position: D, R and the voltage difference
+// to the parent (24 B) and one edge record (two packed 16-bit rows, two
+// couplings: 20 B).
+constexpr int kCableLdsBytesPerNode = 44;
+// A unit solved in LDS packs each record as child row (12 bits), parent row
+// (12 bits) and run length (8 bits): at most 4095 rows, runs of up to
+// kCableRunMax children of one parent at one height per head (a longer run
+// is followed by comparing parents).
+constexpr int kCableLdsUnitMax = 4095;
+constexpr int kCableRunMax = 255;
 
 struct CableDev {
     const double *g_axial;     // uS to the parent
@@ -94,6 +101,7 @@ struct CableDev {
     const int *pos_pnode;      // [n_pos] that node's parent node, or -1
     const int *pos_par;        // [n_pos] position of the parent's row in the same unit, or -1
     const int *pos_src;        // [n_pos] ghost: the piece root's own position; -1 otherwise
+    const int *elim_run;       // per record: run length at the head of a parent's run of a height, else 0
     const int *elim_n;         // edge records: child position, per unit by the child's height
     const int *elim_p;         // parent position
     const int *elim_ptr;       // height boundaries into elim_n / elim_p
@@ -107,8 +115,9 @@ struct CableDev {
     int n_up, n_top, n_top_g, n_down;
     int lds_max_nodes;         // largest unit solved in LDS
     double *ekn, *ekp;         // per edge record: 100 g/area_n, 100 g/area_p
-    double *kn, *kp;           // per node: 100 g/area_n, 100 g/area_parent (0 at a root)
+    double *kn;                // per node: 100 g/area_n (0 at a root)
     double *D, *R;             // per position: rows handed between passes, global-scratch units
+    double *DV;                // per position: v_parent - v_node of this step (global-scratch units)
 };
 
 struct FusedArgs {

@@ -805,17 +805,22 @@ __global__ void k_visolated(NodesDev nd, GlobDev g) {
 // n of the system: D_n dv_n - k_{n,p} dv_p - sum_c k_{n,c} dv_c = R_n with
 // D_n = 1e-3 cm/dt + d_n + k_{n,p} + sum_c k_{n,c}, k_{n,j} = 100 g/area_n.
 //
-// Elimination runs by height from the leaves (a node's height is one more
-// than its highest child's): every edge child -> parent of a height folds
-// the finished child row into its parent, D_p -= k_{p,n} k_{n,p}/D_n and
-// R_p += k_{p,n} R_n/D_n, by atomic adds (several children may share a
-// parent).  Back-substitution walks the same heights downwards from the
-// root: dv_n = (R_n + k_{n,p} dv_p)/D_n.  Each height is one barrier.  The
-// coupling coefficients are precomputed per node and per record at
-// mech_bind_cable, and a unit's records are staged in LDS once, so a height
-// waits on LDS alone.
+// Each position first writes its own row without the terms of its children:
+// D_n = 1e-3 cm/dt + d_n + k_{n,p}, R_n = rhs_n + k_{n,p} (v_p - v_n).
+// Elimination then runs by height from the leaves (a node's height is one
+// more than its highest child's): every edge child -> parent of a height
+// folds the finished child row into its parent together with the child's
+// coupling terms, D_p += k_{p,n} - k_{p,n} k_{n,p}/D_n and R_p += k_{p,n}
+// R_n/D_n - k_{p,n} (v_p - v_n).  A height's records are sorted by parent,
+// and the thread at the head of each parent's run folds the run in order
+// and adds the total to the parent once, so no row is written by two
+// threads in a phase and the result does not depend on scheduling.  Back-substitution walks the same
+// heights downwards from the root: dv_n = (R_n + k_{n,p} dv_p)/D_n.  Each
+// height is one barrier.  The coupling coefficients are precomputed per
+// record at mech_bind_cable, and a unit's records are staged in LDS once, so
+// a height waits on LDS alone.
 //
-// A workgroup solves one unit with its rows and edge records in LDS (36 B
+// A workgroup solves one unit with its rows and edge records in LDS (44 B
 // per position); a FULL unit holds one or more whole cells.  A cell too large for LDS is cut: every maximal subtree that fits becomes a
 // piece (small pieces share a unit as a forest), and the rest, the trunk,
 // one TOP unit.  Pieces eliminate up to their roots and hand the rows over
@@ -834,6 +839,8 @@ template <bool LDS> __device__ __forceinline__ void stc(double *p, double v) {
     if constexpr (LDS) *p = v;
     else __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// A single addition to a row that no other thread touches in this phase:
+// issued as an atomic so that the thread need not wait for the row's value.
 template <bool LDS> __device__ __forceinline__ void addc(double *p, double v) {
     if constexpr (LDS) atomicAdd(p, v);
     else __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -868,13 +875,15 @@ __global__ __launch_bounds__(512) void k_cable(CableDev c, NodesDev nd, GlobDev 
     const int e0 = c.elim_ptr[L0], ne = c.elim_ptr[L1] - e0;
     // Rows: in LDS at position - p0, in global memory at the position.
     // Records (index q - e0): in LDS the unit's records, staged once, with
-    // both row indices packed into one int (a unit in LDS has < 2^16 rows).
+    // both row indices and the run length packed into one int (a unit in
+    // LDS has at most kCableLdsUnitMax rows).
     const int base = LDS ? p0 : 0;
     double *D = LDS ? lds : c.D;
     double *R = LDS ? lds + np : c.R;
-    double *ekn = LDS ? lds + 2 * np : c.ekn + e0;
-    double *ekp = LDS ? lds + 2 * np + ne : c.ekp + e0;
-    int *rec = (int *)(lds + 2 * np + 2 * ne);
+    double *DV = LDS ? lds + 2 * np : c.DV;
+    double *ekn = LDS ? lds + 3 * np : c.ekn + e0;
+    double *ekp = LDS ? lds + 3 * np + ne : c.ekp + e0;
+    int *rec = (int *)(lds + 3 * np + 2 * ne);
     const bool lv_lds = nlev < kCableLevelsLds;
     if (lv_lds)
         for (int j = tid; j <= nlev; j += B) lvl[j] = c.elim_ptr[L0 + j] - e0;
@@ -884,7 +893,7 @@ __global__ __launch_bounds__(512) void k_cable(CableDev c, NodesDev nd, GlobDev 
     // waits about n / (kBatch B) memory latencies instead of n / B.
     if constexpr (LDS)
         for (int q0 = tid; q0 < ne; q0 += kBatch * B) {
-            int a[kBatch], b[kBatch];
+            int a[kBatch], b[kBatch], l[kBatch];
             double x[kBatch], y[kBatch];
 #pragma unroll
             for (int k = 0; k < kBatch; ++k) {
@@ -892,6 +901,7 @@ __global__ __launch_bounds__(512) void k_cable(CableDev c, NodesDev nd, GlobDev 
                 if (q < ne) {
                     a[k] = c.elim_n[e0 + q];
                     b[k] = c.elim_p[e0 + q];
+                    l[k] = c.elim_run[e0 + q];
                     x[k] = c.ekn[e0 + q];
                     y[k] = c.ekp[e0 + q];
                 }
@@ -900,7 +910,7 @@ __global__ __launch_bounds__(512) void k_cable(CableDev c, NodesDev nd, GlobDev 
             for (int k = 0; k < kBatch; ++k) {
                 const int q = q0 + k * B;
                 if (q < ne) {
-                    rec[q] = (a[k] - p0) | ((b[k] - p0) << 16);
+                    rec[q] = (a[k] - p0) | ((b[k] - p0) << 12) | (l[k] << 24);
                     ekn[q] = x[k];
                     ekp[q] = y[k];
                 }
@@ -909,42 +919,40 @@ __global__ __launch_bounds__(512) void k_cable(CableDev c, NodesDev nd, GlobDev 
     auto rows = [&](int q, int &rn, int &rp) {
         if constexpr (LDS) {
             const unsigned r = (unsigned)rec[q];
-            rn = (int)(r & 0xffffu);
-            rp = (int)(r >> 16);
+            rn = (int)(r & 0xfffu);
+            rp = (int)((r >> 12) & 0xfffu);
         } else {
             rn = c.elim_n[e0 + q];
             rp = c.elim_p[e0 + q];
         }
     };
+    auto run_of = [&](int q) {
+        if constexpr (LDS) return (int)((unsigned)rec[q] >> 24);
+        else return c.elim_run[e0 + q];
+    };
 
     if (!down) {
-        // rows: every position adds its own terms and its parent's (ghosts
-        // bring the piece root's eliminated row instead of their own terms)
-        for (int i = p0 + tid; i < p1; i += B) {
-            stc<LDS>(D + (i - base), 0.0);
-            stc<LDS>(R + (i - base), 0.0);
-        }
-        __syncthreads();
+        // rows: every position writes its own terms (ghosts bring the piece
+        // root's eliminated row instead) and its voltage difference to the
+        // parent, which its parent's fold needs
         for (int i0 = p0 + tid; i0 < p1; i0 += kBatch * B) {
-            int n[kBatch], p[kBatch], lp[kBatch], src[kBatch];
+            int n[kBatch], p[kBatch], src[kBatch];
 #pragma unroll
             for (int k = 0; k < kBatch; ++k) {
                 const int i = i0 + k * B;
                 if (i < p1) {
                     n[k] = c.pos_node[i];
                     p[k] = c.pos_pnode[i];
-                    lp[k] = c.pos_par[i];
                     src[k] = c.pos_src[i];
                 }
             }
-            double vn[kBatch], vp[kBatch], a[kBatch], b[kBatch], e[kBatch], f[kBatch], kp[kBatch];
+            double vn[kBatch], vp[kBatch], a[kBatch], b[kBatch], e[kBatch], f[kBatch];
 #pragma unroll
             for (int k = 0; k < kBatch; ++k) {
                 const int i = i0 + k * B;
                 if (i < p1) {
                     vn[k] = nd.v[n[k]];
                     vp[k] = p[k] >= 0 ? nd.v[p[k]] : vn[k];
-                    kp[k] = lp[k] >= 0 ? c.kp[n[k]] : 0.0;
                     if (src[k] >= 0) {
                         a[k] = c.D[src[k]];
                         b[k] = c.R[src[k]];
@@ -966,12 +974,9 @@ __global__ __launch_bounds__(512) void k_cable(CableDev c, NodesDev nd, GlobDev 
                         Dn = 1e-3 * a[k] / g.dt + e[k] + f[k];
                         Rn = b[k] + f[k] * dv;
                     }
-                    if (lp[k] >= 0) {
-                        addc<LDS>(D + (lp[k] - base), kp[k]);
-                        addc<LDS>(R + (lp[k] - base), -kp[k] * dv);
-                    }
-                    addc<LDS>(D + (i - base), Dn);
-                    addc<LDS>(R + (i - base), Rn);
+                    stc<LDS>(D + (i - base), Dn);
+                    stc<LDS>(R + (i - base), Rn);
+                    stc<LDS>(DV + (i - base), dv);
                 }
             }
         }
@@ -982,16 +987,35 @@ __global__ __launch_bounds__(512) void k_cable(CableDev c, NodesDev nd, GlobDev 
         // couplings 0), which serve the back-substitution alone.
         const int nel = mode == kUnitPiece ? nlev : nlev - 1;
         for (int j = 0; j < nel; ++j) {
-            const int qend = lv(j + 1);
-            for (int q = lv(j) + tid; q < qend; q += B) {
+            const int qlo = lv(j), qend = lv(j + 1);
+            for (int q = qlo + tid; q < qend; q += B) {
                 int rn, rp;
                 rows(q, rn, rp);
-                // both loads ahead of the writes, which the compiler cannot
-                // place apart from the child's row
-                const double Dn = ldc<LDS>(D + rn), Rn = ldc<LDS>(R + rn);
-                const double f = ekp[q] / Dn;
-                addc<LDS>(D + rp, -f * ekn[q]);
-                addc<LDS>(R + rp, f * Rn);
+                const int run = run_of(q);
+                // the first child's row is read before the run is looked at,
+                // so a run of one (nearly all) costs no more than a scatter
+                const double Dn = ldc<LDS>(D + rn), Rn = ldc<LDS>(R + rn), dvn = ldc<LDS>(DV + rn);
+                const double kp = ekp[q], kn0 = ekn[q];
+                if (run == 0) continue;   // folded by the head of its parent's run
+                const double f = fdiv(kp, Dn);
+                double aD = kp - f * kn0, aR = f * Rn - kp * dvn;
+                if (run != 1) {
+                    // further children of the parent at this height, in order; a
+                    // run of kCableRunMax goes on while the parent matches
+                    const int end = run < kCableRunMax ? q + run : qend;
+                    for (int r = q + 1; r < end; ++r) {
+                        int cn, cp;
+                        rows(r, cn, cp);
+                        if (cp != rp) break;
+                        const double Dc = ldc<LDS>(D + cn), Rc = ldc<LDS>(R + cn), dvc = ldc<LDS>(DV + cn);
+                        const double kq = ekp[r], h = fdiv(kq, Dc);
+                        aD += kq - h * ekn[r];
+                        aR += h * Rc - kq * dvc;
+                    }
+                }
+                // the parent's only addition of this height
+                addc<LDS>(D + rp, aD);
+                addc<LDS>(R + rp, aR);
             }
             level_barrier<LDS>();
         }
@@ -1041,7 +1065,7 @@ __global__ __launch_bounds__(512) void k_cable(CableDev c, NodesDev nd, GlobDev 
             int rn, rp;
             rows(q, rn, rp);
             const double r = ldc<LDS>(R + rn) + ekn[q] * ldc<LDS>(R + rp);
-            stc<LDS>(R + rn, r / ldc<LDS>(D + rn));
+            stc<LDS>(R + rn, fdiv(r, ldc<LDS>(D + rn)));
         }
         level_barrier<LDS>();
     }
@@ -1087,15 +1111,13 @@ hipError_t launch_cable(const CableDev &c, const NodesDev &nd, const GlobDev &g,
 }
 
 // Coupling coefficients of the tree from the bound area and g_axial: per node
-// (towards its parent, and the parent's towards it) and per edge record (0
-// for a root's own record).
+// (towards its parent) and per edge record (the node's towards its parent and
+// the parent's towards it; 0 for a root's own record).
 __global__ void k_cable_coeffs(CableDev c, const double *area, int n_nodes, int n_edges) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n_nodes) {
         const int p = c.parent[i];
-        const double ga = c.g_axial[i];
-        c.kn[i] = p >= 0 ? 1e2 * ga / area[i] : 0.0;
-        c.kp[i] = p >= 0 ? 1e2 * ga / area[p] : 0.0;
+        c.kn[i] = p >= 0 ? 1e2 * c.g_axial[i] / area[i] : 0.0;
     }
     if (i < n_edges) {
         const int n = c.pos_node[c.elim_n[i]], p = c.parent[n];

@@ -93,7 +93,7 @@ struct SlotHost {
 // mech_bind_cable (the unit kinds and positions are described with CableDev).
 struct CableHost {
     std::vector<int32_t> parent, pos_node, pos_par, pos_src, elim_n, elim_p, elim_ptr, unit_pos, unit_elim,
-        unit_mode, list_up, list_top, list_top_g, list_down, pos_pnode;
+        unit_mode, list_up, list_top, list_top_g, list_down, pos_pnode, elim_run;
     int lds_max = 0;
 };
 
@@ -132,12 +132,24 @@ std::string build_cable(int64_t N, const int32_t *parent, int cap, CableHost &h)
         h.unit_mode.push_back(mode);
         h.unit_pos.push_back((int32_t)h.pos_node.size());
         h.unit_elim.push_back((int32_t)h.elim_ptr.size() - 1);
-        std::stable_sort(recs.begin(), recs.end(), [](const Rec &x, const Rec &y) { return x.h < y.h; });
+        // by height, and within a height by parent, so that a parent's
+        // children of one height form a run that one thread folds in order
+        std::stable_sort(recs.begin(), recs.end(),
+                         [](const Rec &x, const Rec &y) { return x.h != y.h ? x.h < y.h : x.p < y.p; });
         size_t k = 0;
         for (int L = 0; L < nlev; ++L) {
             for (; k < recs.size() && recs[k].h == L; ++k) {
                 h.elim_n.push_back(recs[k].n);
                 h.elim_p.push_back(recs[k].p);
+                // the head of a parent's run of this height carries the run's
+                // length (at most kCableRunMax, longer runs are followed by
+                // parent); the others 0
+                int run = 0;
+                if (k == 0 || recs[k - 1].h != L || recs[k - 1].p != recs[k].p)
+                    while (k + run < recs.size() && recs[k + run].h == L && recs[k + run].p == recs[k].p &&
+                           run < kCableRunMax)
+                        ++run;
+                h.elim_run.push_back(run);
             }
             h.elim_ptr.push_back((int32_t)h.elim_n.size());
         }
@@ -261,13 +273,14 @@ std::string build_cable(int64_t N, const int32_t *parent, int cap, CableHost &h)
 }
 
 // Device layout of a CableHost (256-byte aligned arrays), then the double
-// arrays: ekn, ekp (per edge record), D, R (per position), kn, kp (per node).
-constexpr int kCableIntArrays = 15;
+// arrays: ekn, ekp (per edge record), D, R (per position), kn (per node), DV
+// (per position).
+constexpr int kCableIntArrays = 16;
 size_t cable_layout(const CableHost &h, int64_t N, size_t *offs) {
     const std::vector<int32_t> *arr[kCableIntArrays] = {
         &h.parent, &h.pos_node, &h.pos_par, &h.pos_src, &h.elim_n, &h.elim_p, &h.elim_ptr,
         &h.unit_pos, &h.unit_elim, &h.unit_mode, &h.list_up, &h.list_top, &h.list_top_g, &h.list_down,
-        &h.pos_pnode};
+        &h.pos_pnode, &h.elim_run};
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -281,12 +294,13 @@ size_t cable_layout(const CableHost &h, int64_t N, size_t *offs) {
     offs[kCableIntArrays + 2] = take(8 * P);    // D
     offs[kCableIntArrays + 3] = take(8 * P);    // R
     offs[kCableIntArrays + 4] = take(8 * NN);   // kn
-    offs[kCableIntArrays + 5] = take(8 * NN);   // kp
+    offs[kCableIntArrays + 5] = take(8 * P);    // DV
     return off;
 }
 
 // Positions of a unit whose rows and records fit the LDS a workgroup may
-// take on the current device (packed record rows need fewer than 2^16).
+// take on the current device (at most kCableLdsUnitMax, for the packed
+// records).
 int cable_lds_nodes() {
     int dev = 0, bytes = 65536;
     if (hipGetDevice(&dev) == hipSuccess) {
@@ -294,8 +308,9 @@ int cable_lds_nodes() {
         if (hipDeviceGetAttribute(&b, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && b > 0)
             bytes = b;
     }
-    // the level-boundary table of k_cable takes 4 KiB of static LDS
-    return std::min(65535, std::max(0, (bytes - 8192) / kCableLdsBytesPerNode));
+    // the level-boundary table of k_cable takes 4 KiB of static LDS; a unit's
+    // packed records hold 12-bit rows
+    return std::min(kCableLdsUnitMax, std::max(0, (bytes - 8192) / kCableLdsBytesPerNode));
 }
 
 struct Layout {
@@ -1124,7 +1139,7 @@ int mech_bind_cable(mech_ctx *c, const int32_t *parent, const double *g_axial, i
     const std::vector<int32_t> *arr[kCableIntArrays] = {
         &h.parent, &h.pos_node, &h.pos_par, &h.pos_src, &h.elim_n, &h.elim_p, &h.elim_ptr,
         &h.unit_pos, &h.unit_elim, &h.unit_mode, &h.list_up, &h.list_top, &h.list_top_g, &h.list_down,
-        &h.pos_pnode};
+        &h.pos_pnode, &h.elim_run};
     for (int j = 0; j < kCableIntArrays; ++j)
         if (!arr[j]->empty())
             HIPCHK(c, hipMemcpy(b + offs[j], arr[j]->data(), 4 * arr[j]->size(), hipMemcpyHostToDevice));
@@ -1147,6 +1162,7 @@ int mech_bind_cable(mech_ctx *c, const int32_t *parent, const double *g_axial, i
     d.list_top_g = I[12];
     d.list_down = I[13];
     d.pos_pnode = I[14];
+    d.elim_run = I[15];
     d.n_up = (int)h.list_up.size();
     d.n_top = (int)h.list_top.size();
     d.n_top_g = (int)h.list_top_g.size();
@@ -1157,7 +1173,7 @@ int mech_bind_cable(mech_ctx *c, const int32_t *parent, const double *g_axial, i
     d.D = (double *)(b + offs[kCableIntArrays + 2]);
     d.R = (double *)(b + offs[kCableIntArrays + 3]);
     d.kn = (double *)(b + offs[kCableIntArrays + 4]);
-    d.kp = (double *)(b + offs[kCableIntArrays + 5]);
+    d.DV = (double *)(b + offs[kCableIntArrays + 5]);
     if (c->n_nodes > 0) {
         if (!c->nd.area) return fail(c, MECH_ERR_STATE, "bind area (mech_bind_nodes) before mech_bind_cable");
         HIPCHK(c, launch_cable_coeffs(d, c->nd.area, (int)c->n_nodes, (int)h.elim_n.size(), c->stream));

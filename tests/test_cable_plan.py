@@ -102,21 +102,22 @@ def replay(plan, v, rhs, d, cm, area, g, dt):
             ghost = ps[idx] >= 0
             Dn = np.where(ghost, GD[np.maximum(ps[idx], 0)], 1e-3 * cm[n] / dt + d[n] + kn[n])
             Rn = np.where(ghost, GR[np.maximum(ps[idx], 0)], rhs[n] + kn[n] * dv)
-            lp = plan["pos_par"][idx]
-            m = lp >= 0
-            np.add.at(D, lp[m], kp[n[m]])
-            np.add.at(R, lp[m], -kp[n[m]] * dv[m])
-            np.add.at(D, idx, Dn)
-            np.add.at(R, idx, Rn)
+            # every position writes its own row; a child's coupling terms go
+            # to its parent with its fold
+            D[idx], R[idx] = Dn, Rn
+            DV = np.zeros(P)
+            DV[idx] = dv
             nel = nlev if um[u] == PIECE else nlev - 1
             for j in range(nel):
                 q = np.arange(eptr[L0 + j], eptr[L0 + j + 1])
                 rn, rp = en[q], ep[q]
                 assert np.all(rn != rp)
+                # a height's records sorted by parent: one thread folds each run
+                assert np.all(np.diff(rp) >= 0)
                 Dc, Rc = D[rn].copy(), R[rn].copy()
                 f = ekp[q] / Dc
-                np.add.at(D, rp, -f * ekn[q])
-                np.add.at(R, rp, f * Rc)
+                np.add.at(D, rp, ekp[q] - f * ekn[q])
+                np.add.at(R, rp, f * Rc - ekp[q] * DV[rn])
             if um[u] != TOP:
                 # whole cells and pieces back-substitute in the second pass
                 GD[idx], GR[idx] = D[idx], R[idx]

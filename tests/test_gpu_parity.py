@@ -1009,6 +1009,23 @@ def test_cable_long_chain_trunk_fp64():
     compare_nodes(got, M, "fp64", label="cable chain")
 
 
+@pytest.mark.parametrize("unit_nodes", [0, 7])
+def test_cable_bit_identical_across_runs_and_shapes(unit_nodes):
+    """Every row of the tree solve is written by one thread (a parent's
+    children of one height are folded in order by the head of their run)
+    and the fused current update sums in fixed point, so in cable mode a
+    repeated run and another fused launch shape give the same bits of v,
+    rhs, d, STATEs and spike counts: whole cells (unit_nodes 0) and cells
+    cut into pieces and trunks, some solved in global memory (7)."""
+    w = W.make_cells(51, n_cells=6, lo=40, hi=400, kinds=("pas", "hh", "cahva", "syn"), nsteps=400)
+    base, _ = run_gpu(w, 400, "batched", "fp64", unit_nodes=unit_nodes)
+    assert base["spikes"].sum() > 0
+    again, _ = run_gpu(w, 400, "batched", "fp64", unit_nodes=unit_nodes)
+    _assert_same_bits(again, base, f"cable unit {unit_nodes} repeat")
+    other, _ = run_gpu(w, 400, "batched", "fp64", unit_nodes=unit_nodes, launch=(64, 64, 64, 0, 0))
+    _assert_same_bits(other, base, f"cable unit {unit_nodes} shape")
+
+
 @pytest.mark.parametrize("path", PATHS)
 def test_cable_cells_fp32_reports(path):
     w = W.make_cells(52, n_cells=6, lo=40, hi=400, kinds=("pas", "hh", "syn"), nsteps=400)
