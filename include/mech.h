@@ -315,15 +315,16 @@ int mech_set_resident_steps(mech_ctx *ctx, int steps_per_launch);
 
 /* Time every candidate launch shape of the BATCHED path on `nsteps` steps
  * (HIP events, median of `reps`), time the four fastest again on 4 nsteps
- * steps (median of 2 reps), keep the fastest, and return its ms per step.  STATEs, v, rhs, d, spike counts and the per-node calcium ion are
+ * steps (median of 2 reps), then tile sizes from 10/16 to 20/16 of the
+ * fastest one's, keep the fastest, and return its ms per step.  STATEs, v, rhs, d, spike counts and the per-node calcium ion are
  * saved before and restored after, so the call has no visible effect
  * besides the chosen shape.                                                */
 int mech_autotune(mech_ctx *ctx, double dt, int vmode, int nsteps, int reps, double *best_ms_per_step);
 
-/* The same for the RESIDENT path: launch shapes whose tiles fit the LDS of a
- * workgroup, each timed over `nsteps` steps (at most the steps per launch
- * set by mech_set_resident_steps per launch).  CLAMP and ISOLATED modes
- * only.                                                                    */
+/* The same for the RESIDENT path (with the same second round and tile
+ * refinement): launch shapes whose tiles fit the LDS of a workgroup, each
+ * timed over `nsteps` steps (at most the steps per launch set by
+ * mech_set_resident_steps per launch).  CLAMP and ISOLATED modes only.    */
 int mech_autotune_resident(mech_ctx *ctx, double dt, int vmode, int nsteps, int reps, double *best_ms_per_step);
 
 /* Copy STATE `name` (or "ica" for Ca-HVA, capump and cabuf) of type slot `type_slot` to /

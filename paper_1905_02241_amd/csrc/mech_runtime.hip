@@ -1463,6 +1463,26 @@ static int autotune_impl(mech_ctx *c, double dt, int vmode, int nsteps, int reps
             }
         }
     }
+    // finer tile sizes around the fastest shape (10/16 to 20/16 of its
+    // budget and node span, multiples of 64): the LDS a tile takes sets how
+    // many workgroups share a CU, and the coarse grid's powers of two can
+    // miss the size where one more fits
+    if (rc == MECH_OK && best_t < 1e299) {
+        const Shape b0{best[0], best[1], best[2], best[3], best[4]};
+        for (int num : {10, 11, 12, 13, 14, 15, 17, 18, 20}) {
+            Shape sh = b0;
+            sh.budget = std::max(std::max(b0.block, kMinTileBudget), (b0.budget * num / 16 + 63) / 64 * 64);
+            sh.nodes = std::min(kMaxTileNodes, std::max(kMinTileNodes, (b0.nodes * num / 16 + 63) / 64 * 64));
+            double t;
+            rc = time_shape(sh, 4 * nsteps, 2 * reps, t);
+            if (rc) break;
+            if (t < best_t) {
+                best_t = t;
+                best[1] = sh.budget;
+                best[2] = sh.nodes;
+            }
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     int rc2 = mech_set_launch(c, best[0], best[1], best[2], best[3], best[4]);
