@@ -84,7 +84,7 @@ struct NodesDev {
 // every piece root has a second one as a ghost in its trunk's unit.
 enum { kUnitFull = 0, kUnitPiece = 1, kUnitTop = 2 };
 // LDS of a unit solved there, per position: D, R and the voltage difference
-// to the parent (24 B) and one edge record (two packed 16-bit rows, two
+// to the parent (24 B) and one edge record (packed rows and run length, two
 // couplings: 20 B).
 constexpr int kCableLdsBytesPerNode = 44;
 // A unit solved in LDS packs each record as child row (12 bits), parent row
